@@ -1,0 +1,187 @@
+/*
+ * slrng — bulk generation from the scrambled linear pseudorandom number
+ * generators of D. Blackman and S. Vigna, "Scrambled Linear Pseudorandom
+ * Number Generators" (ACM TOMS), on AMD Instinct MI355X (gfx950).
+ *
+ * C ABI.  No C++ exceptions cross it.  Every function returns SLRNG_OK (0) on
+ * success or a negative SLRNG_E* code; slrng_strerror() names the code and
+ * slrng_last_hip_error() returns the HIP error behind SLRNG_EHIP (per thread).
+ *
+ * Conventions
+ *  - A generator is a linear engine (Section "Linear engines": xoroshiro128,
+ *    xoshiro256, xoshiro512, xoroshiro1024) combined with a scrambler
+ *    (Section "Scramblers": +, ++, *, **), with the parameters of tables
+ *    tab:par64 and tab:scr64 and the state words named in the code figures
+ *    fig:xoroshiro128, fig:xoroshiro1024, fig:xoshiro256 and fig:xoshiro512.
+ *  - A state is k 64-bit words (k = 2, 4, 8, 16) in logical order: the row
+ *    vector that the transition matrix (X_kw of equation eq:M, S_4w, S_8w)
+ *    multiplies from the right.  For xoroshiro128, xoshiro256 and xoshiro512
+ *    this is the array s[] of the figures; for xoroshiro1024 logical word j is
+ *    s[(p + 1 + j) & 15] of fig:xoroshiro1024.
+ *  - Output t of a stream is the scrambler applied to the state after t steps
+ *    (the figures compute the output before advancing the state).
+ *  - Doubles are the upper 53 bits: (x >> 11) * 2^-53, exactly (Section
+ *    "Choosing a generator").
+ *  - Seeding: the state is filled with consecutive outputs of SplitMix64
+ *    seeded with the 64-bit seed (Section "Choosing a generator").
+ *  - Jumps (Section "Combining linear engines and scramblers": every generator
+ *    has jump functions): SLRNG_JUMP advances by 2^(n/2) steps and
+ *    SLRNG_LONG_JUMP by 2^(3n/4) steps, n = 64k the state size in bits.
+ *  - Functions taking a hipStream_t are asynchronous and ordered on that
+ *    stream (0 = the null stream); the caller orders calls on one handle.
+ *  - Device buffers are caller-owned unless stated; handles own their state
+ *    memory.  Handles are not thread-safe.
+ */
+#ifndef SLRNG_H
+#define SLRNG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SLRNG_ABI_VERSION 1
+
+typedef enum slrng_variant {
+  SLRNG_XOROSHIRO128_PLUS = 0,       /* fig:xoroshiro128, s0 + s1 */
+  SLRNG_XOROSHIRO128_PLUSPLUS = 1,   /* rotl(s0 + s1, 17) + s0, engine 49/21/28 */
+  SLRNG_XOROSHIRO128_STARSTAR = 2,   /* rotl(s0 * 5, 7) * 9 */
+  SLRNG_XOSHIRO256_PLUS = 3,         /* fig:xoshiro256, s0 + s3 */
+  SLRNG_XOSHIRO256_PLUSPLUS = 4,     /* rotl(s0 + s3, 23) + s0 */
+  SLRNG_XOSHIRO256_STARSTAR = 5,     /* rotl(s1 * 5, 7) * 9 */
+  SLRNG_XOSHIRO512_PLUS = 6,         /* fig:xoshiro512, s0 + s2 */
+  SLRNG_XOSHIRO512_PLUSPLUS = 7,     /* rotl(s0 + s2, 17) + s2 */
+  SLRNG_XOSHIRO512_STARSTAR = 8,     /* rotl(s1 * 5, 7) * 9 */
+  SLRNG_XOROSHIRO1024_PLUS = 9,      /* fig:xoroshiro1024, s0 + s15 */
+  SLRNG_XOROSHIRO1024_PLUSPLUS = 10, /* rotl(s0 + s15, 23) + s15 */
+  SLRNG_XOROSHIRO1024_STARSTAR = 11, /* rotl(s0 * 5, 7) * 9 */
+  SLRNG_XOROSHIRO128_STAR = 12,      /* s0 * 0x9e3779b97f4a7c13 */
+  SLRNG_XOROSHIRO1024_STAR = 13,     /* s0 * 0x9e3779b97f4a7c13 */
+  SLRNG_NUM_VARIANTS = 14
+} slrng_variant;
+
+typedef enum slrng_kind {
+  SLRNG_U64 = 0, /* uint64 outputs */
+  SLRNG_F64 = 1  /* doubles in [0, 1) from the upper 53 bits */
+} slrng_kind;
+
+typedef enum slrng_jump_kind {
+  SLRNG_JUMP = 0,     /* 2^(n/2) steps */
+  SLRNG_LONG_JUMP = 1 /* 2^(3n/4) steps */
+} slrng_jump_kind;
+
+enum {
+  SLRNG_OK = 0,
+  SLRNG_EINVAL = -1,     /* bad argument (null pointer, unknown enum, ld < n) */
+  SLRNG_ERANGE = -2,     /* a size overflows 64 bits or exceeds a limit */
+  SLRNG_ENOMEM = -3,     /* device or host allocation failed */
+  SLRNG_EZEROSTATE = -4, /* an all-zero state (a fixed point of every engine) */
+  SLRNG_EAGAIN = -5,     /* resource temporarily unavailable (server budget) */
+  SLRNG_EHIP = -6,       /* a HIP call failed; see slrng_last_hip_error() */
+  SLRNG_ENOTIMPL = -7    /* not implemented */
+};
+
+typedef struct slrng_streams slrng_streams; /* opaque: S device-resident states */
+
+/* Library version (SLRNG_ABI_VERSION). */
+int slrng_version(void);
+
+/* Error name of a return code; never NULL. */
+const char *slrng_strerror(int err);
+
+/* HIP error code of the last SLRNG_EHIP returned on this thread. */
+int slrng_last_hip_error(void);
+
+/* Words of state k (2, 4, 8 or 16) of a variant, or SLRNG_EINVAL. */
+int slrng_state_words(int variant);
+
+/* ---------------------------------------------------------------- host-side
+ * polynomial tools (no GPU needed).  Polynomials over Z/2Z are arrays of
+ * little-endian 64-bit words: bit i of word i/64 is the coefficient of x^i.
+ *
+ * slrng_charpoly: the characteristic polynomial p(x) = det(M - xI) of the
+ * variant's engine (Section "Polynomials and full period"), degree n = 64k,
+ * written to out[0 .. n/64] (n/64 + 1 words).  The library derives it with
+ * Berlekamp-Massey on 2n values of one state bit.
+ *
+ * slrng_jump_poly: r(x) = x^J mod p(x) for J = sum_i J_words[i] 2^(64 i),
+ * i < nj, written to out[0 .. n/64) (n/64 words).  By Cayley-Hamilton,
+ * state * M^J = sum_i r_i (state * M^i): the jump of J steps. */
+int slrng_charpoly(int variant, uint64_t *out, int out_words);
+int slrng_jump_poly(int variant, const uint64_t *J_words, int nj, uint64_t *out, int out_words);
+
+/* ---------------------------------------------------------------- streams
+ *
+ * slrng_streams_create: S = n_streams streams on the current device.  The
+ * base state is the SplitMix64 fill of `seed` and stream i is the base
+ * jumped i times by SLRNG_JUMP, i.e. state_i = base * M^(i 2^(n/2)).
+ * n_streams in [1, 2^31] (ERANGE otherwise).  The handle owns 2 S k words of
+ * device memory.
+ *
+ * slrng_streams_create_from_states: S streams with the given logical-order
+ * states, host_words[i*k + j] = word j of stream i.  EZEROSTATE if a state is
+ * all zero.  Synchronous upload.
+ *
+ * slrng_streams_seed: re-seeds an existing handle in place, exactly as
+ * slrng_streams_create would position it (no allocation; asynchronous).
+ *
+ * slrng_streams_count / slrng_streams_variant: S and the variant.
+ *
+ * slrng_streams_jump / slrng_streams_advance: every stream advances by the
+ * jump (SLRNG_JUMP or SLRNG_LONG_JUMP) or by steps_hi 2^64 + steps_lo steps.
+ *
+ * slrng_generate: for every stream i, out[i*ld + t] = output t, t < n; the
+ * stream then stands n steps further (generate(a); generate(b) produces the
+ * same values as generate(a + b)).  dev_out: device memory, 8-byte aligned,
+ * at least (S-1) ld + n elements; ld >= n (EINVAL otherwise), overflow of the
+ * extent is ERANGE.  n = 0 is a successful no-op.  kind selects uint64 or
+ * doubles; both are bit-exact.
+ *
+ * slrng_get_state / slrng_set_state: copy the S x k logical-order states to or
+ * from host memory (host_words[i*k + j]); synchronous on `stream`.  set_state
+ * rejects an all-zero state with EZEROSTATE and leaves the handle unchanged.
+ *
+ * slrng_streams_destroy: frees the handle (after the device is idle). */
+int slrng_streams_create(int variant, uint64_t seed, uint64_t n_streams, hipStream_t stream,
+                         slrng_streams **out);
+int slrng_streams_create_from_states(int variant, const uint64_t *host_words, uint64_t n_streams,
+                                     hipStream_t stream, slrng_streams **out);
+int slrng_streams_seed(slrng_streams *h, uint64_t seed, hipStream_t stream);
+int slrng_streams_count(const slrng_streams *h, uint64_t *n_streams);
+int slrng_streams_variant(const slrng_streams *h, int *variant);
+int slrng_streams_jump(slrng_streams *h, int jump_kind, hipStream_t stream);
+int slrng_streams_advance(slrng_streams *h, uint64_t steps_hi, uint64_t steps_lo,
+                          hipStream_t stream);
+int slrng_generate(slrng_streams *h, int kind, uint64_t n, void *dev_out, uint64_t ld,
+                   hipStream_t stream);
+int slrng_get_state(const slrng_streams *h, uint64_t *host_words, hipStream_t stream);
+int slrng_set_state(slrng_streams *h, const uint64_t *host_words, hipStream_t stream);
+int slrng_streams_destroy(slrng_streams *h);
+
+/* ---------------------------------------------------------------- tuning
+ *
+ * Launch shape of slrng_generate per (variant, kind):
+ *  tile          outputs per lane staged through LDS per round (16 or 32);
+ *  target_waves  streams are split into chunks (each chunk starts from the
+ *                stream jumped by a multiple of the chunk length) until about
+ *                this many waves run, at most 16 chunks per stream;
+ *  min_chunk     no chunk shorter than this many outputs.
+ * Values outside the accepted range give EINVAL. */
+typedef struct slrng_tuning {
+  int32_t tile;
+  int32_t target_waves;
+  uint64_t min_chunk;
+} slrng_tuning;
+
+int slrng_get_tuning(int variant, int kind, slrng_tuning *out);
+int slrng_set_tuning(int variant, int kind, const slrng_tuning *t);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SLRNG_H */

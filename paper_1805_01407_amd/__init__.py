@@ -1,0 +1,21 @@
+"""slrng: bulk generation from the scrambled linear generators of Blackman &
+Vigna ("Scrambled Linear Pseudorandom Number Generators") on MI355X.
+
+The work is done by ``libslrng.so`` (HIP kernels for gfx950 behind a C ABI,
+declared in ``include/slrng.h``).  This package is a thin ctypes binding with
+the same function names; PyTorch only supplies device memory and streams.
+Importing the package does not load the library; the first call does, and it
+raises if the library has not been built (``python -m
+paper_1805_01407_amd.build``).
+"""
+from .binding import (  # noqa: F401
+    VARIANTS, VARIANT_IDS, SlrngError, Streams, lib, library_path,
+    slrng_version, slrng_strerror, slrng_last_hip_error, slrng_state_words,
+    slrng_charpoly, slrng_jump_poly,
+    slrng_streams_create, slrng_streams_create_from_states, slrng_streams_count,
+    slrng_streams_variant, slrng_streams_seed,
+    slrng_streams_jump, slrng_streams_advance, slrng_generate,
+    slrng_get_state, slrng_set_state, slrng_streams_destroy,
+    slrng_get_tuning, slrng_set_tuning, slrng_calib_write, slrng_calib_copy,
+    SLRNG_U64, SLRNG_F64, SLRNG_JUMP, SLRNG_LONG_JUMP,
+)

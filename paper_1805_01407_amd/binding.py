@@ -1,0 +1,309 @@
+"""ctypes binding of libslrng.so (include/slrng.h).  Argument marshalling only:
+every computation happens in the library.
+
+Functions named ``slrng_*`` mirror the C ABI one to one and raise
+``SlrngError`` on a negative return code.  ``Streams`` is a small object
+wrapper over a stream handle that allocates output tensors with torch.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(HERE, "libslrng.so")
+
+SLRNG_U64, SLRNG_F64 = 0, 1
+SLRNG_JUMP, SLRNG_LONG_JUMP = 0, 1
+
+VARIANTS = [
+    "xoroshiro128+", "xoroshiro128++", "xoroshiro128**",
+    "xoshiro256+", "xoshiro256++", "xoshiro256**",
+    "xoshiro512+", "xoshiro512++", "xoshiro512**",
+    "xoroshiro1024+", "xoroshiro1024++", "xoroshiro1024**",
+    "xoroshiro128*", "xoroshiro1024*",
+]
+VARIANT_IDS = {name: i for i, name in enumerate(VARIANTS)}
+_ERRNAMES = {-1: "EINVAL", -2: "ERANGE", -3: "ENOMEM", -4: "EZEROSTATE", -5: "EAGAIN",
+             -6: "EHIP", -7: "ENOTIMPL"}
+
+
+class SlrngError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        self.code = code
+        self.name = _ERRNAMES.get(code, str(code))
+        msg = f"{where}: {self.name}"
+        if code == -6:
+            msg += f" (HIP error {_lib.slrng_last_hip_error()})" if _lib is not None else ""
+        super().__init__(msg)
+
+
+class _Tuning(ctypes.Structure):
+    _fields_ = [("tile", ctypes.c_int32), ("target_waves", ctypes.c_int32),
+                ("min_chunk", ctypes.c_uint64)]
+
+
+_lib = None
+
+
+def library_path() -> str:
+    return _LIB_PATH
+
+
+def lib():
+    """Load libslrng.so (torch first, so both share one HIP runtime)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    import torch  # noqa: F401  (loads the HIP runtime the library binds to)
+    if not os.path.exists(_LIB_PATH):
+        raise ImportError(f"{_LIB_PATH} is missing: build it with "
+                          "`python -m paper_1805_01407_amd.build`")
+    L = ctypes.CDLL(_LIB_PATH)
+    vp, u64, u64p = ctypes.c_void_p, ctypes.c_uint64, ctypes.POINTER(ctypes.c_uint64)
+    i32 = ctypes.c_int
+    sig = {
+        "slrng_version": ([], i32),
+        "slrng_strerror": ([i32], ctypes.c_char_p),
+        "slrng_last_hip_error": ([], i32),
+        "slrng_state_words": ([i32], i32),
+        "slrng_charpoly": ([i32, u64p, i32], i32),
+        "slrng_jump_poly": ([i32, u64p, i32, u64p, i32], i32),
+        "slrng_streams_create": ([i32, u64, u64, vp, ctypes.POINTER(vp)], i32),
+        "slrng_streams_create_from_states": ([i32, u64p, u64, vp, ctypes.POINTER(vp)], i32),
+        "slrng_streams_seed": ([vp, u64, vp], i32),
+        "slrng_streams_count": ([vp, u64p], i32),
+        "slrng_streams_variant": ([vp, ctypes.POINTER(i32)], i32),
+        "slrng_streams_jump": ([vp, i32, vp], i32),
+        "slrng_streams_advance": ([vp, u64, u64, vp], i32),
+        "slrng_generate": ([vp, i32, u64, vp, u64, vp], i32),
+        "slrng_get_state": ([vp, u64p, vp], i32),
+        "slrng_set_state": ([vp, u64p, vp], i32),
+        "slrng_streams_destroy": ([vp], i32),
+        "slrng_get_tuning": ([i32, i32, ctypes.POINTER(_Tuning)], i32),
+        "slrng_set_tuning": ([i32, i32, ctypes.POINTER(_Tuning)], i32),
+        "slrng_calib_write": ([vp, u64, vp], i32),
+        "slrng_calib_copy": ([vp, vp, u64, vp], i32),
+    }
+    for name, (args, res) in sig.items():
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = res
+    _lib = L
+    return L
+
+
+def _check(rc: int, where: str) -> int:
+    if rc < 0:
+        raise SlrngError(rc, where)
+    return rc
+
+
+def _stream(stream) -> int | None:
+    """hipStream_t of a torch stream, an int, or the current torch stream."""
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+def _u64p(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64))
+
+
+def _variant(v) -> int:
+    return VARIANT_IDS[v] if isinstance(v, str) else int(v)
+
+
+# ---------------------------------------------------------------- C ABI mirror
+
+def slrng_version() -> int:
+    return lib().slrng_version()
+
+
+def slrng_strerror(err: int) -> str:
+    return lib().slrng_strerror(err).decode()
+
+
+def slrng_last_hip_error() -> int:
+    return lib().slrng_last_hip_error()
+
+
+def slrng_state_words(variant) -> int:
+    return _check(lib().slrng_state_words(_variant(variant)), "slrng_state_words")
+
+
+def _words_to_int(a: np.ndarray) -> int:
+    v = 0
+    for i, w in enumerate(a.tolist()):
+        v |= int(w) << (64 * i)
+    return v
+
+
+def slrng_charpoly(variant) -> int:
+    """Characteristic polynomial as a Python int (bit i = coefficient of x^i)."""
+    n = 64 * slrng_state_words(variant)
+    out = np.zeros(n // 64 + 1, dtype=np.uint64)
+    _check(lib().slrng_charpoly(_variant(variant), _u64p(out), out.size), "slrng_charpoly")
+    return _words_to_int(out)
+
+
+def slrng_jump_poly(variant, J: int) -> int:
+    """x^J mod p(x) as a Python int."""
+    n = 64 * slrng_state_words(variant)
+    nj = max(0, (J.bit_length() + 63) // 64)
+    jw = np.array([(J >> (64 * i)) & 0xFFFFFFFFFFFFFFFF for i in range(max(nj, 1))],
+                  dtype=np.uint64)
+    out = np.zeros(n // 64, dtype=np.uint64)
+    _check(lib().slrng_jump_poly(_variant(variant), _u64p(jw), nj, _u64p(out), out.size),
+           "slrng_jump_poly")
+    return _words_to_int(out)
+
+
+def slrng_streams_create(variant, seed: int, n_streams: int, stream=None) -> int:
+    h = ctypes.c_void_p()
+    _check(lib().slrng_streams_create(_variant(variant), seed & 0xFFFFFFFFFFFFFFFF, n_streams,
+                                      _stream(stream), ctypes.byref(h)), "slrng_streams_create")
+    return h.value
+
+
+def slrng_streams_create_from_states(variant, states: np.ndarray, stream=None) -> int:
+    st = np.ascontiguousarray(np.asarray(states, dtype=np.uint64))
+    k = slrng_state_words(variant)
+    S = st.size // k
+    h = ctypes.c_void_p()
+    _check(lib().slrng_streams_create_from_states(_variant(variant), _u64p(st), S,
+                                                  _stream(stream), ctypes.byref(h)),
+           "slrng_streams_create_from_states")
+    return h.value
+
+
+def slrng_streams_seed(h: int, seed: int, stream=None) -> None:
+    _check(lib().slrng_streams_seed(h, seed & 0xFFFFFFFFFFFFFFFF, _stream(stream)),
+           "slrng_streams_seed")
+
+
+def slrng_streams_count(h: int) -> int:
+    n = ctypes.c_uint64()
+    _check(lib().slrng_streams_count(h, ctypes.byref(n)), "slrng_streams_count")
+    return n.value
+
+
+def slrng_streams_variant(h: int) -> int:
+    v = ctypes.c_int()
+    _check(lib().slrng_streams_variant(h, ctypes.byref(v)), "slrng_streams_variant")
+    return v.value
+
+
+def slrng_streams_jump(h: int, jump_kind: int = SLRNG_JUMP, stream=None) -> None:
+    _check(lib().slrng_streams_jump(h, jump_kind, _stream(stream)), "slrng_streams_jump")
+
+
+def slrng_streams_advance(h: int, steps: int, stream=None) -> None:
+    _check(lib().slrng_streams_advance(h, (steps >> 64) & 0xFFFFFFFFFFFFFFFF,
+                                       steps & 0xFFFFFFFFFFFFFFFF, _stream(stream)),
+           "slrng_streams_advance")
+
+
+def slrng_generate(h: int, kind: int, n: int, dev_out: int, ld: int, stream=None) -> None:
+    _check(lib().slrng_generate(h, kind, n, dev_out, ld, _stream(stream)), "slrng_generate")
+
+
+def slrng_get_state(h: int, stream=None) -> np.ndarray:
+    """States as an S x k uint64 array (logical order)."""
+    S = slrng_streams_count(h)
+    k = slrng_state_words(slrng_streams_variant(h))
+    out = np.zeros(S * k, dtype=np.uint64)
+    _check(lib().slrng_get_state(h, _u64p(out), _stream(stream)), "slrng_get_state")
+    return out.reshape(S, k)
+
+
+def slrng_set_state(h: int, states: np.ndarray, stream=None) -> None:
+    st = np.ascontiguousarray(np.asarray(states, dtype=np.uint64))
+    _check(lib().slrng_set_state(h, _u64p(st), _stream(stream)), "slrng_set_state")
+
+
+def slrng_streams_destroy(h: int) -> None:
+    _check(lib().slrng_streams_destroy(h), "slrng_streams_destroy")
+
+
+def slrng_get_tuning(variant, kind: int = SLRNG_U64) -> dict:
+    t = _Tuning()
+    _check(lib().slrng_get_tuning(_variant(variant), kind, ctypes.byref(t)), "slrng_get_tuning")
+    return {"tile": t.tile, "target_waves": t.target_waves, "min_chunk": t.min_chunk}
+
+
+def slrng_set_tuning(variant, kind: int, tile: int, target_waves: int, min_chunk: int) -> None:
+    t = _Tuning(tile, target_waves, min_chunk)
+    _check(lib().slrng_set_tuning(_variant(variant), kind, ctypes.byref(t)), "slrng_set_tuning")
+
+
+def slrng_calib_write(dev_out: int, nbytes: int, stream=None) -> None:
+    _check(lib().slrng_calib_write(dev_out, nbytes, _stream(stream)), "slrng_calib_write")
+
+
+def slrng_calib_copy(dev_dst: int, dev_src: int, nbytes: int, stream=None) -> None:
+    _check(lib().slrng_calib_copy(dev_dst, dev_src, nbytes, _stream(stream)), "slrng_calib_copy")
+
+
+# ---------------------------------------------------------------- object wrapper
+
+class Streams:
+    """S device-resident streams of one variant (see slrng_streams_create)."""
+
+    def __init__(self, variant, seed: int = 0, n_streams: int = 1, states=None, stream=None):
+        self.variant = _variant(variant)
+        self.k = slrng_state_words(self.variant)
+        if states is not None:
+            self.h = slrng_streams_create_from_states(self.variant, states, stream)
+        else:
+            self.h = slrng_streams_create(self.variant, seed, n_streams, stream)
+        self.S = slrng_streams_count(self.h)
+
+    def close(self):
+        if getattr(self, "h", None):
+            slrng_streams_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def generate(self, n: int, kind: int = SLRNG_U64, out=None, ld: int | None = None,
+                 stream=None):
+        """Outputs as a torch tensor [S, ld] (int64 bit patterns or float64)."""
+        import torch
+        if ld is None:
+            ld = n
+        if out is None:
+            dt = torch.int64 if kind == SLRNG_U64 else torch.float64
+            out = torch.empty((self.S, max(ld, 1)), dtype=dt, device="cuda")
+        slrng_generate(self.h, kind, n, out.data_ptr(), ld, stream)
+        return out
+
+    def seed(self, seed: int, stream=None):
+        slrng_streams_seed(self.h, seed, stream)
+
+    def jump(self, jump_kind: int = SLRNG_JUMP, stream=None):
+        slrng_streams_jump(self.h, jump_kind, stream)
+
+    def advance(self, steps: int, stream=None):
+        slrng_streams_advance(self.h, steps, stream)
+
+    def get_state(self, stream=None) -> np.ndarray:
+        return slrng_get_state(self.h, stream)
+
+    def set_state(self, states, stream=None):
+        slrng_set_state(self.h, np.asarray(states, dtype=np.uint64).reshape(-1), stream)

@@ -1,0 +1,480 @@
+// C ABI of slrng (include/slrng.h): stream handles, jump planning and launch
+// shapes.  The kernels are in kernels.hip; the polynomial arithmetic that turns
+// a jump distance into a jump polynomial is in f2poly.cpp.
+#include <hip/hip_runtime_api.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <map>
+#include <mutex>
+#include <new>
+#include <tuple>
+#include <vector>
+
+#include "../../include/slrng.h"
+#include "../../include/slrng_calib.h"
+#include "api_internal.hpp"
+#include "engines.hpp"
+#include "f2poly.hpp"
+#include "kernels.hpp"
+
+using namespace slrng;
+
+// ---------------------------------------------------------------- errors
+
+static thread_local int g_last_hip = 0;
+
+namespace slrng {
+int hip_fail(hipError_t e) {
+  g_last_hip = (int)e;
+  return SLRNG_EHIP;
+}
+}  // namespace slrng
+
+#define HIPCHK(call)                              \
+  do {                                            \
+    hipError_t e_ = (call);                       \
+    if (e_ != hipSuccess) return hip_fail(e_);    \
+  } while (0)
+
+extern "C" int slrng_version(void) { return SLRNG_ABI_VERSION; }
+
+extern "C" const char *slrng_strerror(int err) {
+  switch (err) {
+    case SLRNG_OK: return "SLRNG_OK";
+    case SLRNG_EINVAL: return "SLRNG_EINVAL: invalid argument";
+    case SLRNG_ERANGE: return "SLRNG_ERANGE: size out of range";
+    case SLRNG_ENOMEM: return "SLRNG_ENOMEM: out of memory";
+    case SLRNG_EZEROSTATE: return "SLRNG_EZEROSTATE: all-zero state";
+    case SLRNG_EAGAIN: return "SLRNG_EAGAIN: resource temporarily unavailable";
+    case SLRNG_EHIP: return "SLRNG_EHIP: HIP call failed";
+    case SLRNG_ENOTIMPL: return "SLRNG_ENOTIMPL: not implemented";
+    default: return "SLRNG: unknown error";
+  }
+}
+
+extern "C" int slrng_last_hip_error(void) { return g_last_hip; }
+
+// ---------------------------------------------------------------- variants
+
+namespace slrng {
+
+static const int kK[kNumVariants] = {2, 2, 2, 4, 4, 4, 8, 8, 8, 16, 16, 16, 2, 16};
+static const int kEngine[kNumVariants] = {0, 1, 0, 2, 2, 2, 3, 3, 3, 4, 4, 4, 0, 4};
+
+bool valid_variant(int v) { return v >= 0 && v < kNumVariants; }
+int variant_words(int v) { return kK[v]; }
+int variant_engine(int v) { return kEngine[v]; }
+
+// ---------------------------------------------------------------- polynomials
+
+// x^J mod p for a jump kind (2^(n/2) or 2^(3n/4)), cached per engine.
+const Poly &jump_kind_poly(int engine, int jump_kind) {
+  static std::mutex mu;
+  static std::map<std::pair<int, int>, Poly> cache;
+  std::lock_guard<std::mutex> g(mu);
+  auto key = std::make_pair(engine, jump_kind);
+  auto it = cache.find(key);
+  if (it != cache.end()) return it->second;
+  const Field &f = engine_field(engine);
+  Poly r;
+  f.xpow2(jump_kind == SLRNG_LONG_JUMP ? 3 * f.n / 4 : f.n / 2, r);
+  return cache.emplace(key, r).first->second;
+}
+
+// ---------------------------------------------------------------- device tables
+
+// Positioning tables of one engine on one device.
+struct PosTables {
+  int levels = 0;
+  uint64_t *tab0 = nullptr;  // word-major: word w of entry d at [w*1024 + d]
+  uint64_t *up = nullptr;    // (levels-1) x 1024 x 16
+};
+
+static std::mutex g_tab_mu;
+static std::map<std::pair<int, int>, PosTables> g_pos;             // (device, engine)
+static std::map<std::tuple<int, int, uint64_t>, uint64_t *> g_chunk;  // (device, engine, C)
+
+int levels_for(uint64_t S) {
+  int l = 1;
+  uint64_t cap = kTabRadix;
+  while (cap < S && l < kMaxLevels) {
+    cap *= kTabRadix;
+    l++;
+  }
+  return l;
+}
+
+// Entry d = x^(d * 2^e) mod p for d < 1024.
+static void power_table(const Field &f, int e, std::vector<Poly> &out) {
+  out.resize(kTabRadix);
+  Poly g;
+  f.xpow2(e, g);
+  out[0].clear();
+  out[0].w[0] = 1;
+  for (int d = 1; d < kTabRadix; d++) f.mulmod(out[d - 1], g, out[d]);
+}
+
+int get_pos_tables(int device, int engine, int levels, PosTables **out) {
+  std::lock_guard<std::mutex> g(g_tab_mu);
+  PosTables &t = g_pos[std::make_pair(device, engine)];
+  if (t.levels >= levels) {
+    *out = &t;
+    return SLRNG_OK;
+  }
+  const Field &f = engine_field(engine);
+  const int W = f.n / 64;
+  std::vector<Poly> ent;
+  // level 0: jump distance J = 2^(n/2); level l: 1024^l J = 2^(10 l + n/2)
+  power_table(f, f.n / 2, ent);
+  std::vector<uint64_t> h0((size_t)W * kTabRadix);
+  for (int d = 0; d < kTabRadix; d++)
+    for (int w = 0; w < W; w++) h0[(size_t)w * kTabRadix + d] = ent[d].w[w];
+  std::vector<uint64_t> hu((size_t)(levels > 1 ? levels - 1 : 1) * kTabRadix * 16, 0);
+  for (int l = 1; l < levels; l++) {
+    power_table(f, 10 * l + f.n / 2, ent);
+    for (int d = 0; d < kTabRadix; d++)
+      for (int w = 0; w < 16; w++) hu[((size_t)(l - 1) * kTabRadix + d) * 16 + w] = ent[d].w[w];
+  }
+  uint64_t *d0 = nullptr, *du = nullptr;
+  HIPCHK(hipMalloc(&d0, h0.size() * 8));
+  hipError_t e = hipMalloc(&du, hu.size() * 8);
+  if (e != hipSuccess) {
+    (void)hipFree(d0);
+    return hip_fail(e);
+  }
+  HIPCHK(hipMemcpy(d0, h0.data(), h0.size() * 8, hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(du, hu.data(), hu.size() * 8, hipMemcpyHostToDevice));
+  // tables of fewer levels may still be in use by queued kernels: keep them
+  t.tab0 = d0;
+  t.up = du;
+  t.levels = levels;
+  *out = &t;
+  return SLRNG_OK;
+}
+
+// Chunk start polynomials x^(j C) mod p, j < kMaxChunks, 16 words each.
+int get_chunk_polys(int device, int engine, uint64_t C, const uint64_t **out) {
+  std::lock_guard<std::mutex> g(g_tab_mu);
+  auto key = std::make_tuple(device, engine, C);
+  auto it = g_chunk.find(key);
+  if (it != g_chunk.end()) {
+    *out = it->second;
+    return SLRNG_OK;
+  }
+  const Field &f = engine_field(engine);
+  Poly step;
+  uint64_t J[1] = {C};
+  f.xpow(J, 1, step);
+  std::vector<uint64_t> h((size_t)kMaxChunks * 16, 0);
+  Poly cur;
+  cur.clear();
+  cur.w[0] = 1;
+  for (int j = 0; j < kMaxChunks; j++) {
+    for (int w = 0; w < 16; w++) h[(size_t)j * 16 + w] = cur.w[w];
+    Poly nx;
+    f.mulmod(cur, step, nx);
+    cur = nx;
+  }
+  uint64_t *d = nullptr;
+  HIPCHK(hipMalloc(&d, h.size() * 8));
+  HIPCHK(hipMemcpy(d, h.data(), h.size() * 8, hipMemcpyHostToDevice));
+  g_chunk[key] = d;
+  *out = d;
+  return SLRNG_OK;
+}
+
+// ---------------------------------------------------------------- tuning
+
+static slrng_tuning g_tune[kNumVariants][2];
+static std::once_flag g_tune_once;
+
+static void init_tuning() {
+  for (int v = 0; v < kNumVariants; v++)
+    for (int k = 0; k < 2; k++) g_tune[v][k] = slrng_tuning{16, 4096, 4096};
+}
+
+slrng_tuning tuning_for(int v, int kind) {
+  std::call_once(g_tune_once, init_tuning);
+  return g_tune[v][kind];
+}
+
+// Chunk plan of a generate call: nchunks chunks of C outputs (C a multiple of
+// the tile, so the 16-word engine's chunks start block aligned).
+void plan_chunks(uint64_t S, uint64_t n, const slrng_tuning &t, uint64_t &C, uint64_t &nchunks) {
+  const uint64_t waves = (S + kWave - 1) / kWave;
+  uint64_t want = 1;
+  if (waves < (uint64_t)t.target_waves) want = ((uint64_t)t.target_waves + waves - 1) / waves;
+  if (want > (uint64_t)kMaxChunks) want = kMaxChunks;
+  const uint64_t T = (uint64_t)t.tile;
+  C = (n + want - 1) / want;
+  if (C < t.min_chunk) C = t.min_chunk;
+  C = (C + T - 1) / T * T;
+  nchunks = (n + C - 1) / C;
+  if (nchunks == 0) nchunks = 1;
+}
+
+}  // namespace slrng
+
+// ---------------------------------------------------------------- handles
+
+struct slrng_streams {
+  int variant;
+  int k;
+  int engine;
+  int device;
+  uint64_t S;
+  uint64_t *state[2];
+  int cur;
+};
+
+extern "C" int slrng_state_words(int variant) {
+  if (!valid_variant(variant)) return SLRNG_EINVAL;
+  return variant_words(variant);
+}
+
+extern "C" int slrng_charpoly(int variant, uint64_t *out, int out_words) {
+  if (!valid_variant(variant) || !out) return SLRNG_EINVAL;
+  const Field &f = engine_field(variant_engine(variant));
+  if (out_words < f.n / 64 + 1) return SLRNG_EINVAL;
+  for (int i = 0; i <= f.n / 64; i++) out[i] = f.p.w[i];
+  return SLRNG_OK;
+}
+
+extern "C" int slrng_jump_poly(int variant, const uint64_t *J, int nj, uint64_t *out,
+                               int out_words) {
+  if (!valid_variant(variant) || !out || nj < 0 || (nj > 0 && !J)) return SLRNG_EINVAL;
+  const Field &f = engine_field(variant_engine(variant));
+  if (out_words < f.n / 64) return SLRNG_EINVAL;
+  Poly r;
+  if (nj == 0) {
+    r.clear();
+    r.w[0] = 1;
+  } else {
+    f.xpow(J, nj, r);
+  }
+  for (int i = 0; i < f.n / 64; i++) out[i] = r.w[i];
+  return SLRNG_OK;
+}
+
+static int alloc_handle(int variant, uint64_t S, slrng_streams **out) {
+  if (!valid_variant(variant) || !out) return SLRNG_EINVAL;
+  if (S == 0 || S > (1ull << 31)) return SLRNG_ERANGE;
+  slrng_streams *h = new (std::nothrow) slrng_streams();
+  if (!h) return SLRNG_ENOMEM;
+  h->variant = variant;
+  h->k = variant_words(variant);
+  h->engine = variant_engine(variant);
+  h->S = S;
+  h->cur = 0;
+  h->state[0] = h->state[1] = nullptr;
+  hipError_t e = hipGetDevice(&h->device);
+  if (e != hipSuccess) {
+    delete h;
+    return hip_fail(e);
+  }
+  const size_t bytes = (size_t)S * h->k * 8;
+  for (int b = 0; b < 2; b++) {
+    e = hipMalloc(&h->state[b], bytes);
+    if (e != hipSuccess) {
+      if (h->state[0]) (void)hipFree(h->state[0]);
+      delete h;
+      return e == hipErrorOutOfMemory ? SLRNG_ENOMEM : hip_fail(e);
+    }
+  }
+  *out = h;
+  return SLRNG_OK;
+}
+
+extern "C" int slrng_streams_destroy(slrng_streams *h) {
+  if (!h) return SLRNG_EINVAL;
+  for (int b = 0; b < 2; b++)
+    if (h->state[b]) (void)hipFree(h->state[b]);
+  delete h;
+  return SLRNG_OK;
+}
+
+static int position(slrng_streams *h, uint64_t seed, hipStream_t stream) {
+  PosTables *t = nullptr;
+  const int levels = levels_for(h->S);
+  int rc = get_pos_tables(h->device, h->engine, levels, &t);
+  if (rc) return rc;
+  hipError_t e = launch_position(h->variant, seed, h->S, t->tab0, t->up, levels,
+                                 h->state[h->cur], stream);
+  return e == hipSuccess ? SLRNG_OK : hip_fail(e);
+}
+
+extern "C" int slrng_streams_create(int variant, uint64_t seed, uint64_t S, hipStream_t stream,
+                                    slrng_streams **out) {
+  if (!out) return SLRNG_EINVAL;
+  *out = nullptr;
+  slrng_streams *h = nullptr;
+  int rc = alloc_handle(variant, S, &h);
+  if (rc) return rc;
+  rc = position(h, seed, stream);
+  if (rc) {
+    slrng_streams_destroy(h);
+    return rc;
+  }
+  *out = h;
+  return SLRNG_OK;
+}
+
+extern "C" int slrng_streams_seed(slrng_streams *h, uint64_t seed, hipStream_t stream) {
+  if (!h) return SLRNG_EINVAL;
+  return position(h, seed, stream);
+}
+
+static bool any_zero_state(const uint64_t *w, uint64_t S, int k) {
+  for (uint64_t i = 0; i < S; i++) {
+    uint64_t acc = 0;
+    for (int j = 0; j < k; j++) acc |= w[i * k + j];
+    if (!acc) return true;
+  }
+  return false;
+}
+
+extern "C" int slrng_set_state(slrng_streams *h, const uint64_t *host_words, hipStream_t stream) {
+  if (!h || !host_words) return SLRNG_EINVAL;
+  if (any_zero_state(host_words, h->S, h->k)) return SLRNG_EZEROSTATE;
+  std::vector<uint64_t> soa((size_t)h->S * h->k);
+  for (uint64_t i = 0; i < h->S; i++)
+    for (int j = 0; j < h->k; j++) soa[(size_t)j * h->S + i] = host_words[i * h->k + j];
+  HIPCHK(hipMemcpyAsync(h->state[h->cur], soa.data(), soa.size() * 8, hipMemcpyHostToDevice, stream));
+  HIPCHK(hipStreamSynchronize(stream));
+  return SLRNG_OK;
+}
+
+extern "C" int slrng_get_state(const slrng_streams *h, uint64_t *host_words, hipStream_t stream) {
+  if (!h || !host_words) return SLRNG_EINVAL;
+  std::vector<uint64_t> soa((size_t)h->S * h->k);
+  HIPCHK(hipMemcpyAsync(soa.data(), h->state[h->cur], soa.size() * 8, hipMemcpyDeviceToHost, stream));
+  HIPCHK(hipStreamSynchronize(stream));
+  for (uint64_t i = 0; i < h->S; i++)
+    for (int j = 0; j < h->k; j++) host_words[i * h->k + j] = soa[(size_t)j * h->S + i];
+  return SLRNG_OK;
+}
+
+extern "C" int slrng_streams_create_from_states(int variant, const uint64_t *host_words, uint64_t S,
+                                                hipStream_t stream, slrng_streams **out) {
+  if (!out || !host_words) return SLRNG_EINVAL;
+  *out = nullptr;
+  if (valid_variant(variant) && S > 0 && S <= (1ull << 31) &&
+      any_zero_state(host_words, S, variant_words(variant)))
+    return SLRNG_EZEROSTATE;
+  slrng_streams *h = nullptr;
+  int rc = alloc_handle(variant, S, &h);
+  if (rc) return rc;
+  rc = slrng_set_state(h, host_words, stream);
+  if (rc) {
+    slrng_streams_destroy(h);
+    return rc;
+  }
+  *out = h;
+  return SLRNG_OK;
+}
+
+extern "C" int slrng_streams_count(const slrng_streams *h, uint64_t *n) {
+  if (!h || !n) return SLRNG_EINVAL;
+  *n = h->S;
+  return SLRNG_OK;
+}
+
+extern "C" int slrng_streams_variant(const slrng_streams *h, int *v) {
+  if (!h || !v) return SLRNG_EINVAL;
+  *v = h->variant;
+  return SLRNG_OK;
+}
+
+static int apply_uniform(slrng_streams *h, const Poly &r, hipStream_t stream) {
+  UPoly u;
+  for (int i = 0; i < 16; i++) u.w[i] = r.w[i];
+  hipError_t e = launch_jump(h->variant, h->state[h->cur], h->S, u, stream);
+  return e == hipSuccess ? SLRNG_OK : hip_fail(e);
+}
+
+extern "C" int slrng_streams_jump(slrng_streams *h, int jump_kind, hipStream_t stream) {
+  if (!h || (jump_kind != SLRNG_JUMP && jump_kind != SLRNG_LONG_JUMP)) return SLRNG_EINVAL;
+  return apply_uniform(h, jump_kind_poly(h->engine, jump_kind), stream);
+}
+
+extern "C" int slrng_streams_advance(slrng_streams *h, uint64_t hi, uint64_t lo, hipStream_t stream) {
+  if (!h) return SLRNG_EINVAL;
+  if (hi == 0 && lo == 0) return SLRNG_OK;
+  const Field &f = engine_field(h->engine);
+  uint64_t J[2] = {lo, hi};
+  Poly r;
+  f.xpow(J, 2, r);
+  return apply_uniform(h, r, stream);
+}
+
+extern "C" int slrng_generate(slrng_streams *h, int kind, uint64_t n, void *dev_out, uint64_t ld,
+                              hipStream_t stream) {
+  if (!h || (kind != SLRNG_U64 && kind != SLRNG_F64)) return SLRNG_EINVAL;
+  if (n == 0) return SLRNG_OK;
+  if (!dev_out || ((uintptr_t)dev_out & 7)) return SLRNG_EINVAL;
+  if (ld < n) return SLRNG_EINVAL;
+  // extent (S-1) ld + n elements, in bytes, must fit in 64 bits
+  const uint64_t S1 = h->S - 1;
+  if (S1 && ld > (UINT64_MAX - n) / S1) return SLRNG_ERANGE;
+  const uint64_t extent = S1 * ld + n;
+  if (extent > UINT64_MAX / 8) return SLRNG_ERANGE;
+  const slrng_tuning t = tuning_for(h->variant, kind);
+  uint64_t C = 0, nchunks = 1;
+  plan_chunks(h->S, n, t, C, nchunks);
+  const uint64_t *cp = nullptr;
+  if (nchunks > 1) {
+    int rc = get_chunk_polys(h->device, h->engine, C, &cp);
+    if (rc) return rc;
+  }
+  GenArgs a;
+  a.state_in = h->state[h->cur];
+  a.state_out = nchunks > 1 ? h->state[1 - h->cur] : h->state[h->cur];
+  a.S = h->S;
+  a.n = n;
+  a.C = C;
+  a.nchunks = nchunks;
+  a.out = dev_out;
+  a.ld = ld;
+  a.chunk_polys = cp;
+  GenConfig cfg{t.tile};
+  hipError_t e = launch_generate(h->variant, kind, a, cfg, stream);
+  if (e != hipSuccess) return hip_fail(e);
+  if (nchunks > 1) h->cur = 1 - h->cur;
+  return SLRNG_OK;
+}
+
+// ---------------------------------------------------------------- tuning ABI
+
+extern "C" int slrng_get_tuning(int variant, int kind, slrng_tuning *out) {
+  if (!valid_variant(variant) || (kind != SLRNG_U64 && kind != SLRNG_F64) || !out)
+    return SLRNG_EINVAL;
+  *out = tuning_for(variant, kind);
+  return SLRNG_OK;
+}
+
+extern "C" int slrng_set_tuning(int variant, int kind, const slrng_tuning *t) {
+  if (!valid_variant(variant) || (kind != SLRNG_U64 && kind != SLRNG_F64) || !t)
+    return SLRNG_EINVAL;
+  if ((t->tile != 16 && t->tile != 32) || t->target_waves < 1 || t->target_waves > (1 << 20) ||
+      t->min_chunk < 1 || t->min_chunk > (1ull << 40))
+    return SLRNG_EINVAL;
+  tuning_for(variant, kind);
+  g_tune[variant][kind] = *t;
+  return SLRNG_OK;
+}
+
+// ---------------------------------------------------------------- calibration
+
+extern "C" int slrng_calib_write(void *dev_out, uint64_t bytes, hipStream_t stream) {
+  if (!dev_out || bytes % 16 || ((uintptr_t)dev_out & 15)) return SLRNG_EINVAL;
+  hipError_t e = launch_write_ceiling(dev_out, bytes, stream);
+  return e == hipSuccess ? SLRNG_OK : hip_fail(e);
+}
+
+extern "C" int slrng_calib_copy(void *dst, const void *src, uint64_t bytes, hipStream_t stream) {
+  if (!dst || !src || bytes % 16 || ((uintptr_t)dst & 15) || ((uintptr_t)src & 15))
+    return SLRNG_EINVAL;
+  hipError_t e = launch_copy(dst, src, bytes, stream);
+  return e == hipSuccess ? SLRNG_OK : hip_fail(e);
+}

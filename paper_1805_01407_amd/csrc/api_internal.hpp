@@ -1,0 +1,21 @@
+// Internal helpers shared by the C ABI translation units.
+#pragma once
+#include <hip/hip_runtime_api.h>
+#include <stdint.h>
+
+#include "../../include/slrng.h"
+#include "f2poly.hpp"
+
+namespace slrng {
+
+int hip_fail(hipError_t e);  // records the HIP error, returns SLRNG_EHIP
+bool valid_variant(int v);
+int variant_words(int v);
+int variant_engine(int v);
+const Poly &jump_kind_poly(int engine, int jump_kind);
+int levels_for(uint64_t S);
+int get_chunk_polys(int device, int engine, uint64_t C, const uint64_t **out);
+slrng_tuning tuning_for(int v, int kind);
+void plan_chunks(uint64_t S, uint64_t n, const slrng_tuning &t, uint64_t &C, uint64_t &nchunks);
+
+}  // namespace slrng

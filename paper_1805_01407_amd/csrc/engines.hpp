@@ -1,0 +1,220 @@
+// Linear engines and scramblers of Blackman & Vigna, "Scrambled Linear
+// Pseudorandom Number Generators", as compile-time templates usable on the GPU
+// (per-lane state in VGPRs) and on the host (the planner derives each engine's
+// characteristic polynomial from them).
+//
+//  * xoroshiro, 2 words: Section "Linear engines", figure fig:xoroshiro128.
+//  * xoroshiro, 16 words: figure fig:xoroshiro1024.  The figure's cyclic index
+//    p is kept as a compile-time phase P in 0..15 so every register index is
+//    static; a block of 16 steps brings the registers back to logical order
+//    x_j = s[j] (logical order: the row vector of the block matrix eq:M).
+//  * xoshiro, 4 and 8 words: figures fig:xoshiro256 and fig:xoshiro512.
+//  * scramblers +, ++, *, **: Section "Scramblers", applied to the state
+//    before it is advanced; parameters from tables tab:par64 and tab:scr64.
+#pragma once
+#include <stdint.h>
+
+#if defined(__HIPCC__)
+#include <hip/hip_runtime.h>
+#define SL_HD __host__ __device__ __forceinline__
+#else
+#define SL_HD inline
+#endif
+
+namespace slrng {
+
+typedef uint64_t u64;
+
+enum Family { XOROSHIRO = 0, XOSHIRO = 1 };
+enum Scrambler { SCR_PLUS = 0, SCR_PLUSPLUS = 1, SCR_STAR = 2, SCR_STARSTAR = 3 };
+
+template <int R>
+SL_HD u64 rotl(u64 x) {
+  static_assert(R > 0 && R < 64, "rotation amount");
+  return (x << R) | (x >> (64 - R));
+}
+
+// ** multiplies by 2^s + 1 (S = 5, T = 9 in tab:scr64), which the paper notes
+// can be computed as a shift and a sum.
+template <u64 M>
+SL_HD u64 mul_const(u64 x) {
+  if constexpr (M == 5) return x + (x << 2);
+  else if constexpr (M == 9) return x + (x << 3);
+  else return x * M;
+}
+
+// Parameters per variant id (the ids of slrng_variant in include/slrng.h).
+template <int V> struct Params;
+
+#define SL_VARIANT(ID, FAM, K, A, B, C, SCR, R)                           \
+  template <> struct Params<ID> {                                          \
+    static constexpr int family = FAM, k = K, a = A, b = B, c = C;         \
+    static constexpr int scr = SCR, r = R;                                 \
+  };
+
+// tab:par64: xoroshiro128 24/16/37 (for +, *, **); xoroshiro128++ 49/21/28;
+// xoshiro256 17/45; xoshiro512 11/21; xoroshiro1024 25/27/36.
+// tab:scr64: ++ rotation 17 / 23 / 17 / 23; ** is (5, 7, 9).
+SL_VARIANT(0, XOROSHIRO, 2, 24, 16, 37, SCR_PLUS, 0)
+SL_VARIANT(1, XOROSHIRO, 2, 49, 21, 28, SCR_PLUSPLUS, 17)
+SL_VARIANT(2, XOROSHIRO, 2, 24, 16, 37, SCR_STARSTAR, 7)
+SL_VARIANT(3, XOSHIRO, 4, 17, 45, 0, SCR_PLUS, 0)
+SL_VARIANT(4, XOSHIRO, 4, 17, 45, 0, SCR_PLUSPLUS, 23)
+SL_VARIANT(5, XOSHIRO, 4, 17, 45, 0, SCR_STARSTAR, 7)
+SL_VARIANT(6, XOSHIRO, 8, 11, 21, 0, SCR_PLUS, 0)
+SL_VARIANT(7, XOSHIRO, 8, 11, 21, 0, SCR_PLUSPLUS, 17)
+SL_VARIANT(8, XOSHIRO, 8, 11, 21, 0, SCR_STARSTAR, 7)
+SL_VARIANT(9, XOROSHIRO, 16, 25, 27, 36, SCR_PLUS, 0)
+SL_VARIANT(10, XOROSHIRO, 16, 25, 27, 36, SCR_PLUSPLUS, 23)
+SL_VARIANT(11, XOROSHIRO, 16, 25, 27, 36, SCR_STARSTAR, 7)
+SL_VARIANT(12, XOROSHIRO, 2, 24, 16, 37, SCR_STAR, 0)
+SL_VARIANT(13, XOROSHIRO, 16, 25, 27, 36, SCR_STAR, 0)
+#undef SL_VARIANT
+
+constexpr int kNumVariants = 14;
+constexpr u64 kStarMul = 0x9e3779b97f4a7c13ull;  // tab:scr64, the * multiplier
+
+// Engine id: variants that share an engine (same transition matrix) share
+// characteristic polynomial and jump tables.
+template <int V>
+constexpr int engine_id() {
+  using P = Params<V>;
+  return P::k == 2 ? (P::a == 24 ? 0 : 1) : (P::k == 4 ? 2 : (P::k == 8 ? 3 : 4));
+}
+constexpr int kNumEngines = 5;
+
+// Steps per static block: 16 for the cyclic 16-word xoroshiro, 1 otherwise.
+template <int V>
+constexpr int block_steps() { return Params<V>::k == 16 ? 16 : 1; }
+
+// ---------------------------------------------------------------- output
+
+// Scrambled output of the current state.  P is the step's phase inside a
+// block (only meaningful for 16 words: the figure's s0 is s[P] and its s15
+// is s[(P + 15) & 15]).
+template <int V, int P>
+SL_HD u64 output(const u64 (&s)[Params<V>::k]) {
+  using Q = Params<V>;
+  constexpr int K = Q::k;
+  if constexpr (Q::family == XOROSHIRO) {
+    constexpr int i0 = K == 2 ? 0 : (P & 15);
+    constexpr int il = K == 2 ? 1 : ((P + 15) & 15);
+    const u64 s0 = s[i0], sl = s[il];
+    if constexpr (Q::scr == SCR_PLUS) return s0 + sl;
+    else if constexpr (Q::scr == SCR_PLUSPLUS) {
+      // fig:xoroshiro128 adds s0 after the rotation, fig:xoroshiro1024 s15
+      if constexpr (K == 2) return rotl<Q::r>(s0 + sl) + s0;
+      else return rotl<Q::r>(s0 + sl) + sl;
+    } else if constexpr (Q::scr == SCR_STAR) return s0 * kStarMul;
+    else return mul_const<9>(rotl<7>(mul_const<5>(s0)));
+  } else {
+    if constexpr (Q::scr == SCR_STARSTAR) return mul_const<9>(rotl<7>(mul_const<5>(s[1])));
+    else if constexpr (K == 4) {
+      if constexpr (Q::scr == SCR_PLUS) return s[0] + s[3];
+      else return rotl<Q::r>(s[0] + s[3]) + s[0];      // fig:xoshiro256
+    } else {
+      if constexpr (Q::scr == SCR_PLUS) return s[0] + s[2];
+      else return rotl<Q::r>(s[0] + s[2]) + s[2];      // fig:xoshiro512
+    }
+  }
+}
+
+// ---------------------------------------------------------------- step
+
+template <int V, int P>
+SL_HD void step(u64 (&s)[Params<V>::k]) {
+  using Q = Params<V>;
+  constexpr int K = Q::k;
+  if constexpr (Q::family == XOROSHIRO) {
+    constexpr int i0 = K == 2 ? 0 : (P & 15);
+    constexpr int il = K == 2 ? 1 : ((P + 15) & 15);
+    const u64 s0 = s[i0];
+    const u64 t = s[il] ^ s0;
+    // the updated pair lands in the slots of s[q] and s[p] of the figure:
+    // for two words that is s[0] and s[1]; for 16 words s[P+15] and s[P]
+    if constexpr (K == 2) {
+      s[0] = rotl<Q::a>(s0) ^ t ^ (t << Q::b);
+      s[1] = rotl<Q::c>(t);
+    } else {
+      s[il] = rotl<Q::a>(s0) ^ t ^ (t << Q::b);
+      s[i0] = rotl<Q::c>(t);
+    }
+  } else if constexpr (K == 4) {
+    const u64 t = s[1] << Q::a;
+    s[2] ^= s[0];
+    s[3] ^= s[1];
+    s[1] ^= s[2];
+    s[0] ^= s[3];
+    s[2] ^= t;
+    s[3] = rotl<Q::b>(s[3]);
+  } else {
+    const u64 t = s[1] << Q::a;
+    s[2] ^= s[0];
+    s[5] ^= s[1];
+    s[1] ^= s[2];
+    s[7] ^= s[3];
+    s[3] ^= s[4];
+    s[4] ^= s[5];
+    s[0] ^= s[6];
+    s[6] ^= s[7];
+    s[6] ^= t;
+    s[7] = rotl<Q::b>(s[7]);
+  }
+}
+
+// Logical word j of a 16-word state whose registers have run `ph` steps past
+// logical alignment: s[(ph + j) & 15].
+template <int V>
+SL_HD void rotate_to_logical(u64 (&s)[Params<V>::k], int ph) {
+  constexpr int K = Params<V>::k;
+  if constexpr (K == 16) {
+    // rotate left by ph in four static passes (ph is uniform across a wave)
+    if (ph & 1) { u64 t = s[0]; for (int j = 0; j < 15; j++) s[j] = s[j + 1]; s[15] = t; }
+    if (ph & 2) { u64 t0 = s[0], t1 = s[1]; for (int j = 0; j < 14; j++) s[j] = s[j + 2]; s[14] = t0; s[15] = t1; }
+    if (ph & 4) { u64 t[4]; for (int j = 0; j < 4; j++) t[j] = s[j]; for (int j = 0; j < 12; j++) s[j] = s[j + 4]; for (int j = 0; j < 4; j++) s[12 + j] = t[j]; }
+    if (ph & 8) { u64 t[8]; for (int j = 0; j < 8; j++) t[j] = s[j]; for (int j = 0; j < 8; j++) s[j] = s[j + 8]; for (int j = 0; j < 8; j++) s[8 + j] = t[j]; }
+  } else {
+    (void)s; (void)ph;
+  }
+}
+
+// Host-side single step on a logical-order state (slow path for the planner).
+template <int V>
+inline void host_step_logical(u64 *x) {
+  constexpr int K = Params<V>::k;
+  u64 s[K];
+  for (int j = 0; j < K; j++) s[j] = x[j];
+  step<V, 0>(s);
+  if constexpr (K == 16) rotate_to_logical<V>(s, 1);
+  for (int j = 0; j < K; j++) x[j] = s[j];
+}
+
+template <int V>
+inline u64 host_output_logical(const u64 *x) {
+  constexpr int K = Params<V>::k;
+  u64 s[K];
+  for (int j = 0; j < K; j++) s[j] = x[j];
+  return output<V, 0>(s);
+}
+
+// ---------------------------------------------------------------- SplitMix64
+
+// Seeding (Section "Choosing a generator"): the state is filled with
+// consecutive outputs of SplitMix64 seeded with the 64-bit seed.  SplitMix64
+// (Steele, Lea, Flood, OOPSLA 2014): counter += golden gamma, then the mix64
+// finalizer.
+constexpr u64 kGoldenGamma = 0x9e3779b97f4a7c15ull;
+
+SL_HD u64 splitmix64_mix(u64 z) {
+  z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+  z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+  return z ^ (z >> 31);
+}
+
+template <int K>
+SL_HD void splitmix64_fill(u64 seed, u64 (&s)[K]) {
+#pragma unroll
+  for (int j = 0; j < K; j++) s[j] = splitmix64_mix(seed + (u64)(j + 1) * kGoldenGamma);
+}
+
+}  // namespace slrng

@@ -1,0 +1,394 @@
+// gfx950 kernels for bulk generation from scrambled linear generators
+// (Blackman & Vigna, "Scrambled Linear Pseudorandom Number Generators").
+//
+// Design for CDNA4:
+//  * one stream per lane; the k-word engine state lives in VGPRs and every
+//    step is a handful of 64-bit VALU xor / shift / rotate operations (the
+//    code figures of Section "Linear engines");
+//  * outputs are stream-major (out[i*ld + t]), so a lane's consecutive outputs
+//    are contiguous.  Each wave stages a tile of T outputs per lane in LDS
+//    (row = lane) and then reads it back column-wise so that each
+//    global_store_dwordx4 writes whole 128/256-byte runs of a few rows:
+//    fully coalesced, nontemporal (write-once data, no reuse);
+//  * waves never wait on each other: every wave owns its LDS rows and the
+//    LDS exchange inside a wave is ordered by the in-order LDS queue plus
+//    a wavefront-scope fence (no workgroup barrier);
+//  * positioning uses the jump polynomials of the planner (Cayley-Hamilton
+//    reading of the paper's jump functions): acc ^= s for every set
+//    coefficient while the engine steps.
+#include <hip/hip_runtime.h>
+
+#include "engines.hpp"
+#include "kernels.hpp"
+
+namespace slrng {
+
+typedef u64 u64x2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Exact 53-bit double of the upper 53 bits: (x >> 11) * 2^-53 as
+// hi * 2^-21 + lo * 2^-53 with hi = x >> 43 (21 bits) and lo = bits 11..42;
+// both products are exact and so is their sum (53 significant bits).
+__device__ __forceinline__ u64 to_f64_bits(u64 x) {
+  const unsigned hi = (unsigned)(x >> 43);
+  const unsigned lo = (unsigned)(x >> 11);
+  const double d = __fma_rn((double)hi, 0x1p-21, (double)lo * 0x1p-53);
+  return (u64)__double_as_longlong(d);
+}
+
+template <int KIND>
+__device__ __forceinline__ u64 emit(u64 x) {
+  if constexpr (KIND == 1) return to_f64_bits(x);
+  else return x;
+}
+
+// compile-time loop
+template <int N, typename F, int I = 0>
+__device__ __forceinline__ void static_for(F &&f) {
+  if constexpr (I < N) {
+    f(std::integral_constant<int, I>{});
+    static_for<N, F, I + 1>(static_cast<F &&>(f));
+  }
+}
+
+// ---------------------------------------------------------------- jumps
+
+// acc ^= logical(s) at phase P (16 words: logical word j is s[(P+j)&15])
+template <int V, int P>
+__device__ __forceinline__ void acc_xor(u64 (&acc)[Params<V>::k], const u64 (&s)[Params<V>::k]) {
+  constexpr int K = Params<V>::k;
+#pragma unroll
+  for (int j = 0; j < K; j++) acc[j] ^= s[K == 16 ? ((P + j) & 15) : j];
+}
+
+template <int V, int P>
+__device__ __forceinline__ void acc_xor_masked(u64 (&acc)[Params<V>::k], const u64 (&s)[Params<V>::k],
+                                               u64 m) {
+  constexpr int K = Params<V>::k;
+#pragma unroll
+  for (int j = 0; j < K; j++) acc[j] ^= s[K == 16 ? ((P + j) & 15) : j] & m;
+}
+
+// s <- s * M^J where the uniform polynomial r(x) = x^J mod p has its 64-bit
+// words at r[0 .. n/64) (same address in every lane).
+template <int V>
+__device__ __forceinline__ void jump_uniform(u64 (&s)[Params<V>::k], const u64 *__restrict__ r) {
+  constexpr int K = Params<V>::k;
+  constexpr int BLK = block_steps<V>();
+  u64 acc[K];
+#pragma unroll
+  for (int j = 0; j < K; j++) acc[j] = 0;
+  for (int wi = 0; wi < K; wi++) {  // n/64 = K words
+    // readfirstlane returns int: widen through unsigned so the low half is
+    // not sign-extended into the high half
+    const u64 lo = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)r[wi]);
+    const u64 hi = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)(r[wi] >> 32));
+    const u64 word = lo | (hi << 32);
+    for (int b = 0; b < 64; b += BLK) {
+      static_for<BLK>([&](auto P) {
+        if ((word >> (b + P)) & 1) acc_xor<V, P>(acc, s);
+        step<V, P>(s);
+      });
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < K; j++) s[j] = acc[j];
+}
+
+// The same with a per-lane polynomial read word by word from r_words(wi).
+template <int V, typename GetWord>
+__device__ __forceinline__ void jump_lane(u64 (&s)[Params<V>::k], GetWord &&r_word) {
+  constexpr int K = Params<V>::k;
+  constexpr int BLK = block_steps<V>();
+  u64 acc[K];
+#pragma unroll
+  for (int j = 0; j < K; j++) acc[j] = 0;
+  for (int wi = 0; wi < K; wi++) {
+    const u64 word = r_word(wi);
+    const unsigned half[2] = {(unsigned)word, (unsigned)(word >> 32)};
+#pragma unroll
+    for (int h = 0; h < 2; h++) {
+      for (int b = 0; b < 32; b += BLK) {
+        static_for<BLK>([&](auto P) {
+          // sign-extended one-bit field: 0 or all ones
+          const int m32 = __builtin_amdgcn_sbfe((int)half[h], b + P, 1);
+          const u64 m = (u64)(long long)m32;
+          acc_xor_masked<V, P>(acc, s, m);
+          step<V, P>(s);
+        });
+      }
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < K; j++) s[j] = acc[j];
+}
+
+// ---------------------------------------------------------------- generation tiles
+
+template <int T>
+struct TileGeom {
+  static constexpr int kPad = 2;            // u64 of padding per LDS row
+  static constexpr int kStride = T + kPad;  // LDS row stride (u64), even
+  static constexpr int kWaveLds = kWave * kStride;
+};
+
+// T outputs of one lane into its LDS row (row pointer `row`), as pairs.
+template <int V, int KIND, int T>
+__device__ __forceinline__ void gen_tile_full(u64 (&s)[Params<V>::k], u64 *row) {
+  constexpr int BLK = block_steps<V>();
+  static_assert(T % BLK == 0 && T % 2 == 0, "tile");
+#pragma unroll
+  for (int t0 = 0; t0 < T; t0 += (BLK > 2 ? BLK : 2)) {
+    static_for<(BLK > 2 ? BLK : 2) / 2>([&](auto H) {
+      constexpr int P0 = (2 * H.value) % BLK;
+      constexpr int P1 = (2 * H.value + 1) % BLK;
+      u64x2 v;
+      v.x = emit<KIND>(output<V, P0>(s));
+      step<V, P0>(s);
+      v.y = emit<KIND>(output<V, P1>(s));
+      step<V, P1>(s);
+      *reinterpret_cast<u64x2 *>(row + t0 + 2 * H.value) = v;
+    });
+  }
+}
+
+// m < T outputs (the last, partial tile of a chunk).  Returns the number of
+// steps past the last 16-step block boundary (for the 16-word engine).
+template <int V, int KIND, int T>
+__device__ __forceinline__ int gen_tile_partial(u64 (&s)[Params<V>::k], u64 *row, int m) {
+  constexpr int BLK = block_steps<V>();
+#pragma unroll
+  for (int t0 = 0; t0 < T; t0 += BLK) {
+    if (t0 >= m) break;
+    static_for<BLK>([&](auto P) {
+      if (t0 + P < m) {
+        row[t0 + P] = emit<KIND>(output<V, P>(s));
+        step<V, P>(s);
+      }
+    });
+  }
+  return m % BLK;
+}
+
+template <typename VT>
+__device__ __forceinline__ void nt_store(VT *p, VT v) {
+  __builtin_nontemporal_store(v, p);
+}
+
+// Store a staged tile: rows 0..rows_live of the wave, m outputs each, to
+// base + r*ld + c.  A16: every row start is 16-byte aligned (dwordx4 path).
+template <int T, bool A16>
+__device__ __forceinline__ void store_tile(const u64 *lds, int lane, u64 *base, u64 ld,
+                                           int rows_live, int m) {
+  constexpr int S = TileGeom<T>::kStride;
+  if constexpr (A16) {
+    constexpr int LPR = T / 2;         // lanes per row, 16 bytes each
+    constexpr int RPI = kWave / LPR;   // rows per store instruction
+#pragma unroll
+    for (int q = 0; q < T / 2; q++) {
+      const int r = q * RPI + lane / LPR;
+      const int c = 2 * (lane % LPR);
+      if (r < rows_live && c < m) {
+        const u64x2 v = *reinterpret_cast<const u64x2 *>(lds + r * S + c);
+        u64 *dst = base + (u64)r * ld + c;
+        if (c + 1 < m) nt_store(reinterpret_cast<u64x2 *>(dst), v);
+        else nt_store(dst, v.x);
+      }
+    }
+  } else {
+    constexpr int LPR = T;
+    constexpr int RPI = kWave / LPR;
+#pragma unroll
+    for (int q = 0; q < T; q++) {
+      const int r = q * RPI + lane / LPR;
+      const int c = lane % LPR;
+      if (r < rows_live && c < m) nt_store(base + (u64)r * ld + c, lds[r * S + c]);
+    }
+  }
+}
+
+template <int V, int KIND, int T, bool A16>
+__global__ __launch_bounds__(kBlock) void k_generate(GenArgs a) {
+  constexpr int K = Params<V>::k;
+  __shared__ __attribute__((aligned(16))) u64 lds_all[(kBlock / kWave) * TileGeom<T>::kWaveLds];
+  const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+  const u64 row0 = ((u64)blockIdx.x * (kBlock / kWave) + wave) * kWave;
+  if (row0 >= a.S) return;  // uniform per wave
+  const u64 i = row0 + lane;
+  const bool live = i < a.S;
+  const u64 j = blockIdx.y;
+  const u64 t_begin = j * a.C;
+  const u64 cnt = (a.n - t_begin < a.C) ? a.n - t_begin : a.C;
+
+  u64 s[K];
+#pragma unroll
+  for (int w = 0; w < K; w++) s[w] = live ? a.state_in[(u64)w * a.S + i] : 0;
+  if (j > 0) jump_uniform<V>(s, a.chunk_polys + j * 16);
+
+  u64 *lds = lds_all + wave * TileGeom<T>::kWaveLds;
+  u64 *myrow = lds + lane * TileGeom<T>::kStride;
+  const int rows_live = (a.S - row0 < (u64)kWave) ? (int)(a.S - row0) : kWave;
+  u64 *base = reinterpret_cast<u64 *>(a.out) + row0 * a.ld + t_begin;
+  int ph = 0;
+  for (u64 t0 = 0; t0 < cnt; t0 += T) {
+    const int m = (cnt - t0 < (u64)T) ? (int)(cnt - t0) : T;
+    if (m == T) gen_tile_full<V, KIND, T>(s, myrow);
+    else ph = gen_tile_partial<V, KIND, T>(s, myrow, m);
+    wave_sync();
+    store_tile<T, A16>(lds, lane, base + t0, a.ld, rows_live, m);
+    wave_sync();
+  }
+  if constexpr (K == 16) rotate_to_logical<V>(s, ph);
+  if (j + 1 == a.nchunks && live) {
+#pragma unroll
+    for (int w = 0; w < K; w++) a.state_out[(u64)w * a.S + i] = s[w];
+  }
+}
+
+// ---------------------------------------------------------------- positioning
+
+template <int V>
+__global__ __launch_bounds__(kBlock) void k_position(u64 seed, u64 S, const u64 *__restrict__ tab0,
+                                                     const u64 *__restrict__ up, int levels,
+                                                     u64 *__restrict__ state_out) {
+  constexpr int K = Params<V>::k;
+  const u64 i = (u64)blockIdx.x * kBlock + threadIdx.x;
+  const u64 first = i - (threadIdx.x % kWave);
+  if (first >= S) return;  // uniform per wave
+  u64 s[K];
+  splitmix64_fill<K>(seed, s);
+  const unsigned d0 = (unsigned)(i % kTabRadix);
+  jump_lane<V>(s, [&](int wi) { return tab0[(u64)wi * kTabRadix + d0]; });
+  for (int l = 1; l < levels; l++) {
+    // (i >> 10l) is the same in every lane of a wave (64 divides 1024)
+    const unsigned d = (unsigned)((first >> (10 * l)) % kTabRadix);
+    if (d) jump_uniform<V>(s, up + ((u64)(l - 1) * kTabRadix + d) * 16);
+  }
+  if (i < S) {
+#pragma unroll
+    for (int w = 0; w < K; w++) state_out[(u64)w * S + i] = s[w];
+  }
+}
+
+template <int V>
+__global__ __launch_bounds__(kBlock) void k_jump(u64 *__restrict__ state, u64 S, UPoly r) {
+  constexpr int K = Params<V>::k;
+  const u64 i = (u64)blockIdx.x * kBlock + threadIdx.x;
+  const u64 first = i - (threadIdx.x % kWave);
+  if (first >= S) return;
+  const bool live = i < S;
+  u64 s[K];
+#pragma unroll
+  for (int w = 0; w < K; w++) s[w] = live ? state[(u64)w * S + i] : 0;
+  jump_uniform<V>(s, r.w);
+  if (live) {
+#pragma unroll
+    for (int w = 0; w < K; w++) state[(u64)w * S + i] = s[w];
+  }
+}
+
+// ---------------------------------------------------------------- calibration
+
+__global__ __launch_bounds__(kBlock) void k_write_ceiling(u64x2 *out, u64 n16) {
+  const u64 stride = (u64)gridDim.x * kBlock;
+  const u64x2 v = {0x0123456789abcdefull, 0xfedcba9876543210ull};
+  for (u64 i = (u64)blockIdx.x * kBlock + threadIdx.x; i < n16; i += stride) nt_store(out + i, v);
+}
+
+__global__ __launch_bounds__(kBlock) void k_copy(u64x2 *dst, const u64x2 *src, u64 n16) {
+  const u64 stride = (u64)gridDim.x * kBlock;
+  for (u64 i = (u64)blockIdx.x * kBlock + threadIdx.x; i < n16; i += stride) dst[i] = src[i];
+}
+
+// ---------------------------------------------------------------- launchers
+
+template <int V, int KIND, int T>
+static hipError_t gen_t(const GenArgs &a, hipStream_t st) {
+  const u64 waves = (a.S + kWave - 1) / kWave;
+  dim3 grid((unsigned)((waves + (kBlock / kWave) - 1) / (kBlock / kWave)), (unsigned)a.nchunks);
+  const bool a16 = ((uintptr_t)a.out % 16 == 0) && (a.ld % 2 == 0) && (a.C % 2 == 0);
+  if (a16) hipLaunchKernelGGL((k_generate<V, KIND, T, true>), grid, dim3(kBlock), 0, st, a);
+  else hipLaunchKernelGGL((k_generate<V, KIND, T, false>), grid, dim3(kBlock), 0, st, a);
+  return hipGetLastError();
+}
+
+template <int V>
+static hipError_t gen_v(int kind, const GenArgs &a, const GenConfig &cfg, hipStream_t st) {
+  if (cfg.tile == 32) return kind ? gen_t<V, 1, 32>(a, st) : gen_t<V, 0, 32>(a, st);
+  return kind ? gen_t<V, 1, 16>(a, st) : gen_t<V, 0, 16>(a, st);
+}
+
+#define SL_DISPATCH(v, EXPR_T)      \
+  switch (v) {                      \
+    case 0: return EXPR_T(0);       \
+    case 1: return EXPR_T(1);       \
+    case 2: return EXPR_T(2);       \
+    case 3: return EXPR_T(3);       \
+    case 4: return EXPR_T(4);       \
+    case 5: return EXPR_T(5);       \
+    case 6: return EXPR_T(6);       \
+    case 7: return EXPR_T(7);       \
+    case 8: return EXPR_T(8);       \
+    case 9: return EXPR_T(9);       \
+    case 10: return EXPR_T(10);     \
+    case 11: return EXPR_T(11);     \
+    case 12: return EXPR_T(12);     \
+    case 13: return EXPR_T(13);     \
+    default: return hipErrorInvalidValue; \
+  }
+
+hipError_t launch_generate(int variant, int kind, const GenArgs &a, const GenConfig &cfg,
+                           hipStream_t st) {
+#define SL_GEN(V) gen_v<V>(kind, a, cfg, st)
+  SL_DISPATCH(variant, SL_GEN)
+#undef SL_GEN
+}
+
+template <int V>
+static hipError_t pos_v(u64 seed, u64 S, const u64 *tab0, const u64 *up, int levels, u64 *out,
+                        hipStream_t st) {
+  dim3 grid((unsigned)((S + kBlock - 1) / kBlock));
+  hipLaunchKernelGGL((k_position<V>), grid, dim3(kBlock), 0, st, seed, S, tab0, up, levels, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_position(int variant, uint64_t seed, uint64_t S, const uint64_t *tab0,
+                           const uint64_t *up, int levels, uint64_t *state_out, hipStream_t st) {
+#define SL_POS(V) pos_v<V>(seed, S, tab0, up, levels, state_out, st)
+  SL_DISPATCH(variant, SL_POS)
+#undef SL_POS
+}
+
+template <int V>
+static hipError_t jump_v(u64 *state, u64 S, const UPoly &r, hipStream_t st) {
+  dim3 grid((unsigned)((S + kBlock - 1) / kBlock));
+  hipLaunchKernelGGL((k_jump<V>), grid, dim3(kBlock), 0, st, state, S, r);
+  return hipGetLastError();
+}
+
+hipError_t launch_jump(int variant, uint64_t *state, uint64_t S, const UPoly &r, hipStream_t st) {
+#define SL_JMP(V) jump_v<V>(state, S, r, st)
+  SL_DISPATCH(variant, SL_JMP)
+#undef SL_JMP
+}
+
+hipError_t launch_write_ceiling(void *out, uint64_t bytes, hipStream_t st) {
+  const u64 n16 = bytes / 16;
+  hipLaunchKernelGGL(k_write_ceiling, dim3(256 * 32), dim3(kBlock), 0, st,
+                     reinterpret_cast<u64x2 *>(out), n16);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy(void *dst, const void *src, uint64_t bytes, hipStream_t st) {
+  const u64 n16 = bytes / 16;
+  hipLaunchKernelGGL(k_copy, dim3(256 * 32), dim3(kBlock), 0, st, reinterpret_cast<u64x2 *>(dst),
+                     reinterpret_cast<const u64x2 *>(src), n16);
+  return hipGetLastError();
+}
+
+}  // namespace slrng

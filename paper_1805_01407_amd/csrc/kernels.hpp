@@ -1,0 +1,57 @@
+// Launch interface of the gfx950 kernels (internal to the library).
+#pragma once
+#include <hip/hip_runtime_api.h>
+#include <stdint.h>
+
+namespace slrng {
+
+constexpr int kWave = 64;        // lanes per wavefront on CDNA
+constexpr int kBlock = 256;      // 4 waves per workgroup, each wave independent
+constexpr int kTabRadix = 1024;  // entries per positioning table level
+constexpr int kMaxLevels = 4;    // up to 2^40 streams
+constexpr int kMaxChunks = 16;   // chunks per stream in one generate launch
+
+// A polynomial of degree < 1024 passed by value (jump by one uniform distance).
+struct UPoly {
+  uint64_t w[16];
+};
+
+// Generation of n outputs per stream for S streams whose states are stored
+// word-major (word w of stream i at state[w*S + i]).  Each stream may be split
+// into chunks of C outputs; chunk j starts from the stream state jumped by
+// j*C steps (chunk_polys[j] = x^(jC) mod p, 16 words per entry).
+struct GenArgs {
+  const uint64_t *state_in;
+  uint64_t *state_out;
+  uint64_t S;
+  uint64_t n;
+  uint64_t C;
+  uint64_t nchunks;
+  void *out;
+  uint64_t ld;
+  const uint64_t *chunk_polys;
+};
+
+struct GenConfig {
+  int tile;  // outputs per lane staged through LDS per round: 16 or 32
+};
+
+// All return hipError_t of the launch.
+hipError_t launch_generate(int variant, int kind, const GenArgs &a, const GenConfig &cfg,
+                           hipStream_t st);
+
+// Stream positioning: stream i = splitmix(seed) * M^(i*J).  tab0 is the
+// per-lane level (word-major: word w of entry d at tab0[w*1024 + d]); upper
+// levels hold entry d of level l at up[((l-1)*1024 + d)*16].
+hipError_t launch_position(int variant, uint64_t seed, uint64_t S, const uint64_t *tab0,
+                           const uint64_t *up, int levels, uint64_t *state_out, hipStream_t st);
+
+// In-place jump of S word-major states by one polynomial.
+hipError_t launch_jump(int variant, uint64_t *state, uint64_t S, const UPoly &r, hipStream_t st);
+
+// Calibration: write `bytes` of a constant with the same store path, and a
+// plain copy kernel.
+hipError_t launch_write_ceiling(void *out, uint64_t bytes, hipStream_t st);
+hipError_t launch_copy(void *dst, const void *src, uint64_t bytes, hipStream_t st);
+
+}  // namespace slrng

@@ -1,0 +1,115 @@
+"""CPU checks of the C-ABI library: it loads, exports every declared symbol, and
+its host-side polynomial planner agrees with the oracle's independent
+Berlekamp-Massey and square-and-multiply routes.  No kernel is launched."""
+import ctypes
+import glob
+import os
+import random
+import re
+
+import numpy as np
+import pytest
+
+import oracle as O
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def P():
+    import paper_1805_01407_amd as P
+    if not os.path.exists(P.library_path()):
+        from paper_1805_01407_amd import build
+        build.build()
+    P.lib()
+    return P
+
+
+def declared_functions():
+    names = set()
+    for h in glob.glob(os.path.join(ROOT, "include", "*.h")):
+        text = open(h).read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        for m in re.finditer(r"^\s*[A-Za-z_][\w \*]*?\b(slrng_\w+)\s*\(", text, flags=re.M):
+            names.add(m.group(1))
+    return sorted(names)
+
+
+def test_every_declared_symbol_is_exported(P):
+    names = declared_functions()
+    assert len(names) >= 20
+    L = ctypes.CDLL(P.library_path())
+    for n in names:
+        assert hasattr(L, n), n
+
+
+def test_binding_mirrors_every_declared_symbol(P):
+    for n in declared_functions():
+        assert hasattr(P, n), n
+
+
+def test_version_and_errors(P):
+    assert P.slrng_version() == 1
+    for code in range(0, -8, -1):
+        assert P.slrng_strerror(code).startswith("SLRNG")
+    assert "unknown" in P.slrng_strerror(-99)
+    with pytest.raises(P.SlrngError):
+        P.slrng_state_words(14)
+    assert [P.slrng_state_words(v) for v in range(14)] == \
+        [2, 2, 2, 4, 4, 4, 8, 8, 8, 16, 16, 16, 2, 16]
+
+
+@pytest.mark.parametrize("name", list(O.GEN64))
+def test_charpoly_matches_oracle(P, name):
+    assert P.slrng_charpoly(name) == O.charpoly(O.GEN64[name])
+
+
+@pytest.mark.parametrize("name", ["xoroshiro128+", "xoroshiro128++", "xoshiro256++",
+                                  "xoshiro512**", "xoroshiro1024**"])
+def test_jump_poly_matches_oracle(P, name):
+    g = O.GEN64[name]
+    p = O.charpoly(g)
+    rnd = random.Random(name)
+    Js = [0, 1, 2, 63, 64, g.n - 1, g.n, 1 << (g.n // 2), 1 << (3 * g.n // 4),
+          (1 << 128) - 1, rnd.getrandbits(64), rnd.getrandbits(100)]
+    for J in Js:
+        assert P.slrng_jump_poly(name, J) == O.xpow_mod(J, p), J
+
+
+def test_jump_poly_homomorphism_in_the_library(P):
+    # r_a * r_b = r_{a+b} mod p, with the oracle's multiplier as the judge
+    name = "xoshiro256**"
+    p = O.charpoly(O.GEN64[name])
+    a, b = 1 << 128, 1 << 192
+    ra, rb = P.slrng_jump_poly(name, a), P.slrng_jump_poly(name, b)
+    assert O.poly_mulmod(ra, rb, p) == P.slrng_jump_poly(name, a + b)
+
+
+def test_zero_state_rejected_before_any_device_call(P):
+    st = np.zeros((3, 4), dtype=np.uint64)
+    st[0, 1] = 5
+    with pytest.raises(P.SlrngError) as e:
+        P.slrng_streams_create_from_states("xoshiro256**", st.reshape(-1), stream=0)
+    assert e.value.name == "EZEROSTATE"
+
+
+def test_tuning_validation(P):
+    t = P.slrng_get_tuning("xoshiro256**")
+    assert t["tile"] in (16, 32)
+    with pytest.raises(P.SlrngError):
+        P.slrng_set_tuning("xoshiro256**", 0, 24, 1024, 1024)
+    with pytest.raises(P.SlrngError):
+        P.slrng_set_tuning("xoshiro256**", 2, 16, 1024, 1024)
+    P.slrng_set_tuning("xoshiro256**", 0, t["tile"], t["target_waves"], t["min_chunk"])
+
+
+def test_invalid_arguments_return_einval(P):
+    L = P.lib()
+    assert L.slrng_streams_jump(None, 0, None) == -1
+    assert L.slrng_generate(None, 0, 10, None, 10, None) == -1
+    assert L.slrng_streams_destroy(None) == -1
+    h = ctypes.c_void_p()
+    assert L.slrng_streams_create(99, 1, 1, None, ctypes.byref(h)) == -1
+    assert L.slrng_streams_create(0, 1, 0, None, ctypes.byref(h)) == -2
+    assert L.slrng_streams_create(0, 1, (1 << 31) + 1, None, ctypes.byref(h)) == -2
+    assert L.slrng_calib_write(None, 16, None) == -1
