@@ -16,7 +16,6 @@ from __future__ import annotations
 import argparse
 import json
 import os
-import subprocess
 import sys
 import time
 
@@ -32,27 +31,49 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(S_sample: int, N: int, seconds_cap: float = 30.0) -> dict:
-    """The oracle (plain serial C, threaded over streams) on a bounded sample of
-    the same workload: for each of the eight generators, S_sample streams of
-    the seed-1 chain, N outputs each, as uint64 and as doubles."""
+def profiled_traffic() -> int | None:
+    """HBM bytes per generation launch from the committed counter summary
+    (FETCH_SIZE and WRITE_SIZE, scaled by a copy kernel), or None when the
+    kernel source has changed since those counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "k_generate_full_family_sweep_pmc.md")
+    src = os.path.join(ROOT, "paper_1805_01407_amd", "csrc", "kernels.hip")
+    try:
+        fields = dict(line.split(": ", 1) for line in open(path).read().splitlines()
+                      if line.startswith(("traffic_bytes_per_launch: ", "source_sha256: ")))
+        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    except (OSError, ValueError):
+        return None
+    if fields.get("source_sha256") != sha:
+        return None
+    return int(fields["traffic_bytes_per_launch"])
+
+
+def cpu_baseline(batch: int, N: int, seconds: float = 15.0) -> dict:
+    """The oracle (plain serial C, threaded over streams only) on a bounded
+    sample of the same workload: for each of the eight generators in turn,
+    batches of `batch` streams of the seed-1 chain, N outputs each, as uint64
+    and as doubles, until `seconds` of host time are spent."""
     import oracle as O
     nth = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
-    nth = min(nth, 16)
+    nth = max(1, min(nth, 16))
+    chains = {name: O.stream_chain(O.GEN64[name], 1, batch) for name in SWEEP}
     outs = 0
+    rounds = 0
     t0 = time.perf_counter()
-    for name in SWEEP:
-        g = O.GEN64[name]
-        st = O.stream_chain(g, 1, S_sample)
-        O.generate_many(g, st, N, kind="u64", nthreads=nth)
-        O.generate_many(g, st, N, kind="f64", nthreads=nth)
-        outs += 2 * S_sample * N
-        if time.perf_counter() - t0 > seconds_cap:
+    while True:
+        for name in SWEEP:
+            g = O.GEN64[name]
+            O.generate_many(g, chains[name], N, kind="u64", nthreads=nth)
+            O.generate_many(g, chains[name], N, kind="f64", nthreads=nth)
+            outs += 2 * batch * N
+        rounds += 1
+        if time.perf_counter() - t0 >= seconds:
             break
     dt = time.perf_counter() - t0
     return {"value": outs / dt, "unit": "outputs/s", "cores": nth, "kind": "oracle",
-            "sample": f"8 generators x {S_sample} streams x {N} outputs x (u64 + f64), "
-                      f"seed 1, stream chain included; {dt:.1f} s"}
+            "sample": f"{rounds} round(s) of 8 generators x {batch} streams x {N} outputs x "
+                      f"(u64 + f64) from the seed-1 chains; {outs:.3g} outputs in {dt:.1f} s"}
 
 
 def main():
@@ -63,7 +84,8 @@ def main():
     ap.add_argument("--streams", type=int, default=65536)
     ap.add_argument("--n", type=int, default=65536)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--cpu-streams", type=int, default=256)
+    ap.add_argument("--cpu-streams", type=int, default=512, help="streams per oracle batch")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -137,7 +159,12 @@ def main():
         ds = [durs[j] for j in range(len(durs)) if (j // 2) % len(SWEEP) == i]
         per_variant[name] = round(bytes_per_launch / (sum(ds) / len(ds) * 1e-3) / 1e9, 1)
 
-    cpu = None if args.no_cpu else cpu_baseline(args.cpu_streams, N)
+    # a plain copy of known size, for scaling the hardware memory counters
+    copy_bytes = 4 << 30
+    P.slrng_calib_copy(buf_f.data_ptr(), buf_u.data_ptr(), copy_bytes, stream)
+    torch.cuda.synchronize()
+
+    cpu = None if args.no_cpu else cpu_baseline(args.cpu_streams, N, args.cpu_seconds)
     for h in hs.values():
         h.close()
 
@@ -158,7 +185,8 @@ def main():
                                "outputs, uint64 + doubles, seeds 1..8",
                    "streams": S, "outputs_per_stream": N, "generators": SWEEP},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None},
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": profiled_traffic()},
         "write_ceiling_GBs": ceiling,
         "gen_GBs_per_generator": per_variant,
         "cpu_baseline": cpu,

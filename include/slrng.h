@@ -169,11 +169,19 @@ int slrng_streams_destroy(slrng_streams *h);
  *  target_waves  streams are split into chunks (each chunk starts from the
  *                stream jumped by a multiple of the chunk length) until about
  *                this many waves run, at most 16 chunks per stream;
+ *  skew          1, 2, 4, 8 or 16 classes of staggered chunk boundaries
+ *                (groups of 64 streams in different classes start their
+ *                chunks at different offsets, which spreads concurrent stores
+ *                over the memory channels when the row stride is a power of
+ *                two); 1 = no stagger;
  *  min_chunk     no chunk shorter than this many outputs.
- * Values outside the accepted range give EINVAL. */
+ * The launch shape never changes the values produced.  Values outside the
+ * accepted range give EINVAL. */
 typedef struct slrng_tuning {
   int32_t tile;
   int32_t target_waves;
+  int32_t skew;
+  int32_t reserved; /* 0 */
   uint64_t min_chunk;
 } slrng_tuning;
 

@@ -2,8 +2,8 @@
  * Measurement aids shipped with slrng (not part of the generators' method).
  *
  * slrng_calib_write: writes `bytes` (a multiple of 16) of a constant pattern
- *   to dev_out with the same nontemporal 16-byte stores as the generation
- *   kernel: the achievable HBM write ceiling of this store path.
+ *   to dev_out with the same 16-byte stores as the generation kernel, in a
+ *   contiguous grid-stride sweep: a write ceiling of this store path.
  * slrng_calib_copy: copies `bytes` (a multiple of 16) from dev_src to dev_dst:
  *   a kernel of known traffic (bytes read + bytes written) against which the
  *   hardware memory counters are scaled.

@@ -93,7 +93,7 @@ struct PosTables {
 
 static std::mutex g_tab_mu;
 static std::map<std::pair<int, int>, PosTables> g_pos;             // (device, engine)
-static std::map<std::tuple<int, int, uint64_t>, uint64_t *> g_chunk;  // (device, engine, C)
+static std::map<std::tuple<int, int, uint64_t, uint64_t>, uint64_t *> g_slot;  // (device, engine, C, D)
 
 int levels_for(uint64_t S) {
   int l = 1;
@@ -153,34 +153,34 @@ int get_pos_tables(int device, int engine, int levels, PosTables **out) {
   return SLRNG_OK;
 }
 
-// Chunk start polynomials x^(j C) mod p, j < kMaxChunks, 16 words each.
-int get_chunk_polys(int device, int engine, uint64_t C, const uint64_t **out) {
+// Slot start polynomials x^(j C - delta_d) mod p with delta_d = d C / D, for
+// skew class d < D and slot j < kMaxSlots (entry (d kMaxSlots + j), 16 words;
+// entries with j C < delta_d are unused).
+int get_slot_polys(int device, int engine, uint64_t C, uint64_t D, const uint64_t **out) {
   std::lock_guard<std::mutex> g(g_tab_mu);
-  auto key = std::make_tuple(device, engine, C);
-  auto it = g_chunk.find(key);
-  if (it != g_chunk.end()) {
+  auto key = std::make_tuple(device, engine, C, D);
+  auto it = g_slot.find(key);
+  if (it != g_slot.end()) {
     *out = it->second;
     return SLRNG_OK;
   }
   const Field &f = engine_field(engine);
-  Poly step;
-  uint64_t J[1] = {C};
-  f.xpow(J, 1, step);
-  std::vector<uint64_t> h((size_t)kMaxChunks * 16, 0);
-  Poly cur;
-  cur.clear();
-  cur.w[0] = 1;
-  for (int j = 0; j < kMaxChunks; j++) {
-    for (int w = 0; w < 16; w++) h[(size_t)j * 16 + w] = cur.w[w];
-    Poly nx;
-    f.mulmod(cur, step, nx);
-    cur = nx;
+  std::vector<uint64_t> h((size_t)D * kMaxSlots * 16, 0);
+  for (uint64_t d = 0; d < D; d++) {
+    const uint64_t delta = d * (C / D);
+    for (int j = 1; j < kMaxSlots; j++) {
+      const uint64_t pos = (uint64_t)j * C - delta;
+      Poly r;
+      uint64_t J[1] = {pos};
+      f.xpow(J, 1, r);
+      for (int w = 0; w < 16; w++) h[((size_t)d * kMaxSlots + j) * 16 + w] = r.w[w];
+    }
   }
-  uint64_t *d = nullptr;
-  HIPCHK(hipMalloc(&d, h.size() * 8));
-  HIPCHK(hipMemcpy(d, h.data(), h.size() * 8, hipMemcpyHostToDevice));
-  g_chunk[key] = d;
-  *out = d;
+  uint64_t *dev = nullptr;
+  HIPCHK(hipMalloc(&dev, h.size() * 8));
+  HIPCHK(hipMemcpy(dev, h.data(), h.size() * 8, hipMemcpyHostToDevice));
+  g_slot[key] = dev;
+  *out = dev;
   return SLRNG_OK;
 }
 
@@ -191,7 +191,7 @@ static std::once_flag g_tune_once;
 
 static void init_tuning() {
   for (int v = 0; v < kNumVariants; v++)
-    for (int k = 0; k < 2; k++) g_tune[v][k] = slrng_tuning{16, 4096, 4096};
+    for (int k = 0; k < 2; k++) g_tune[v][k] = slrng_tuning{32, 8192, 4, 0, 4096};
 }
 
 slrng_tuning tuning_for(int v, int kind) {
@@ -199,19 +199,23 @@ slrng_tuning tuning_for(int v, int kind) {
   return g_tune[v][kind];
 }
 
-// Chunk plan of a generate call: nchunks chunks of C outputs (C a multiple of
-// the tile, so the 16-word engine's chunks start block aligned).
-void plan_chunks(uint64_t S, uint64_t n, const slrng_tuning &t, uint64_t &C, uint64_t &nchunks) {
+// Slot plan of a generate call: chunks of C outputs (C a multiple of D times
+// the tile, so every slot boundary is tile aligned), nslots = chunks + 1 when
+// the boundaries are staggered.
+void plan_slots(uint64_t S, uint64_t n, const slrng_tuning &t, uint64_t &C, uint64_t &nslots,
+                uint64_t &D) {
   const uint64_t waves = (S + kWave - 1) / kWave;
   uint64_t want = 1;
   if (waves < (uint64_t)t.target_waves) want = ((uint64_t)t.target_waves + waves - 1) / waves;
   if (want > (uint64_t)kMaxChunks) want = kMaxChunks;
-  const uint64_t T = (uint64_t)t.tile;
+  D = (uint64_t)t.skew;
+  const uint64_t unit = (uint64_t)t.tile * D;
   C = (n + want - 1) / want;
   if (C < t.min_chunk) C = t.min_chunk;
-  C = (C + T - 1) / T * T;
-  nchunks = (n + C - 1) / C;
+  C = (C + unit - 1) / unit * unit;
+  uint64_t nchunks = (n + C - 1) / C;
   if (nchunks == 0) nchunks = 1;
+  nslots = nchunks + (D > 1 ? 1 : 0);
 }
 
 }  // namespace slrng
@@ -420,27 +424,30 @@ extern "C" int slrng_generate(slrng_streams *h, int kind, uint64_t n, void *dev_
   const uint64_t extent = S1 * ld + n;
   if (extent > UINT64_MAX / 8) return SLRNG_ERANGE;
   const slrng_tuning t = tuning_for(h->variant, kind);
-  uint64_t C = 0, nchunks = 1;
-  plan_chunks(h->S, n, t, C, nchunks);
-  const uint64_t *cp = nullptr;
-  if (nchunks > 1) {
-    int rc = get_chunk_polys(h->device, h->engine, C, &cp);
+  uint64_t C = 0, nslots = 1, D = 1;
+  plan_slots(h->S, n, t, C, nslots, D);
+  const uint64_t *sp = nullptr;
+  if (nslots > 1) {
+    int rc = get_slot_polys(h->device, h->engine, C, D, &sp);
     if (rc) return rc;
   }
   GenArgs a;
   a.state_in = h->state[h->cur];
-  a.state_out = nchunks > 1 ? h->state[1 - h->cur] : h->state[h->cur];
+  // with several slots, other waves still read the start states while the
+  // last slot finishes: the final states go to the other buffer
+  a.state_out = nslots > 1 ? h->state[1 - h->cur] : h->state[h->cur];
   a.S = h->S;
   a.n = n;
   a.C = C;
-  a.nchunks = nchunks;
+  a.nslots = nslots;
+  a.D = D;
   a.out = dev_out;
   a.ld = ld;
-  a.chunk_polys = cp;
+  a.slot_polys = sp;
   GenConfig cfg{t.tile};
   hipError_t e = launch_generate(h->variant, kind, a, cfg, stream);
   if (e != hipSuccess) return hip_fail(e);
-  if (nchunks > 1) h->cur = 1 - h->cur;
+  if (nslots > 1) h->cur = 1 - h->cur;
   return SLRNG_OK;
 }
 
@@ -457,7 +464,9 @@ extern "C" int slrng_set_tuning(int variant, int kind, const slrng_tuning *t) {
   if (!valid_variant(variant) || (kind != SLRNG_U64 && kind != SLRNG_F64) || !t)
     return SLRNG_EINVAL;
   if ((t->tile != 16 && t->tile != 32) || t->target_waves < 1 || t->target_waves > (1 << 20) ||
-      t->min_chunk < 1 || t->min_chunk > (1ull << 40))
+      t->min_chunk < 1 || t->min_chunk > (1ull << 40) || t->reserved != 0)
+    return SLRNG_EINVAL;
+  if (t->skew != 1 && t->skew != 2 && t->skew != 4 && t->skew != 8 && t->skew != 16)
     return SLRNG_EINVAL;
   tuning_for(variant, kind);
   g_tune[variant][kind] = *t;

@@ -14,8 +14,9 @@ int variant_words(int v);
 int variant_engine(int v);
 const Poly &jump_kind_poly(int engine, int jump_kind);
 int levels_for(uint64_t S);
-int get_chunk_polys(int device, int engine, uint64_t C, const uint64_t **out);
+int get_slot_polys(int device, int engine, uint64_t C, uint64_t D, const uint64_t **out);
 slrng_tuning tuning_for(int v, int kind);
-void plan_chunks(uint64_t S, uint64_t n, const slrng_tuning &t, uint64_t &C, uint64_t &nchunks);
+void plan_slots(uint64_t S, uint64_t n, const slrng_tuning &t, uint64_t &C, uint64_t &nslots,
+                uint64_t &D);
 
 }  // namespace slrng

@@ -175,6 +175,13 @@ __device__ __forceinline__ int gen_tile_partial(u64 (&s)[Params<V>::k], u64 *row
   return m % BLK;
 }
 
+// Output stores are plain (write-back) stores: measured faster than
+// nontemporal ones for the tiled stream-major pattern on gfx950.
+template <typename VT>
+__device__ __forceinline__ void out_store(VT *p, VT v) {
+  *p = v;
+}
+
 template <typename VT>
 __device__ __forceinline__ void nt_store(VT *p, VT v) {
   __builtin_nontemporal_store(v, p);
@@ -196,8 +203,8 @@ __device__ __forceinline__ void store_tile(const u64 *lds, int lane, u64 *base, 
       if (r < rows_live && c < m) {
         const u64x2 v = *reinterpret_cast<const u64x2 *>(lds + r * S + c);
         u64 *dst = base + (u64)r * ld + c;
-        if (c + 1 < m) nt_store(reinterpret_cast<u64x2 *>(dst), v);
-        else nt_store(dst, v.x);
+        if (c + 1 < m) out_store(reinterpret_cast<u64x2 *>(dst), v);
+        else out_store(dst, v.x);
       }
     }
   } else {
@@ -207,7 +214,7 @@ __device__ __forceinline__ void store_tile(const u64 *lds, int lane, u64 *base, 
     for (int q = 0; q < T; q++) {
       const int r = q * RPI + lane / LPR;
       const int c = lane % LPR;
-      if (r < rows_live && c < m) nt_store(base + (u64)r * ld + c, lds[r * S + c]);
+      if (r < rows_live && c < m) out_store(base + (u64)r * ld + c, lds[r * S + c]);
     }
   }
 }
@@ -217,18 +224,29 @@ __global__ __launch_bounds__(kBlock) void k_generate(GenArgs a) {
   constexpr int K = Params<V>::k;
   __shared__ __attribute__((aligned(16))) u64 lds_all[(kBlock / kWave) * TileGeom<T>::kWaveLds];
   const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
-  const u64 row0 = ((u64)blockIdx.x * (kBlock / kWave) + wave) * kWave;
+  const u64 g = (u64)blockIdx.x * (kBlock / kWave) + wave;  // stream group
+  const u64 row0 = g * kWave;
   if (row0 >= a.S) return;  // uniform per wave
   const u64 i = row0 + lane;
   const bool live = i < a.S;
+  // slot boundaries of this group (uniform per wave)
+  const u64 d = g % a.D;
+  const u64 delta = d * (a.C / a.D);
   const u64 j = blockIdx.y;
-  const u64 t_begin = j * a.C;
-  const u64 cnt = (a.n - t_begin < a.C) ? a.n - t_begin : a.C;
+  auto bound = [&](u64 jj) -> u64 {
+    if (jj == 0) return 0;
+    if (jj >= a.nslots) return a.n;
+    const u64 p = jj * a.C - delta;
+    return p < a.n ? p : a.n;
+  };
+  const u64 t_begin = bound(j), t_end = bound(j + 1);
+  if (t_begin >= t_end) return;  // empty slot
+  const u64 cnt = t_end - t_begin;
 
   u64 s[K];
 #pragma unroll
   for (int w = 0; w < K; w++) s[w] = live ? a.state_in[(u64)w * a.S + i] : 0;
-  if (j > 0) jump_uniform<V>(s, a.chunk_polys + j * 16);
+  if (j > 0) jump_uniform<V>(s, a.slot_polys + (d * kMaxSlots + j) * 16);
 
   u64 *lds = lds_all + wave * TileGeom<T>::kWaveLds;
   u64 *myrow = lds + lane * TileGeom<T>::kStride;
@@ -244,7 +262,7 @@ __global__ __launch_bounds__(kBlock) void k_generate(GenArgs a) {
     wave_sync();
   }
   if constexpr (K == 16) rotate_to_logical<V>(s, ph);
-  if (j + 1 == a.nchunks && live) {
+  if (t_end == a.n && live) {
 #pragma unroll
     for (int w = 0; w < K; w++) a.state_out[(u64)w * a.S + i] = s[w];
   }
@@ -297,7 +315,7 @@ __global__ __launch_bounds__(kBlock) void k_jump(u64 *__restrict__ state, u64 S,
 __global__ __launch_bounds__(kBlock) void k_write_ceiling(u64x2 *out, u64 n16) {
   const u64 stride = (u64)gridDim.x * kBlock;
   const u64x2 v = {0x0123456789abcdefull, 0xfedcba9876543210ull};
-  for (u64 i = (u64)blockIdx.x * kBlock + threadIdx.x; i < n16; i += stride) nt_store(out + i, v);
+  for (u64 i = (u64)blockIdx.x * kBlock + threadIdx.x; i < n16; i += stride) out_store(out + i, v);
 }
 
 __global__ __launch_bounds__(kBlock) void k_copy(u64x2 *dst, const u64x2 *src, u64 n16) {
@@ -310,8 +328,10 @@ __global__ __launch_bounds__(kBlock) void k_copy(u64x2 *dst, const u64x2 *src, u
 template <int V, int KIND, int T>
 static hipError_t gen_t(const GenArgs &a, hipStream_t st) {
   const u64 waves = (a.S + kWave - 1) / kWave;
-  dim3 grid((unsigned)((waves + (kBlock / kWave) - 1) / (kBlock / kWave)), (unsigned)a.nchunks);
-  const bool a16 = ((uintptr_t)a.out % 16 == 0) && (a.ld % 2 == 0) && (a.C % 2 == 0);
+  dim3 grid((unsigned)((waves + (kBlock / kWave) - 1) / (kBlock / kWave)), (unsigned)a.nslots);
+  // slot starts are multiples of C/D (even), so rows start 16-byte aligned
+  // when the buffer and the row stride are
+  const bool a16 = ((uintptr_t)a.out % 16 == 0) && (a.ld % 2 == 0) && ((a.C / a.D) % 2 == 0);
   if (a16) hipLaunchKernelGGL((k_generate<V, KIND, T, true>), grid, dim3(kBlock), 0, st, a);
   else hipLaunchKernelGGL((k_generate<V, KIND, T, false>), grid, dim3(kBlock), 0, st, a);
   return hipGetLastError();

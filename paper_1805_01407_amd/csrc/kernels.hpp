@@ -10,6 +10,8 @@ constexpr int kBlock = 256;      // 4 waves per workgroup, each wave independent
 constexpr int kTabRadix = 1024;  // entries per positioning table level
 constexpr int kMaxLevels = 4;    // up to 2^40 streams
 constexpr int kMaxChunks = 16;   // chunks per stream in one generate launch
+constexpr int kMaxSkew = 16;     // skew classes of chunk boundaries
+constexpr int kMaxSlots = kMaxChunks + 1;
 
 // A polynomial of degree < 1024 passed by value (jump by one uniform distance).
 struct UPoly {
@@ -17,19 +19,27 @@ struct UPoly {
 };
 
 // Generation of n outputs per stream for S streams whose states are stored
-// word-major (word w of stream i at state[w*S + i]).  Each stream may be split
-// into chunks of C outputs; chunk j starts from the stream state jumped by
-// j*C steps (chunk_polys[j] = x^(jC) mod p, 16 words per entry).
+// word-major (word w of stream i at state[w*S + i]).
+//
+// Each stream may be split into slots that start from the stream state jumped
+// ahead, so that short, wide workloads still fill the GPU.  Streams are taken
+// 64 at a time (one wave, "group" g); group g has skew class d = g mod D and
+// offset delta_d = d*C/D, and slot j covers outputs [b_j, b_{j+1}) with
+// b_0 = 0, b_j = min(n, j*C - delta_d) for 0 < j < nslots and b_nslots = n.
+// Staggering the boundaries keeps concurrent waves off the same low address
+// bits when the row stride is a power of two.  The start polynomial of slot
+// j > 0 is x^(j*C - delta_d) mod p, at slot_polys[(d*kMaxSlots + j)*16].
 struct GenArgs {
   const uint64_t *state_in;
   uint64_t *state_out;
   uint64_t S;
   uint64_t n;
   uint64_t C;
-  uint64_t nchunks;
+  uint64_t nslots;
+  uint64_t D;
   void *out;
   uint64_t ld;
-  const uint64_t *chunk_polys;
+  const uint64_t *slot_polys;
 };
 
 struct GenConfig {

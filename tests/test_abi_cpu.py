@@ -100,7 +100,9 @@ def test_tuning_validation(P):
         P.slrng_set_tuning("xoshiro256**", 0, 24, 1024, 1024)
     with pytest.raises(P.SlrngError):
         P.slrng_set_tuning("xoshiro256**", 2, 16, 1024, 1024)
-    P.slrng_set_tuning("xoshiro256**", 0, t["tile"], t["target_waves"], t["min_chunk"])
+    with pytest.raises(P.SlrngError):
+        P.slrng_set_tuning("xoshiro256**", 0, 16, 1024, 1024, skew=3)
+    P.slrng_set_tuning("xoshiro256**", 0, t["tile"], t["target_waves"], t["min_chunk"], t["skew"])
 
 
 def test_invalid_arguments_return_einval(P):

@@ -108,16 +108,17 @@ def test_zero_length_is_noop(P):
 
 @pytest.mark.parametrize("name", ["xoshiro256**", "xoroshiro1024**", "xoroshiro128++", "xoshiro512+"])
 def test_chunk_split_matches_unsplit(P, name):
-    """Force the stream-splitting path (chunks jumped by multiples of C)."""
-    import torch
+    """Force the stream-splitting path (slots jumped ahead, with and without
+    staggered boundaries): the values never depend on the launch shape."""
     t = P.slrng_get_tuning(name)
     try:
-        for tile in (16, 32):
-            P.slrng_set_tuning(name, 0, tile, 1 << 16, 64)
-            check_generate(P, name, 21, 96, 3000)
+        for tile, skew in ((16, 1), (32, 1), (16, 4), (32, 16)):
+            P.slrng_set_tuning(name, 0, tile, 1 << 16, 64, skew)
+            check_generate(P, name, 21, 300, 3001)
             check_generate(P, name, 22, 3, 100)
+            check_generate(P, name, 23, 64, 1)
     finally:
-        P.slrng_set_tuning(name, 0, t["tile"], t["target_waves"], t["min_chunk"])
+        P.slrng_set_tuning(name, 0, t["tile"], t["target_waves"], t["min_chunk"], t["skew"])
 
 
 def test_split_calls_equal_one_call(P):
