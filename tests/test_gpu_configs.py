@@ -1,0 +1,119 @@
+"""GPU parity at the full sizes of the benchmark configurations, in the launch
+configuration bench.py times (default tuning), bit for bit against the oracle.
+
+* sweep: 65,536 streams x 65,536 outputs (32 GiB per kind) — xoshiro256**
+  compared in full (uint64 and doubles); xoroshiro1024** and xoroshiro128+ on
+  sampled rows plus every final state;
+* jump-ahead: 1,048,576 xoshiro256++ streams positioned by the jump chain,
+  then long-jumped once: all states compared, then 1,024 outputs per stream
+  (8 GiB) compared in full.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def P():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1805_01407_amd as P
+    P.lib()
+    return P
+
+
+def announce(*a):
+    print("[case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+def compare_blocks(buf, st0, g, N, kind, block=2048):
+    """Compare a device [S, N] buffer with the oracle, block of rows at a time."""
+    S = st0.shape[0]
+    for r0 in range(0, S, block):
+        r1 = min(S, r0 + block)
+        got = buf[r0:r1].cpu().numpy().view(np.uint64)
+        exp, _ = O.generate_many(g, st0[r0:r1], N, kind="u64", nthreads=16)
+        if kind == 1:
+            exp = ((exp >> np.uint64(11)).astype(np.float64) * 2.0**-53).view(np.uint64)
+        if not np.array_equal(got, exp):
+            bad = np.argwhere(got != exp)[0]
+            raise AssertionError(f"rows {r0}..{r1}: first mismatch at {bad}")
+
+
+def test_sweep_full_size_xoshiro256ss_complete(P):
+    import torch
+    name, seed, S, N = "xoshiro256**", 3, 65536, 65536
+    g = O.GEN64[name]
+    announce("sweep full", name, S, N)
+    st0 = O.stream_chain(g, seed, S)
+    buf = torch.empty((S, N), dtype=torch.int64, device="cuda")
+    with P.Streams(name, seed, S) as h:
+        assert np.array_equal(h.get_state(), st0)
+        P.slrng_generate(h.h, P.SLRNG_U64, N, buf.data_ptr(), N, 0)
+        torch.cuda.synchronize()
+        fin = h.get_state()
+        compare_blocks(buf, st0, g, N, 0)
+        h.seed(seed)
+        P.slrng_generate(h.h, P.SLRNG_F64, N, buf.data_ptr(), N, 0)
+        torch.cuda.synchronize()
+        compare_blocks(buf, st0, g, N, 1)
+    exp_fin = O.jump_many(g, st0, N, nthreads=16)
+    assert np.array_equal(fin, exp_fin)
+    del buf
+    torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("name", ["xoroshiro1024**", "xoroshiro128+"])
+def test_sweep_full_size_sampled_rows(P, name):
+    import torch
+    seed, S, N = 5, 65536, 65536
+    g = O.GEN64[name]
+    announce("sweep sampled", name, S, N)
+    st0 = O.stream_chain(g, seed, S)
+    rows = sorted({0, 1, 63, 64, 65, 1023, 1024, 4095, 32767, 65472, 65535} |
+                  set(np.random.default_rng(0).integers(0, S, 8).tolist()))
+    buf = torch.empty((S, N), dtype=torch.int64, device="cuda")
+    with P.Streams(name, seed, S) as h:
+        assert np.array_equal(h.get_state(), st0)
+        for kind in (P.SLRNG_U64, P.SLRNG_F64):
+            h.seed(seed)
+            P.slrng_generate(h.h, kind, N, buf.data_ptr(), N, 0)
+            torch.cuda.synchronize()
+            idx = torch.tensor(rows, device="cuda")
+            got = buf.index_select(0, idx).cpu().numpy().view(np.uint64)
+            exp, _ = O.generate_many(g, st0[rows], N, kind="u64", nthreads=16)
+            if kind == P.SLRNG_F64:
+                exp = ((exp >> np.uint64(11)).astype(np.float64) * 2.0**-53).view(np.uint64)
+            assert np.array_equal(got, exp)
+        fin = h.get_state()
+    assert np.array_equal(fin, O.jump_many(g, st0, N, nthreads=16))
+    del buf
+    torch.cuda.empty_cache()
+
+
+def test_jump_ahead_at_scale_1m_xoshiro256pp(P):
+    import torch
+    name, seed, S, N = "xoshiro256++", 42, 1 << 20, 1024
+    g = O.GEN64[name]
+    announce("jump ahead", name, S)
+    chain = O.stream_chain(g, seed, S)
+    exp = O.jump_many(g, chain, O.jump_distance(g, "long"), nthreads=16)
+    buf = torch.empty((S, N), dtype=torch.int64, device="cuda")
+    with P.Streams(name, seed, S) as h:
+        assert np.array_equal(h.get_state(), chain)
+        h.jump(P.SLRNG_LONG_JUMP)
+        assert np.array_equal(h.get_state(), exp)
+        P.slrng_generate(h.h, P.SLRNG_U64, N, buf.data_ptr(), N, 0)
+        torch.cuda.synchronize()
+        compare_blocks(buf, exp, g, N, 0, block=1 << 17)
+        fin = h.get_state()
+    assert np.array_equal(fin, O.jump_many(g, exp, N, nthreads=16))
+    del buf
+    torch.cuda.empty_cache()
