@@ -188,6 +188,70 @@ typedef struct slrng_tuning {
 int slrng_get_tuning(int variant, int kind, slrng_tuning *out);
 int slrng_set_tuning(int variant, int kind, const slrng_tuning *t);
 
+/* ---------------------------------------------------------------- batches
+ *
+ * Many independent requests of uneven lengths and mixed generators in one
+ * launch.  Request r asks for n outputs of generator `variant`, as `kind`,
+ * starting `start` steps after the origin state (the SplitMix64 fill of
+ * `seed`, as in slrng_streams_create): dev_out[t] = output (start + t) of
+ * that stream, t < n.  dev_out: device memory, 8-byte aligned, n elements.
+ * Requests are independent (they may overlap in stream and position, not in
+ * output memory).  Every request's values are the same in any batch, alone or
+ * in any mix, in every mode.
+ *
+ * slrng_batch_plan: plans a batch once (host descriptors, jump polynomials,
+ * device descriptor upload; with SLRNG_BATCH_GRAPH also captures and
+ * instantiates a hipGraph).  The request array is not kept.
+ * slrng_batch_launch: enqueues the planned work on `stream` (asynchronous;
+ * replays the graph in SLRNG_BATCH_GRAPH mode).  Launches of one batch must
+ * not overlap in time (they share a claim counter).
+ * slrng_batch_run: plan + launch + synchronize + destroy.
+ * slrng_batch_info: tiles, lane-chunks and outputs of a plan.
+ * Errors: EINVAL for a bad variant, kind, mode, tile, null or misaligned
+ * output; ERANGE for more than 2^24 requests or a request too long to chunk.
+ *
+ * Options (slrng_batch_default_opts fills the defaults):
+ *  mode          SLRNG_BATCH_GRAPH: one persistent kernel over all tiles,
+ *                captured into a hipGraph at plan time;
+ *                SLRNG_BATCH_PERSISTENT: the same kernel launched directly;
+ *                SLRNG_BATCH_PLAIN: one launch of the same kernel per request
+ *                (the unbatched comparison form).
+ *  tile          outputs per lane staged through LDS per round (16 or 32);
+ *  waves_per_cu  persistent grid size (0 = default);
+ *  chunk[v]      lane-chunk length for variant v (0 = default): a request is
+ *                cut into chunks of this many outputs, each on one lane,
+ *                started by a jump of j*chunk steps. */
+typedef struct slrng_request {
+  int32_t variant;
+  int32_t kind;
+  uint64_t seed;
+  uint64_t start;
+  uint64_t n;
+  void *dev_out;
+} slrng_request;
+
+enum { SLRNG_BATCH_GRAPH = 0, SLRNG_BATCH_PERSISTENT = 1, SLRNG_BATCH_PLAIN = 2 };
+
+typedef struct slrng_batch_opts {
+  int32_t mode;
+  int32_t tile;
+  int32_t waves_per_cu;
+  int32_t reserved;
+  uint64_t chunk[SLRNG_NUM_VARIANTS];
+} slrng_batch_opts;
+
+typedef struct slrng_batch slrng_batch; /* opaque planned batch */
+
+int slrng_batch_default_opts(slrng_batch_opts *opts);
+int slrng_batch_plan(const slrng_request *reqs, size_t n_reqs, const slrng_batch_opts *opts,
+                     slrng_batch **out);
+int slrng_batch_launch(slrng_batch *b, hipStream_t stream);
+int slrng_batch_info(const slrng_batch *b, uint64_t *n_tiles, uint64_t *n_lanes,
+                     uint64_t *total_outputs);
+int slrng_batch_destroy(slrng_batch *b);
+int slrng_batch_run(const slrng_request *reqs, size_t n_reqs, const slrng_batch_opts *opts,
+                    hipStream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

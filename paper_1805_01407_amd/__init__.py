@@ -18,4 +18,7 @@ from .binding import (  # noqa: F401
     slrng_get_state, slrng_set_state, slrng_streams_destroy,
     slrng_get_tuning, slrng_set_tuning, slrng_calib_write, slrng_calib_copy,
     SLRNG_U64, SLRNG_F64, SLRNG_JUMP, SLRNG_LONG_JUMP,
+    SLRNG_BATCH_GRAPH, SLRNG_BATCH_PERSISTENT, SLRNG_BATCH_PLAIN, REQUEST_DTYPE, make_requests,
+    slrng_batch_default_opts, slrng_batch_plan, slrng_batch_launch, slrng_batch_info,
+    slrng_batch_destroy, slrng_batch_run,
 )

@@ -46,6 +46,20 @@ class _Tuning(ctypes.Structure):
                 ("min_chunk", ctypes.c_uint64)]
 
 
+NUM_VARIANTS = 14
+SLRNG_BATCH_GRAPH, SLRNG_BATCH_PERSISTENT, SLRNG_BATCH_PLAIN = 0, 1, 2
+
+# slrng_request as a numpy record (40 bytes, the C layout)
+REQUEST_DTYPE = np.dtype([("variant", "<i4"), ("kind", "<i4"), ("seed", "<u8"), ("start", "<u8"),
+                          ("n", "<u8"), ("dev_out", "<u8")])
+
+
+class _BatchOpts(ctypes.Structure):
+    _fields_ = [("mode", ctypes.c_int32), ("tile", ctypes.c_int32),
+                ("waves_per_cu", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("chunk", ctypes.c_uint64 * NUM_VARIANTS)]
+
+
 _lib = None
 
 
@@ -85,6 +99,12 @@ def lib():
         "slrng_streams_destroy": ([vp], i32),
         "slrng_get_tuning": ([i32, i32, ctypes.POINTER(_Tuning)], i32),
         "slrng_set_tuning": ([i32, i32, ctypes.POINTER(_Tuning)], i32),
+        "slrng_batch_default_opts": ([ctypes.POINTER(_BatchOpts)], i32),
+        "slrng_batch_plan": ([vp, ctypes.c_size_t, ctypes.POINTER(_BatchOpts), ctypes.POINTER(vp)], i32),
+        "slrng_batch_launch": ([vp, vp], i32),
+        "slrng_batch_info": ([vp, u64p, u64p, u64p], i32),
+        "slrng_batch_destroy": ([vp], i32),
+        "slrng_batch_run": ([vp, ctypes.c_size_t, ctypes.POINTER(_BatchOpts), vp], i32),
         "slrng_calib_write": ([vp, u64, vp], i32),
         "slrng_calib_copy": ([vp, vp, u64, vp], i32),
     }
@@ -251,6 +271,66 @@ def slrng_calib_write(dev_out: int, nbytes: int, stream=None) -> None:
 
 def slrng_calib_copy(dev_dst: int, dev_src: int, nbytes: int, stream=None) -> None:
     _check(lib().slrng_calib_copy(dev_dst, dev_src, nbytes, _stream(stream)), "slrng_calib_copy")
+
+
+def slrng_batch_default_opts(mode: int = SLRNG_BATCH_GRAPH, tile: int | None = None,
+                             waves_per_cu: int | None = None, chunk: dict | None = None):
+    """Default batch options, with optional overrides (chunk: {variant: length})."""
+    o = _BatchOpts()
+    _check(lib().slrng_batch_default_opts(ctypes.byref(o)), "slrng_batch_default_opts")
+    o.mode = mode
+    if tile is not None:
+        o.tile = tile
+    if waves_per_cu is not None:
+        o.waves_per_cu = waves_per_cu
+    for v, c in (chunk or {}).items():
+        o.chunk[_variant(v)] = c
+    return o
+
+
+def make_requests(variant, kind, seed, start, n, dev_out) -> np.ndarray:
+    """Pack request fields (scalars or arrays) into slrng_request records."""
+    cols = np.broadcast_arrays(np.asarray(variant), np.asarray(kind), np.asarray(seed, dtype=np.uint64),
+                               np.asarray(start, dtype=np.uint64), np.asarray(n, dtype=np.uint64),
+                               np.asarray(dev_out, dtype=np.uint64))
+    r = np.zeros(cols[0].shape, dtype=REQUEST_DTYPE).reshape(-1)
+    for name, c in zip(REQUEST_DTYPE.names, cols):
+        r[name] = c.reshape(-1)
+    return r
+
+
+def _reqs(reqs: np.ndarray):
+    reqs = np.ascontiguousarray(reqs, dtype=REQUEST_DTYPE)
+    return reqs, reqs.ctypes.data_as(ctypes.c_void_p), reqs.size
+
+
+def slrng_batch_plan(reqs: np.ndarray, opts=None) -> int:
+    reqs, ptr, n = _reqs(reqs)
+    b = ctypes.c_void_p()
+    _check(lib().slrng_batch_plan(ptr, n, ctypes.byref(opts) if opts is not None else None,
+                                  ctypes.byref(b)), "slrng_batch_plan")
+    return b.value
+
+
+def slrng_batch_launch(b: int, stream=None) -> None:
+    _check(lib().slrng_batch_launch(b, _stream(stream)), "slrng_batch_launch")
+
+
+def slrng_batch_info(b: int) -> dict:
+    t, l, o = ctypes.c_uint64(), ctypes.c_uint64(), ctypes.c_uint64()
+    _check(lib().slrng_batch_info(b, ctypes.byref(t), ctypes.byref(l), ctypes.byref(o)),
+           "slrng_batch_info")
+    return {"tiles": t.value, "lanes": l.value, "outputs": o.value}
+
+
+def slrng_batch_destroy(b: int) -> None:
+    _check(lib().slrng_batch_destroy(b), "slrng_batch_destroy")
+
+
+def slrng_batch_run(reqs: np.ndarray, opts=None, stream=None) -> None:
+    reqs, ptr, n = _reqs(reqs)
+    _check(lib().slrng_batch_run(ptr, n, ctypes.byref(opts) if opts is not None else None,
+                                 _stream(stream)), "slrng_batch_run")
 
 
 # ---------------------------------------------------------------- object wrapper

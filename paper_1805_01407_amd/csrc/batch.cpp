@@ -1,0 +1,440 @@
+// Batched generation: host planner and C ABI (slrng_batch_*).
+//
+// Planning (host): validate requests; per request with start > 0 compute the
+// start polynomial x^start mod p (request state kernel); cut requests into
+// lane-chunks; group by (variant, kind); sort by length; pack into tiles of
+// 64; order tiles heaviest first; upload descriptors.  Launch: either one
+// persistent kernel over all tiles (optionally captured once into a hipGraph
+// and replayed), or — the plain form used for comparison — one launch of the
+// same kernel per request.
+#include <hip/hip_runtime_api.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <algorithm>
+#include <map>
+#include <mutex>
+#include <new>
+#include <tuple>
+#include <vector>
+
+#include "../../include/slrng.h"
+#include "api_internal.hpp"
+#include "batch.hpp"
+#include "engines.hpp"
+#include "f2poly.hpp"
+#include "kernels.hpp"
+
+using namespace slrng;
+
+#define HIPCHK(call)                              \
+  do {                                            \
+    hipError_t e_ = (call);                       \
+    if (e_ != hipSuccess) return hip_fail(e_);    \
+  } while (0)
+
+namespace {
+
+constexpr uint32_t kMaxTable = 8192;  // chunk-table entries per variant
+
+// Chunk tables x^(j C) mod p for j < entries, word-major, per (device, engine, C).
+struct ChunkTable {
+  uint64_t *dev = nullptr;
+  uint32_t n = 0;
+};
+std::mutex g_ct_mu;
+std::map<std::tuple<int, int, uint64_t>, ChunkTable> g_ct;
+
+int chunk_table(int device, int engine, uint64_t C, uint32_t need, ChunkTable *out) {
+  std::lock_guard<std::mutex> g(g_ct_mu);
+  ChunkTable &t = g_ct[std::make_tuple(device, engine, C)];
+  if (t.n >= need) {
+    *out = t;
+    return SLRNG_OK;
+  }
+  uint32_t n = std::max<uint32_t>(need, 64);
+  n = std::min<uint32_t>(std::max<uint32_t>(n, t.n * 2), kMaxTable);
+  const Field &f = engine_field(engine);
+  const int W = f.n / 64;
+  Poly step, cur;
+  uint64_t J[1] = {C};
+  f.xpow(J, 1, step);
+  cur.clear();
+  cur.w[0] = 1;
+  std::vector<uint64_t> h((size_t)W * n);
+  for (uint32_t j = 0; j < n; j++) {
+    for (int w = 0; w < W; w++) h[(size_t)w * n + j] = cur.w[w];
+    Poly nx;
+    f.mulmod(cur, step, nx);
+    cur = nx;
+  }
+  uint64_t *d = nullptr;
+  HIPCHK(hipMalloc(&d, h.size() * 8));
+  HIPCHK(hipMemcpy(d, h.data(), h.size() * 8, hipMemcpyHostToDevice));
+  // a smaller table may still be in use by queued work: it is kept
+  t.dev = d;
+  t.n = n;
+  *out = t;
+  return SLRNG_OK;
+}
+
+struct Lane {
+  LaneDesc d;
+  int variant, kind;
+};
+
+}  // namespace
+
+// ---------------------------------------------------------------- the batch object
+
+struct slrng_batch {
+  int device = 0;
+  slrng_batch_opts opts;
+  uint64_t n_requests = 0, total_outputs = 0;
+  // one plan per launch unit: a single unit for the batched forms, one per
+  // request for the plain form
+  struct Unit {
+    uint32_t tile0 = 0, ntiles = 0;
+  };
+  std::vector<Unit> units;
+  uint32_t ntiles = 0, nlanes = 0;
+  TileDesc *d_tiles = nullptr;
+  LaneDesc *d_lanes = nullptr;
+  uint64_t *d_req_state = nullptr;
+  uint64_t *d_req_seed = nullptr, *d_req_poly = nullptr;
+  uint32_t *d_req_slot = nullptr;
+  unsigned *d_counter = nullptr;  // one counter per unit
+  std::vector<std::pair<int, ReqArgs>> req_launches;
+  BatchArgs args;
+  unsigned blocks = 0;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+static void free_batch(slrng_batch *b) {
+  if (!b) return;
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  void *ptrs[] = {b->d_tiles, b->d_lanes, b->d_req_state, b->d_req_seed, b->d_req_poly,
+                  b->d_req_slot, b->d_counter};
+  for (void *p : ptrs)
+    if (p) (void)hipFree(p);
+  delete b;
+}
+
+extern "C" int slrng_batch_default_opts(slrng_batch_opts *o) {
+  if (!o) return SLRNG_EINVAL;
+  memset(o, 0, sizeof(*o));
+  o->mode = SLRNG_BATCH_GRAPH;
+  o->tile = 16;
+  o->waves_per_cu = 12;
+  for (int v = 0; v < SLRNG_NUM_VARIANTS; v++) o->chunk[v] = (v == 9 || v == 10 || v == 11 || v == 13) ? 65536 : 16384;
+  return SLRNG_OK;
+}
+
+static int enqueue_unit(slrng_batch *b, const slrng_batch::Unit &u, unsigned *counter,
+                        hipStream_t st) {
+  if (u.ntiles == 0) return SLRNG_OK;
+  BatchArgs a = b->args;
+  a.tiles = b->d_tiles + u.tile0;
+  a.ntiles = u.ntiles;
+  a.counter = counter;
+  hipError_t e = launch_batch_reset(counter, st);
+  if (e != hipSuccess) return hip_fail(e);
+  const unsigned blocks = std::min<unsigned>(b->blocks, (u.ntiles + 3) / 4);
+  e = launch_batch(a, b->opts.tile, blocks, st);
+  return e == hipSuccess ? SLRNG_OK : hip_fail(e);
+}
+
+// Enqueue the whole batch on `st` (no graph).
+static int enqueue_all(slrng_batch *b, hipStream_t st) {
+  for (auto &rl : b->req_launches) {
+    hipError_t e = launch_req_state(rl.first, rl.second, st);
+    if (e != hipSuccess) return hip_fail(e);
+  }
+  for (size_t i = 0; i < b->units.size(); i++) {
+    int rc = enqueue_unit(b, b->units[i], b->d_counter + (b->units.size() > 1 ? i : 0), st);
+    if (rc) return rc;
+  }
+  return SLRNG_OK;
+}
+
+extern "C" int slrng_batch_plan(const slrng_request *reqs, size_t n_reqs,
+                                const slrng_batch_opts *opts, slrng_batch **out) {
+  if (!out || (n_reqs && !reqs)) return SLRNG_EINVAL;
+  *out = nullptr;
+  slrng_batch_opts o;
+  if (opts) o = *opts;
+  else slrng_batch_default_opts(&o);
+  if (o.mode != SLRNG_BATCH_GRAPH && o.mode != SLRNG_BATCH_PERSISTENT && o.mode != SLRNG_BATCH_PLAIN)
+    return SLRNG_EINVAL;
+  if (o.tile != 16 && o.tile != 32) return SLRNG_EINVAL;
+  if (o.waves_per_cu < 0 || o.waves_per_cu > 64) return SLRNG_EINVAL;
+  if (n_reqs > (1u << 24)) return SLRNG_ERANGE;
+  for (size_t r = 0; r < n_reqs; r++) {
+    const slrng_request &q = reqs[r];
+    if (!valid_variant(q.variant) || (q.kind != SLRNG_U64 && q.kind != SLRNG_F64)) return SLRNG_EINVAL;
+    if (q.n && (!q.dev_out || ((uintptr_t)q.dev_out & 7))) return SLRNG_EINVAL;
+    if (q.n > UINT64_MAX / 8) return SLRNG_ERANGE;
+  }
+  slrng_batch *b = new (std::nothrow) slrng_batch();
+  if (!b) return SLRNG_ENOMEM;
+  b->opts = o;
+  b->n_requests = n_reqs;
+  int rc = SLRNG_OK;
+  hipError_t e = hipGetDevice(&b->device);
+  if (e != hipSuccess) {
+    free_batch(b);
+    return hip_fail(e);
+  }
+  // chunk length per variant: the option value, rounded up to the tile and
+  // raised if a request would need more than kMaxTable chunks
+  uint64_t C[kNumVariants];
+  uint64_t maxn[kNumVariants] = {0};
+  for (size_t r = 0; r < n_reqs; r++) maxn[reqs[r].variant] = std::max(maxn[reqs[r].variant], reqs[r].n);
+  for (int v = 0; v < kNumVariants; v++) {
+    uint64_t c = o.chunk[v] ? o.chunk[v] : 16384;
+    if (c > 0xffffffffull) c = 0xffffffffull & ~(uint64_t)63;
+    c = (c + o.tile - 1) / o.tile * o.tile;
+    const uint64_t need = (maxn[v] + kMaxTable - 1) / kMaxTable;
+    if (c < need) c = (need + o.tile - 1) / o.tile * o.tile;
+    if (c > 0xffffffffull) {
+      free_batch(b);
+      return SLRNG_ERANGE;
+    }
+    C[v] = c;
+  }
+  // requests with a start offset: request-state slots and start polynomials
+  std::vector<uint32_t> req_slot(n_reqs, kNoReqState);
+  std::vector<std::vector<uint32_t>> by_var(kNumVariants);
+  uint32_t nslots = 0;
+  for (size_t r = 0; r < n_reqs; r++)
+    if (reqs[r].start && reqs[r].n) {
+      req_slot[r] = nslots++;
+      by_var[reqs[r].variant].push_back((uint32_t)r);
+    }
+  // lanes
+  std::vector<Lane> lanes;
+  uint32_t tab_need[kNumVariants] = {0};
+  for (size_t r = 0; r < n_reqs; r++) {
+    const slrng_request &q = reqs[r];
+    if (!q.n) continue;
+    b->total_outputs += q.n;
+    const uint64_t c = C[q.variant];
+    const uint64_t nch = (q.n + c - 1) / c;
+    tab_need[q.variant] = std::max<uint32_t>(tab_need[q.variant], (uint32_t)nch);
+    for (uint64_t j = 0; j < nch; j++) {
+      Lane l;
+      l.variant = q.variant;
+      l.kind = q.kind;
+      l.d.seed = q.seed;
+      l.d.out = (uint64_t)(uintptr_t)q.dev_out + j * c * 8;
+      l.d.len = (uint32_t)std::min<uint64_t>(c, q.n - j * c);
+      l.d.jidx = (uint32_t)j;
+      l.d.req = req_slot[r];
+      l.d.pad = (uint32_t)r;  // request index, used to split the plain form
+      lanes.push_back(l);
+    }
+  }
+  // tables
+  for (int v = 0; v < kNumVariants; v++) {
+    b->args.tab[v] = nullptr;
+    b->args.tab_n[v] = 0;
+    if (!tab_need[v]) continue;
+    ChunkTable t;
+    rc = chunk_table(b->device, variant_engine(v), C[v], tab_need[v], &t);
+    if (rc) {
+      free_batch(b);
+      return rc;
+    }
+    b->args.tab[v] = t.dev;
+    b->args.tab_n[v] = t.n;
+  }
+  // tiles: per unit (the whole batch, or one request), per (variant, kind),
+  // lanes sorted by length, 64 per tile; tiles heaviest first within a unit
+  const bool plain = o.mode == SLRNG_BATCH_PLAIN;
+  std::vector<LaneDesc> h_lanes;
+  std::vector<TileDesc> h_tiles;
+  h_lanes.reserve(lanes.size());
+  auto key_of = [&](const Lane &l) -> std::tuple<uint64_t, int, int> {
+    return std::make_tuple(plain ? (uint64_t)l.d.pad : 0ull, l.variant, l.kind);
+  };
+  std::stable_sort(lanes.begin(), lanes.end(), [&](const Lane &x, const Lane &y) {
+    auto kx = key_of(x), ky = key_of(y);
+    if (kx != ky) return kx < ky;
+    return x.d.len > y.d.len;
+  });
+  // relative cost of one output per variant (engine and scrambler work)
+  auto cost = [](int v) -> uint64_t { return v >= 6 && v <= 8 ? 3 : (v >= 9 ? 2 : 2); };
+  size_t i = 0;
+  while (i < lanes.size()) {
+    const auto unit_key = std::get<0>(key_of(lanes[i]));
+    slrng_batch::Unit u;
+    u.tile0 = (uint32_t)h_tiles.size();
+    std::vector<std::pair<uint64_t, TileDesc>> tiles;
+    while (i < lanes.size() && std::get<0>(key_of(lanes[i])) == unit_key) {
+      const auto k = key_of(lanes[i]);
+      size_t e2 = i;
+      while (e2 < lanes.size() && key_of(lanes[e2]) == k) e2++;
+      for (size_t s = i; s < e2; s += kWave) {
+        const size_t cnt = std::min<size_t>(kWave, e2 - s);
+        TileDesc td;
+        td.variant = (uint16_t)lanes[s].variant;
+        td.kind = (uint8_t)lanes[s].kind;
+        td.nlanes = (uint8_t)cnt;
+        td.max_len = lanes[s].d.len;  // sorted: the first is the longest
+        td.lane0 = (uint32_t)(h_lanes.size());
+        td.need_jump = 0;
+        for (size_t q = s; q < s + cnt; q++) {
+          LaneDesc d = lanes[q].d;
+          if (d.jidx) td.need_jump = 1;
+          d.pad = 0;
+          h_lanes.push_back(d);
+        }
+        tiles.push_back({(uint64_t)td.max_len * cost(td.variant), td});
+      }
+      i = e2;
+    }
+    std::stable_sort(tiles.begin(), tiles.end(),
+                     [](const std::pair<uint64_t, TileDesc> &x, const std::pair<uint64_t, TileDesc> &y) {
+                       return x.first > y.first;
+                     });
+    for (auto &t : tiles) h_tiles.push_back(t.second);
+    u.ntiles = (uint32_t)h_tiles.size() - u.tile0;
+    b->units.push_back(u);
+  }
+  if (b->units.empty()) b->units.push_back(slrng_batch::Unit());
+  b->ntiles = (uint32_t)h_tiles.size();
+  b->nlanes = (uint32_t)h_lanes.size();
+  // device buffers
+  auto upload = [&](void **dst, const void *src, size_t bytes) -> int {
+    if (!bytes) return SLRNG_OK;
+    hipError_t e3 = hipMalloc(dst, bytes);
+    if (e3 != hipSuccess) return e3 == hipErrorOutOfMemory ? SLRNG_ENOMEM : hip_fail(e3);
+    e3 = hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice);
+    return e3 == hipSuccess ? SLRNG_OK : hip_fail(e3);
+  };
+  rc = upload((void **)&b->d_tiles, h_tiles.data(), h_tiles.size() * sizeof(TileDesc));
+  if (!rc) rc = upload((void **)&b->d_lanes, h_lanes.data(), h_lanes.size() * sizeof(LaneDesc));
+  if (!rc) {
+    std::vector<unsigned> zeros(b->units.size(), 0);
+    rc = upload((void **)&b->d_counter, zeros.data(), zeros.size() * sizeof(unsigned));
+  }
+  if (!rc && nslots) {
+    e = hipMalloc(&b->d_req_state, (size_t)nslots * 16 * 8);
+    if (e != hipSuccess) rc = hip_fail(e);
+    std::vector<uint64_t> seeds, polys;
+    std::vector<uint32_t> slots;
+    for (int v = 0; v < kNumVariants && !rc; v++) {
+      if (by_var[v].empty()) continue;
+      const Field &f = engine_field(variant_engine(v));
+      for (uint32_t r : by_var[v]) {
+        seeds.push_back(reqs[r].seed);
+        slots.push_back(req_slot[r]);
+        Poly pr;
+        uint64_t J[1] = {reqs[r].start};
+        f.xpow(J, 1, pr);
+        for (int w = 0; w < 16; w++) polys.push_back(pr.w[w]);
+      }
+    }
+    if (!rc) rc = upload((void **)&b->d_req_seed, seeds.data(), seeds.size() * 8);
+    if (!rc) rc = upload((void **)&b->d_req_poly, polys.data(), polys.size() * 8);
+    if (!rc) rc = upload((void **)&b->d_req_slot, slots.data(), slots.size() * 4);
+    uint32_t off = 0;
+    for (int v = 0; v < kNumVariants && !rc; v++) {
+      if (by_var[v].empty()) continue;
+      ReqArgs ra;
+      ra.seeds = b->d_req_seed + off;
+      ra.polys = b->d_req_poly + (size_t)off * 16;
+      ra.slot = b->d_req_slot + off;
+      ra.req_state = b->d_req_state;
+      ra.m = (uint32_t)by_var[v].size();
+      b->req_launches.push_back({v, ra});
+      off += ra.m;
+    }
+  }
+  if (rc) {
+    free_batch(b);
+    return rc;
+  }
+  b->args.tiles = b->d_tiles;
+  b->args.ntiles = b->ntiles;
+  b->args.pad = 0;
+  b->args.lanes = b->d_lanes;
+  b->args.req_state = b->d_req_state;
+  b->args.counter = b->d_counter;
+  int cus = 0;
+  e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, b->device);
+  if (e != hipSuccess) {
+    free_batch(b);
+    return hip_fail(e);
+  }
+  const int wpc = o.waves_per_cu ? o.waves_per_cu : 12;
+  b->blocks = (unsigned)std::max(1, cus * wpc / (kBlock / kWave));
+  // graph: capture the whole enqueue sequence once
+  if (o.mode == SLRNG_BATCH_GRAPH) {
+    hipStream_t cs = nullptr;
+    e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+      free_batch(b);
+      return hip_fail(e);
+    }
+    e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+      rc = enqueue_all(b, cs);
+      hipGraph_t g = nullptr;
+      hipError_t e2 = hipStreamEndCapture(cs, &g);
+      if (!rc && e2 != hipSuccess) rc = hip_fail(e2);
+      b->graph = g;
+      if (!rc) {
+        e2 = hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0);
+        if (e2 != hipSuccess) rc = hip_fail(e2);
+      }
+    } else {
+      rc = hip_fail(e);
+    }
+    (void)hipStreamDestroy(cs);
+    if (rc) {
+      free_batch(b);
+      return rc;
+    }
+  }
+  *out = b;
+  return SLRNG_OK;
+}
+
+extern "C" int slrng_batch_launch(slrng_batch *b, hipStream_t stream) {
+  if (!b) return SLRNG_EINVAL;
+  if (b->exec) {
+    hipError_t e = hipGraphLaunch(b->exec, stream);
+    return e == hipSuccess ? SLRNG_OK : hip_fail(e);
+  }
+  return enqueue_all(b, stream);
+}
+
+extern "C" int slrng_batch_info(const slrng_batch *b, uint64_t *n_tiles, uint64_t *n_lanes,
+                                uint64_t *total_outputs) {
+  if (!b) return SLRNG_EINVAL;
+  if (n_tiles) *n_tiles = b->ntiles;
+  if (n_lanes) *n_lanes = b->nlanes;
+  if (total_outputs) *total_outputs = b->total_outputs;
+  return SLRNG_OK;
+}
+
+extern "C" int slrng_batch_destroy(slrng_batch *b) {
+  if (!b) return SLRNG_EINVAL;
+  free_batch(b);
+  return SLRNG_OK;
+}
+
+extern "C" int slrng_batch_run(const slrng_request *reqs, size_t n_reqs, const slrng_batch_opts *opts,
+                               hipStream_t stream) {
+  slrng_batch *b = nullptr;
+  int rc = slrng_batch_plan(reqs, n_reqs, opts, &b);
+  if (rc) return rc;
+  rc = slrng_batch_launch(b, stream);
+  hipError_t e = hipStreamSynchronize(stream);
+  free_batch(b);
+  if (rc) return rc;
+  return e == hipSuccess ? SLRNG_OK : hip_fail(e);
+}

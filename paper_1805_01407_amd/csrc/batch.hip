@@ -1,0 +1,190 @@
+// Persistent batched generation kernel (see batch.hpp for the work split).
+//
+// Each wave repeatedly claims one tile (64 lane-chunks of one variant and
+// kind) from an atomic counter, switches on the tile's variant and kind (the
+// switch is uniform per wave: the tile index is read through readfirstlane, so
+// the branch is a scalar one), positions its lanes (SplitMix64 origin or a
+// precomputed request state, then one per-lane jump by the chunk offset), and
+// generates with the same LDS-staged tile and store code as k_generate, with a
+// destination pointer and a length per row.
+#include <hip/hip_runtime.h>
+
+#include "batch.hpp"
+#include "gen_device.hpp"
+
+namespace slrng {
+
+// Store a staged tile with per-row destinations and lengths: row r writes
+// outputs t0 + c for c < m and t0 + c < len[r].
+template <int T, bool A16>
+__device__ __forceinline__ void store_tile_rows(const u64 *lds, int lane, const u64 *rowptr,
+                                                const unsigned *rowlen, int nrows, unsigned t0,
+                                                int m) {
+  constexpr int S = TileGeom<T>::kStride;
+  if constexpr (A16) {
+    constexpr int LPR = T / 2;
+    constexpr int RPI = kWave / LPR;
+#pragma unroll
+    for (int q = 0; q < T / 2; q++) {
+      const int r = q * RPI + lane / LPR;
+      const int c = 2 * (lane % LPR);
+      if (r < nrows && c < m) {
+        const unsigned len = rowlen[r];
+        const unsigned col = t0 + (unsigned)c;
+        if (col < len) {
+          const u64x2 v = *reinterpret_cast<const u64x2 *>(lds + r * S + c);
+          u64 *dst = reinterpret_cast<u64 *>(rowptr[r]) + col;
+          if (col + 1 < len && c + 1 < m) out_store(reinterpret_cast<u64x2 *>(dst), v);
+          else out_store(dst, v.x);
+        }
+      }
+    }
+  } else {
+    constexpr int LPR = T;
+    constexpr int RPI = kWave / LPR;
+#pragma unroll
+    for (int q = 0; q < T; q++) {
+      const int r = q * RPI + lane / LPR;
+      const int c = lane % LPR;
+      if (r < nrows && c < m) {
+        const unsigned col = t0 + (unsigned)c;
+        if (col < rowlen[r]) out_store(reinterpret_cast<u64 *>(rowptr[r]) + col, lds[r * S + c]);
+      }
+    }
+  }
+}
+
+template <int V, int KIND, int T>
+__device__ __forceinline__ void batch_tile(const BatchArgs &a, const TileDesc &td, u64 *lds,
+                                           u64 *rowptr, unsigned *rowlen, int lane) {
+  constexpr int K = Params<V>::k;
+  const bool active = lane < (int)td.nlanes;
+  LaneDesc ld;
+  if (active) {
+    ld = a.lanes[td.lane0 + lane];
+  } else {
+    ld.seed = 0;
+    ld.out = 0;
+    ld.len = 0;
+    ld.jidx = 0;
+    ld.req = kNoReqState;
+    ld.pad = 0;
+  }
+  u64 s[K];
+  if (ld.req != kNoReqState) {
+#pragma unroll
+    for (int w = 0; w < K; w++) s[w] = a.req_state[(u64)ld.req * 16 + w];
+  } else {
+    splitmix64_fill<K>(ld.seed, s);
+  }
+  if (td.need_jump) {
+    const u64 *tab = a.tab[V];
+    const u64 tn = a.tab_n[V];
+    const u64 jj = ld.jidx;
+    jump_lane<V>(s, [&](int wi) { return tab[(u64)wi * tn + jj]; });
+  }
+  rowptr[lane] = ld.out;
+  rowlen[lane] = ld.len;
+  const bool a16 = __all((ld.out & 15) == 0);
+  wave_sync();
+  u64 *myrow = lds + lane * TileGeom<T>::kStride;
+  const int nrows = td.nlanes;
+  for (unsigned t0 = 0; t0 < td.max_len; t0 += T) {
+    const int m = (td.max_len - t0 < (unsigned)T) ? (int)(td.max_len - t0) : T;
+    if (m == T) gen_tile_full<V, KIND, T>(s, myrow);
+    else gen_tile_partial<V, KIND, T>(s, myrow, m);
+    wave_sync();
+    if (a16) store_tile_rows<T, true>(lds, lane, rowptr, rowlen, nrows, t0, m);
+    else store_tile_rows<T, false>(lds, lane, rowptr, rowlen, nrows, t0, m);
+    wave_sync();
+  }
+}
+
+template <int T>
+__global__ __launch_bounds__(kBlock) void k_batch(BatchArgs a) {
+  __shared__ __attribute__((aligned(16))) u64 lds_all[(kBlock / kWave) * TileGeom<T>::kWaveLds];
+  __shared__ u64 rowptr_all[kBlock];
+  __shared__ unsigned rowlen_all[kBlock];
+  const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+  u64 *lds = lds_all + wave * TileGeom<T>::kWaveLds;
+  u64 *rowptr = rowptr_all + wave * kWave;
+  unsigned *rowlen = rowlen_all + wave * kWave;
+  for (;;) {
+    unsigned t = 0;
+    if (lane == 0) t = atomicAdd(a.counter, 1u);
+    t = (unsigned)__builtin_amdgcn_readfirstlane((int)t);
+    if (t >= a.ntiles) break;  // every wave reaches this: the counter only grows
+    const TileDesc td = a.tiles[t];
+    switch (td.variant * 2 + td.kind) {
+#define SL_CASE(V)                                                  \
+  case 2 * V: batch_tile<V, 0, T>(a, td, lds, rowptr, rowlen, lane); break; \
+  case 2 * V + 1: batch_tile<V, 1, T>(a, td, lds, rowptr, rowlen, lane); break;
+      SL_CASE(0) SL_CASE(1) SL_CASE(2) SL_CASE(3) SL_CASE(4) SL_CASE(5) SL_CASE(6)
+      SL_CASE(7) SL_CASE(8) SL_CASE(9) SL_CASE(10) SL_CASE(11) SL_CASE(12) SL_CASE(13)
+#undef SL_CASE
+      default: break;
+    }
+    wave_sync();
+  }
+}
+
+__global__ void k_batch_reset(unsigned *counter) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *counter = 0;
+}
+
+template <int V>
+__global__ __launch_bounds__(kBlock) void k_req_state(ReqArgs a) {
+  constexpr int K = Params<V>::k;
+  const unsigned i = blockIdx.x * kBlock + threadIdx.x;
+  const unsigned first = i - (threadIdx.x % kWave);
+  if (first >= a.m) return;
+  const bool live = i < a.m;
+  u64 s[K];
+  splitmix64_fill<K>(live ? a.seeds[i] : 0, s);
+  const unsigned pi = live ? i : 0;
+  jump_lane<V>(s, [&](int wi) { return a.polys[(u64)pi * 16 + wi]; });
+  if (live) {
+#pragma unroll
+    for (int w = 0; w < K; w++) a.req_state[(u64)a.slot[i] * 16 + w] = s[w];
+  }
+}
+
+hipError_t launch_batch(const BatchArgs &a, int tile, unsigned blocks, hipStream_t st) {
+  if (tile == 16) hipLaunchKernelGGL(k_batch<16>, dim3(blocks), dim3(kBlock), 0, st, a);
+  else hipLaunchKernelGGL(k_batch<32>, dim3(blocks), dim3(kBlock), 0, st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_reset(unsigned *counter, hipStream_t st) {
+  hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(64), 0, st, counter);
+  return hipGetLastError();
+}
+
+template <int V>
+static hipError_t req_v(const ReqArgs &a, hipStream_t st) {
+  dim3 grid((a.m + kBlock - 1) / kBlock);
+  hipLaunchKernelGGL((k_req_state<V>), grid, dim3(kBlock), 0, st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_req_state(int variant, const ReqArgs &a, hipStream_t st) {
+  switch (variant) {
+    case 0: return req_v<0>(a, st);
+    case 1: return req_v<1>(a, st);
+    case 2: return req_v<2>(a, st);
+    case 3: return req_v<3>(a, st);
+    case 4: return req_v<4>(a, st);
+    case 5: return req_v<5>(a, st);
+    case 6: return req_v<6>(a, st);
+    case 7: return req_v<7>(a, st);
+    case 8: return req_v<8>(a, st);
+    case 9: return req_v<9>(a, st);
+    case 10: return req_v<10>(a, st);
+    case 11: return req_v<11>(a, st);
+    case 12: return req_v<12>(a, st);
+    case 13: return req_v<13>(a, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace slrng

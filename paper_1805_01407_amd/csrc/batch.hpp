@@ -1,0 +1,65 @@
+// Batched generation: descriptors shared by the host planner and the
+// persistent kernel (internal to the library).
+//
+// A request asks for n outputs of one generator, starting `start` steps after
+// the SplitMix64-seeded origin state of `seed`.  The planner cuts every
+// request into lane-chunks of at most C_v outputs (C_v per variant); chunk j
+// starts from the request's start state jumped by j*C_v steps (one per-lane
+// jump with the table entry x^(j C_v) mod p).  Lane-chunks of the same variant
+// and kind are sorted by length and packed 64 to a tile; one wave processes a
+// tile.  A persistent kernel claims tiles through an atomic counter, heaviest
+// tiles first, and switches on the (wave-uniform) variant and kind.
+#pragma once
+#include <hip/hip_runtime_api.h>
+#include <stdint.h>
+
+#include "engines.hpp"
+
+namespace slrng {
+
+constexpr uint32_t kNoReqState = 0xffffffffu;
+
+struct TileDesc {
+  uint16_t variant;
+  uint8_t kind;
+  uint8_t nlanes;     // 1..64
+  uint32_t max_len;   // longest lane-chunk of the tile
+  uint32_t lane0;     // first lane descriptor
+  uint32_t need_jump; // 1 if some lane has a chunk index > 0
+};
+
+struct LaneDesc {
+  uint64_t seed;      // origin seed (used when req == kNoReqState)
+  uint64_t out;       // device address of the chunk's first output
+  uint32_t len;       // outputs of this chunk
+  uint32_t jidx;      // chunk index j (table entry x^(j C) mod p)
+  uint32_t req;       // request-state index, or kNoReqState
+  uint32_t pad;
+};
+
+struct BatchArgs {
+  const TileDesc *tiles;
+  uint32_t ntiles;
+  uint32_t pad;
+  const LaneDesc *lanes;
+  const uint64_t *req_state;          // [r][16] start states of requests with start > 0
+  const uint64_t *tab[kNumVariants];  // chunk tables, word-major: word w of entry j at [w*tab_n + j]
+  uint32_t tab_n[kNumVariants];
+  unsigned *counter;                  // tile claim counter (zeroed by k_batch_reset)
+};
+
+// Request start states for requests with start > 0: state of request r =
+// SplitMix64(seed) jumped by `start` (per-request polynomial, 16 words).
+struct ReqArgs {
+  const uint64_t *seeds;    // [m]
+  const uint64_t *polys;    // [m][16]
+  const uint32_t *slot;     // [m] index into req_state
+  uint64_t *req_state;      // [..][16]
+  uint32_t m;
+};
+
+hipError_t launch_batch(const BatchArgs &a, int tile, unsigned blocks, hipStream_t st);
+hipError_t launch_batch_reset(unsigned *counter, hipStream_t st);
+hipError_t launch_req_state(int variant, const ReqArgs &a, hipStream_t st);
+
+}  // namespace slrng

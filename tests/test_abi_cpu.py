@@ -115,3 +115,28 @@ def test_invalid_arguments_return_einval(P):
     assert L.slrng_streams_create(0, 1, 0, None, ctypes.byref(h)) == -2
     assert L.slrng_streams_create(0, 1, (1 << 31) + 1, None, ctypes.byref(h)) == -2
     assert L.slrng_calib_write(None, 16, None) == -1
+
+
+def test_batch_argument_errors_before_any_device_call(P):
+    bad_variant = P.make_requests(14, 0, 1, 0, 10, 4096)
+    misaligned = P.make_requests(0, 0, 1, 0, 10, 4100)
+    bad_kind = P.make_requests(0, 2, 1, 0, 10, 4096)
+    null_out = P.make_requests(0, 0, 1, 0, 10, 0)
+    for reqs in (bad_variant, misaligned, bad_kind, null_out):
+        with pytest.raises(P.SlrngError) as e:
+            P.slrng_batch_run(reqs, None, 0)
+        assert e.value.name == "EINVAL"
+    o = P.slrng_batch_default_opts()
+    o.mode = 7
+    with pytest.raises(P.SlrngError):
+        P.slrng_batch_run(P.make_requests(0, 0, 1, 0, 10, 4096), o, 0)
+    o = P.slrng_batch_default_opts(tile=24)
+    with pytest.raises(P.SlrngError):
+        P.slrng_batch_run(P.make_requests(0, 0, 1, 0, 10, 4096), o, 0)
+
+
+def test_request_record_layout(P):
+    assert P.REQUEST_DTYPE.itemsize == 40
+    r = P.make_requests([1, 2], 1, [5, 6], 0, 7, [8, 16])
+    assert r["variant"].tolist() == [1, 2] and r["seed"].tolist() == [5, 6]
+    assert r["dev_out"].tolist() == [8, 16]
