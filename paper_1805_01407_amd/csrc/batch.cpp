@@ -279,10 +279,11 @@ extern "C" int slrng_batch_plan(const slrng_request *reqs, size_t n_reqs,
       for (size_t s = i; s < e2; s += kWave) {
         const size_t cnt = std::min<size_t>(kWave, e2 - s);
         TileDesc td;
-        td.variant = (uint16_t)lanes[s].variant;
+        td.variant = (uint8_t)lanes[s].variant;
         td.kind = (uint8_t)lanes[s].kind;
         td.nlanes = (uint8_t)cnt;
         td.max_len = lanes[s].d.len;  // sorted: the first is the longest
+        td.min_len = lanes[s + cnt - 1].d.len;
         td.lane0 = (uint32_t)(h_lanes.size());
         td.need_jump = 0;
         for (size_t q = s; q < s + cnt; q++) {

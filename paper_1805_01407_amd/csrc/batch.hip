@@ -19,11 +19,22 @@ namespace slrng {
 template <int T, bool A16>
 __device__ __forceinline__ void store_tile_rows(const u64 *lds, int lane, const u64 *rowptr,
                                                 const unsigned *rowlen, int nrows, unsigned t0,
-                                                int m) {
+                                                int m, bool full) {
   constexpr int S = TileGeom<T>::kStride;
   if constexpr (A16) {
     constexpr int LPR = T / 2;
     constexpr int RPI = kWave / LPR;
+    if (full) {  // all 64 rows have T more outputs: no predicates
+      const int r0 = lane / LPR;
+      const int c = 2 * (lane % LPR);
+#pragma unroll
+      for (int q = 0; q < T / 2; q++) {
+        const int r = q * RPI + r0;
+        const u64x2 v = *reinterpret_cast<const u64x2 *>(lds + r * S + c);
+        out_store(reinterpret_cast<u64x2 *>(reinterpret_cast<u64 *>(rowptr[r]) + t0 + c), v);
+      }
+      return;
+    }
 #pragma unroll
     for (int q = 0; q < T / 2; q++) {
       const int r = q * RPI + lane / LPR;
@@ -94,8 +105,9 @@ __device__ __forceinline__ void batch_tile(const BatchArgs &a, const TileDesc &t
     if (m == T) gen_tile_full<V, KIND, T>(s, myrow);
     else gen_tile_partial<V, KIND, T>(s, myrow, m);
     wave_sync();
-    if (a16) store_tile_rows<T, true>(lds, lane, rowptr, rowlen, nrows, t0, m);
-    else store_tile_rows<T, false>(lds, lane, rowptr, rowlen, nrows, t0, m);
+    const bool full = nrows == kWave && m == T && t0 + T <= td.min_len;
+    if (a16) store_tile_rows<T, true>(lds, lane, rowptr, rowlen, nrows, t0, m, full);
+    else store_tile_rows<T, false>(lds, lane, rowptr, rowlen, nrows, t0, m, full);
     wave_sync();
   }
 }

@@ -20,12 +20,13 @@ namespace slrng {
 constexpr uint32_t kNoReqState = 0xffffffffu;
 
 struct TileDesc {
-  uint16_t variant;
+  uint8_t variant;
   uint8_t kind;
   uint8_t nlanes;     // 1..64
+  uint8_t need_jump;  // 1 if some lane has a chunk index > 0
   uint32_t max_len;   // longest lane-chunk of the tile
+  uint32_t min_len;   // shortest lane-chunk of the tile
   uint32_t lane0;     // first lane descriptor
-  uint32_t need_jump; // 1 if some lane has a chunk index > 0
 };
 
 struct LaneDesc {

@@ -28,19 +28,50 @@ typedef uint64_t u64;
 enum Family { XOROSHIRO = 0, XOSHIRO = 1 };
 enum Scrambler { SCR_PLUS = 0, SCR_PLUSPLUS = 1, SCR_STAR = 2, SCR_STARSTAR = 3 };
 
+// Left rotation of a 64-bit word.  On the GPU it is two v_alignbit_b32 (a
+// funnel shift of the two 32-bit halves) instead of two 64-bit shifts and an or.
 template <int R>
 SL_HD u64 rotl(u64 x) {
   static_assert(R > 0 && R < 64, "rotation amount");
+#if defined(__HIP_DEVICE_COMPILE__)
+  const unsigned lo = (unsigned)x, hi = (unsigned)(x >> 32);
+  unsigned nlo, nhi;
+  if constexpr (R == 32) {
+    nlo = hi;
+    nhi = lo;
+  } else if constexpr (R < 32) {
+    nhi = __builtin_amdgcn_alignbit(hi, lo, 32 - R);
+    nlo = __builtin_amdgcn_alignbit(lo, hi, 32 - R);
+  } else {
+    nhi = __builtin_amdgcn_alignbit(lo, hi, 64 - R);
+    nlo = __builtin_amdgcn_alignbit(hi, lo, 64 - R);
+  }
+  return ((u64)nhi << 32) | nlo;
+#else
   return (x << R) | (x >> (64 - R));
+#endif
 }
 
 // ** multiplies by 2^s + 1 (S = 5, T = 9 in tab:scr64), which the paper notes
-// can be computed as a shift and a sum.
+// can be computed as a shift and a sum.  On the GPU that is one
+// v_lshl_add_u64 (the compiler would otherwise turn it back into 32-bit
+// multiply-adds).
 template <u64 M>
 SL_HD u64 mul_const(u64 x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  if constexpr (M == 5 || M == 9) {
+    u64 r;
+    if constexpr (M == 5) asm("v_lshl_add_u64 %0, %1, 2, %1" : "=v"(r) : "v"(x));
+    else asm("v_lshl_add_u64 %0, %1, 3, %1" : "=v"(r) : "v"(x));
+    return r;
+  } else {
+    return x * M;
+  }
+#else
   if constexpr (M == 5) return x + (x << 2);
   else if constexpr (M == 9) return x + (x << 3);
   else return x * M;
+#endif
 }
 
 // Parameters per variant id (the ids of slrng_variant in include/slrng.h).

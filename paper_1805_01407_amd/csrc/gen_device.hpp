@@ -176,6 +176,7 @@ __device__ __forceinline__ void nt_store(VT *p, VT v) {
 
 // Store a staged tile: rows 0..rows_live of the wave, m outputs each, to
 // base + r*ld + c.  A16: every row start is 16-byte aligned (dwordx4 path).
+// A full tile (all 64 rows, T outputs) takes the unpredicated path.
 template <int T, bool A16>
 __device__ __forceinline__ void store_tile(const u64 *lds, int lane, u64 *base, u64 ld,
                                            int rows_live, int m) {
@@ -183,25 +184,37 @@ __device__ __forceinline__ void store_tile(const u64 *lds, int lane, u64 *base, 
   if constexpr (A16) {
     constexpr int LPR = T / 2;         // lanes per row, 16 bytes each
     constexpr int RPI = kWave / LPR;   // rows per store instruction
+    const int r0 = lane / LPR;
+    const int c = 2 * (lane % LPR);
+    const u64x2 *src = reinterpret_cast<const u64x2 *>(lds + r0 * S + c);
+    u64 *dst = base + (u64)r0 * ld + c;
+    const u64 step = (u64)RPI * ld;
+    if (rows_live == kWave && m == T) {
+#pragma unroll
+      for (int q = 0; q < T / 2; q++)
+        out_store(reinterpret_cast<u64x2 *>(dst + q * step), src[q * RPI * S / 2]);
+      return;
+    }
 #pragma unroll
     for (int q = 0; q < T / 2; q++) {
-      const int r = q * RPI + lane / LPR;
-      const int c = 2 * (lane % LPR);
+      const int r = q * RPI + r0;
       if (r < rows_live && c < m) {
-        const u64x2 v = *reinterpret_cast<const u64x2 *>(lds + r * S + c);
-        u64 *dst = base + (u64)r * ld + c;
-        if (c + 1 < m) out_store(reinterpret_cast<u64x2 *>(dst), v);
-        else out_store(dst, v.x);
+        const u64x2 v = src[q * RPI * S / 2];
+        if (c + 1 < m) out_store(reinterpret_cast<u64x2 *>(dst + q * step), v);
+        else out_store(dst + q * step, v.x);
       }
     }
   } else {
     constexpr int LPR = T;
     constexpr int RPI = kWave / LPR;
+    const int r0 = lane / LPR;
+    const int c = lane % LPR;
+    u64 *dst = base + (u64)r0 * ld + c;
+    const u64 step = (u64)RPI * ld;
 #pragma unroll
     for (int q = 0; q < T; q++) {
-      const int r = q * RPI + lane / LPR;
-      const int c = lane % LPR;
-      if (r < rows_live && c < m) out_store(base + (u64)r * ld + c, lds[r * S + c]);
+      const int r = q * RPI + r0;
+      if (r < rows_live && c < m) out_store(dst + q * step, lds[r * S + c]);
     }
   }
 }
