@@ -76,6 +76,49 @@ def cpu_baseline(batch: int, N: int, seconds: float = 15.0) -> dict:
                       f"(u64 + f64) from the seed-1 chains; {outs:.3g} outputs in {dt:.1f} s"}
 
 
+def batched_section(P, torch, stream, launches: int = 3) -> dict:
+    """The batched-requests workload (10,000 requests, generator uniform over
+    the eight swept variants, lengths log-uniform in [1, 2^24), 30% doubles):
+    one persistent launch replayed from a hipGraph, against the plain form (one
+    launch of the same kernel per request).  Per-request latency is the time
+    from the start of the launch until that request's outputs are complete."""
+    import numpy as np
+    from paper_1805_01407_amd import workloads as W
+    w = W.batch_requests()
+    arena = torch.empty((w["arena_elems"],), dtype=torch.int64, device="cuda")
+    reqs = P.make_requests(w["variant"], w["kind"], w["seed"], w["start"], w["n"],
+                           arena.data_ptr() + 8 * w["offset"])
+    total = int(w["n"].sum())
+    out = {"requests": len(w["n"]), "outputs": total}
+    for label, mode, reps in (("batched_graph", P.SLRNG_BATCH_GRAPH, launches),
+                              ("plain_per_request", P.SLRNG_BATCH_PLAIN, 1)):
+        t0 = time.perf_counter()
+        b = P.slrng_batch_plan(reqs, P.slrng_batch_default_opts(mode=mode))
+        plan_ms = (time.perf_counter() - t0) * 1e3
+        try:
+            P.slrng_batch_launch(b, stream)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(reps):
+                P.slrng_batch_launch(b, stream)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / reps
+            lat = P.slrng_batch_latencies(b, len(w["n"]), stream)
+        finally:
+            P.slrng_batch_destroy(b)
+        gbs = 8 * total / (ms * 1e-3) / 1e9
+        out[label] = {"ms_per_launch": round(ms, 3), "outputs_per_s": total / (ms * 1e-3),
+                      "GBs": round(gbs, 1), "frac_of_hbm_peak": round(gbs / HBM_PEAK_GBS, 4),
+                      "latency_p50_ms": round(float(np.percentile(lat, 50)), 3),
+                      "latency_p99_ms": round(float(np.percentile(lat, 99)), 3),
+                      "plan_ms": round(plan_ms, 1)}
+    del arena
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -84,6 +127,7 @@ def main():
     ap.add_argument("--streams", type=int, default=65536)
     ap.add_argument("--n", type=int, default=65536)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched-requests section")
     ap.add_argument("--cpu-streams", type=int, default=512, help="streams per oracle batch")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     args = ap.parse_args()
@@ -164,9 +208,13 @@ def main():
     P.slrng_calib_copy(buf_f.data_ptr(), buf_u.data_ptr(), copy_bytes, stream)
     torch.cuda.synchronize()
 
-    cpu = None if args.no_cpu else cpu_baseline(args.cpu_streams, N, args.cpu_seconds)
     for h in hs.values():
         h.close()
+    del buf_u, buf_f
+    torch.cuda.empty_cache()
+    batched = None if args.no_batch else batched_section(P, torch, stream)
+
+    cpu = None if args.no_cpu else cpu_baseline(args.cpu_streams, N, args.cpu_seconds)
 
     out = {
         "metric": "64-bit outputs/s (uint64 + [0,1) doubles), full family sweep",
@@ -189,6 +237,7 @@ def main():
                      "traffic": profiled_traffic()},
         "write_ceiling_GBs": ceiling,
         "gen_GBs_per_generator": per_variant,
+        "batched_requests": batched,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

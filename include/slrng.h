@@ -207,6 +207,12 @@ int slrng_set_tuning(int variant, int kind, const slrng_tuning *t);
  * not overlap in time (they share a claim counter).
  * slrng_batch_run: plan + launch + synchronize + destroy.
  * slrng_batch_info: tiles, lane-chunks and outputs of a plan.
+ * slrng_batch_latencies: a measurement aid.  Launches the planned batch once
+ * with timing events (without the graph), waits for it, and writes for every
+ * request the time in ms from the start of the launch until that request's
+ * outputs were complete: one value for all requests in the batched modes,
+ * each request's own launch end in the plain form (0 for empty requests).
+ * done_ms has one entry per planned request.  Synchronous.
  * Errors: EINVAL for a bad variant, kind, mode, tile, null or misaligned
  * output; ERANGE for more than 2^24 requests or a request too long to chunk.
  *
@@ -248,6 +254,7 @@ int slrng_batch_plan(const slrng_request *reqs, size_t n_reqs, const slrng_batch
 int slrng_batch_launch(slrng_batch *b, hipStream_t stream);
 int slrng_batch_info(const slrng_batch *b, uint64_t *n_tiles, uint64_t *n_lanes,
                      uint64_t *total_outputs);
+int slrng_batch_latencies(slrng_batch *b, hipStream_t stream, double *done_ms);
 int slrng_batch_destroy(slrng_batch *b);
 int slrng_batch_run(const slrng_request *reqs, size_t n_reqs, const slrng_batch_opts *opts,
                     hipStream_t stream);

@@ -20,5 +20,5 @@ from .binding import (  # noqa: F401
     SLRNG_U64, SLRNG_F64, SLRNG_JUMP, SLRNG_LONG_JUMP,
     SLRNG_BATCH_GRAPH, SLRNG_BATCH_PERSISTENT, SLRNG_BATCH_PLAIN, REQUEST_DTYPE, make_requests,
     slrng_batch_default_opts, slrng_batch_plan, slrng_batch_launch, slrng_batch_info,
-    slrng_batch_destroy, slrng_batch_run,
+    slrng_batch_destroy, slrng_batch_run, slrng_batch_latencies, set_batch_defaults,
 )

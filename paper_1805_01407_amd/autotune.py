@@ -1,0 +1,170 @@
+"""Autotuner for the launch shapes of slrng on the current GPU.
+
+It times the library's own kernels through the C ABI (HIP events on the
+current torch stream) and keeps the fastest shape:
+
+* ``slrng_generate``, per variant and kind: LDS tile (16 or 32 outputs per lane
+  per round), wave target (how finely short, wide requests are split into
+  jumped slots) and the number of staggered slot-boundary classes;
+* batched generation: LDS tile, persistent grid (waves per CU) and lane-chunk
+  length per variant, on a seeded batched workload.
+
+The result is a JSON file keyed by GPU architecture; the binding applies it
+when it loads the library (``apply``).  The launch shape never changes any
+output value, only speed.
+
+    python -m paper_1805_01407_amd.autotune [--out FILE] [--quick]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import statistics
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+DEFAULT_PATH = os.path.join(HERE, "tuning.json")
+
+
+def _arch() -> str | None:
+    import torch
+    if not torch.cuda.is_available():
+        return None
+    return torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
+
+
+def _time_ms(fn, reps: int) -> float:
+    import torch
+    fn()
+    torch.cuda.synchronize()
+    times = []
+    for _ in range(reps):
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record()
+        fn()
+        b.record()
+        torch.cuda.synchronize()
+        times.append(a.elapsed_time(b))
+    return statistics.median(times)
+
+
+def tune_generate(variants, S=65536, N=65536, reps=5, quick=False, log=print) -> dict:
+    import torch
+    from . import binding as B
+    buf = torch.empty((S, N), dtype=torch.int64, device="cuda")
+    out = {}
+    tiles = (16, 32)
+    waves = (4096, 8192) if quick else (2048, 4096, 8192, 16384)
+    skews = (1, 4) if quick else (1, 4, 16)
+    for name in variants:
+        for kind in (B.SLRNG_U64, B.SLRNG_F64):
+            best = None
+            with B.Streams(name, 1, S) as h:
+                for tile in tiles:
+                    for tw in waves:
+                        for sk in skews:
+                            B.slrng_set_tuning(name, kind, tile, tw, 1024, sk)
+                            ms = _time_ms(lambda: B.slrng_generate(h.h, kind, N, buf.data_ptr(), N),
+                                          reps)
+                            if best is None or ms < best[0]:
+                                best = (ms, {"tile": tile, "target_waves": tw, "skew": sk,
+                                             "min_chunk": 1024})
+            gbs = 8 * S * N / (best[0] * 1e-3) / 1e9
+            log(f"generate {name} kind {kind}: {best[1]} {gbs:.0f} GB/s")
+            out[f"{name}/{kind}"] = dict(best[1], GBs=round(gbs, 1))
+            B.slrng_set_tuning(name, kind, **{k: best[1][k] for k in
+                                              ("tile", "target_waves", "min_chunk", "skew")})
+    del buf
+    torch.cuda.empty_cache()
+    return out
+
+
+def tune_batch(reps=5, quick=False, log=print) -> dict:
+    import torch
+    from . import binding as B
+    from . import workloads as W
+    w = W.batch_requests()
+    arena = torch.empty((w["arena_elems"],), dtype=torch.int64, device="cuda")
+    reqs = B.make_requests(w["variant"], w["kind"], w["seed"], w["start"], w["n"],
+                           arena.data_ptr() + 8 * w["offset"])
+    total = int(w["n"].sum())
+    heavy = {9, 10, 11, 13}  # 16-word engine: longer chunks amortise its jump
+    best = None
+    for tile in (16, 32):
+        for wpc in ((8, 12) if quick else (8, 12, 16)):
+            for light in ((8192, 16384) if quick else (4096, 8192, 16384)):
+                for hv in ((32768, 65536) if quick else (16384, 32768, 65536)):
+                    chunk = {v: (hv if v in heavy else light) for v in range(B.NUM_VARIANTS)}
+                    opts = B.slrng_batch_default_opts(mode=B.SLRNG_BATCH_GRAPH, tile=tile,
+                                                      waves_per_cu=wpc, chunk=chunk)
+                    b = B.slrng_batch_plan(reqs, opts)
+                    try:
+                        ms = _time_ms(lambda: B.slrng_batch_launch(b), reps)
+                    finally:
+                        B.slrng_batch_destroy(b)
+                    if best is None or ms < best[0]:
+                        best = (ms, {"tile": tile, "waves_per_cu": wpc, "chunk_light": light,
+                                     "chunk_heavy": hv})
+    gbs = 8 * total / (best[0] * 1e-3) / 1e9
+    log(f"batch: {best[1]} {gbs:.0f} GB/s")
+    del arena
+    torch.cuda.empty_cache()
+    return dict(best[1], GBs=round(gbs, 1))
+
+
+def load(path: str = DEFAULT_PATH) -> dict | None:
+    try:
+        with open(path) as f:
+            return json.load(f)
+    except (OSError, ValueError):
+        return None
+
+
+def apply(path: str = DEFAULT_PATH) -> bool:
+    """Apply saved tuning for this GPU's architecture (no-op without a GPU or a
+    matching entry).  Returns True if something was applied."""
+    data = load(path)
+    arch = _arch() if data else None
+    if not data or not arch or arch not in data:
+        return False
+    from . import binding as B
+    t = data[arch]
+    for key, cfg in t.get("generate", {}).items():
+        name, kind = key.rsplit("/", 1)
+        B.slrng_set_tuning(name, int(kind), cfg["tile"], cfg["target_waves"], cfg["min_chunk"],
+                           cfg["skew"])
+    if "batch" in t:
+        B.set_batch_defaults(t["batch"])
+    return True
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--out", default=DEFAULT_PATH)
+    ap.add_argument("--quick", action="store_true")
+    ap.add_argument("--only", choices=["generate", "batch"], default=None)
+    args = ap.parse_args(argv)
+    sys.path.insert(0, os.path.dirname(HERE))
+    from . import binding as B
+    B.lib()
+    arch = _arch()
+    if arch is None:
+        print("autotune: no GPU", file=sys.stderr)
+        return 2
+    data = load(args.out) or {}
+    entry = data.get(arch, {})
+    if args.only in (None, "generate"):
+        entry["generate"] = tune_generate(B.VARIANTS, quick=args.quick)
+    if args.only in (None, "batch"):
+        entry["batch"] = tune_batch(quick=args.quick)
+    data[arch] = entry
+    with open(args.out, "w") as f:
+        json.dump(data, f, indent=1, sort_keys=True)
+    print(f"autotune: wrote {args.out}")
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

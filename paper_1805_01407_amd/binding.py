@@ -103,6 +103,7 @@ def lib():
         "slrng_batch_plan": ([vp, ctypes.c_size_t, ctypes.POINTER(_BatchOpts), ctypes.POINTER(vp)], i32),
         "slrng_batch_launch": ([vp, vp], i32),
         "slrng_batch_info": ([vp, u64p, u64p, u64p], i32),
+        "slrng_batch_latencies": ([vp, vp, ctypes.POINTER(ctypes.c_double)], i32),
         "slrng_batch_destroy": ([vp], i32),
         "slrng_batch_run": ([vp, ctypes.c_size_t, ctypes.POINTER(_BatchOpts), vp], i32),
         "slrng_calib_write": ([vp, u64, vp], i32),
@@ -113,6 +114,9 @@ def lib():
         f.argtypes = args
         f.restype = res
     _lib = L
+    # launch shapes chosen by the autotuner for this GPU, if any were saved
+    from . import autotune
+    autotune.apply()
     return L
 
 
@@ -273,11 +277,29 @@ def slrng_calib_copy(dev_dst: int, dev_src: int, nbytes: int, stream=None) -> No
     _check(lib().slrng_calib_copy(dev_dst, dev_src, nbytes, _stream(stream)), "slrng_calib_copy")
 
 
+_batch_defaults: dict = {}
+_HEAVY = (9, 10, 11, 13)  # variants of the 16-word engine
+
+
+def set_batch_defaults(cfg: dict) -> None:
+    """Tuned batch defaults: tile, waves_per_cu, chunk_light, chunk_heavy."""
+    _batch_defaults.clear()
+    _batch_defaults.update(cfg)
+
+
 def slrng_batch_default_opts(mode: int = SLRNG_BATCH_GRAPH, tile: int | None = None,
                              waves_per_cu: int | None = None, chunk: dict | None = None):
-    """Default batch options, with optional overrides (chunk: {variant: length})."""
+    """Default batch options (the library's, then tuned values if the
+    autotuner saved any), with optional overrides (chunk: {variant: length})."""
     o = _BatchOpts()
     _check(lib().slrng_batch_default_opts(ctypes.byref(o)), "slrng_batch_default_opts")
+    if _batch_defaults:
+        o.tile = _batch_defaults.get("tile", o.tile)
+        o.waves_per_cu = _batch_defaults.get("waves_per_cu", o.waves_per_cu)
+        for v in range(NUM_VARIANTS):
+            key = "chunk_heavy" if v in _HEAVY else "chunk_light"
+            if key in _batch_defaults:
+                o.chunk[v] = _batch_defaults[key]
     o.mode = mode
     if tile is not None:
         o.tile = tile
@@ -321,6 +343,15 @@ def slrng_batch_info(b: int) -> dict:
     _check(lib().slrng_batch_info(b, ctypes.byref(t), ctypes.byref(l), ctypes.byref(o)),
            "slrng_batch_info")
     return {"tiles": t.value, "lanes": l.value, "outputs": o.value}
+
+
+def slrng_batch_latencies(b: int, n_requests: int, stream=None) -> np.ndarray:
+    """Per-request completion times (ms from launch start) of one timed launch."""
+    out = np.zeros(max(n_requests, 1), dtype=np.float64)
+    _check(lib().slrng_batch_latencies(b, _stream(stream),
+                                       out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))),
+           "slrng_batch_latencies")
+    return out[:n_requests]
 
 
 def slrng_batch_destroy(b: int) -> None:

@@ -95,6 +95,10 @@ struct slrng_batch {
   // request for the plain form
   struct Unit {
     uint32_t tile0 = 0, ntiles = 0;
+    int64_t req = -1;           // plain form: the request
+    int variant = -1;           // plain form: the request's variant
+    const uint64_t *tab = nullptr;  // plain form: its chunk table
+    uint32_t tab_n = 0;
   };
   std::vector<Unit> units;
   uint32_t ntiles = 0, nlanes = 0;
@@ -136,6 +140,10 @@ static int enqueue_unit(slrng_batch *b, const slrng_batch::Unit &u, unsigned *co
                         hipStream_t st) {
   if (u.ntiles == 0) return SLRNG_OK;
   BatchArgs a = b->args;
+  if (u.variant >= 0) {
+    a.tab[u.variant] = u.tab;
+    a.tab_n[u.variant] = u.tab_n;
+  }
   a.tiles = b->d_tiles + u.tile0;
   a.ntiles = u.ntiles;
   a.counter = counter;
@@ -213,6 +221,20 @@ extern "C" int slrng_batch_plan(const slrng_request *reqs, size_t n_reqs,
       req_slot[r] = nslots++;
       by_var[reqs[r].variant].push_back((uint32_t)r);
     }
+  int cus = 0;
+  e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, b->device);
+  if (e != hipSuccess) {
+    free_batch(b);
+    return hip_fail(e);
+  }
+  const int wpc = o.waves_per_cu ? o.waves_per_cu : 12;
+  b->blocks = (unsigned)std::max(1, cus * wpc / (kBlock / kWave));
+  const bool plain = o.mode == SLRNG_BATCH_PLAIN;
+  // The plain form runs each request alone, so each request is cut finely
+  // enough to fill the GPU by itself: chunk = the smallest power of two >= 1024
+  // giving at most one chunk per lane of the persistent grid (capped by C_v).
+  const uint64_t grid_lanes = (uint64_t)b->blocks * kBlock;
+  std::vector<uint64_t> req_chunk(n_reqs, 0);
   // lanes
   std::vector<Lane> lanes;
   uint32_t tab_need[kNumVariants] = {0};
@@ -220,9 +242,16 @@ extern "C" int slrng_batch_plan(const slrng_request *reqs, size_t n_reqs,
     const slrng_request &q = reqs[r];
     if (!q.n) continue;
     b->total_outputs += q.n;
-    const uint64_t c = C[q.variant];
+    uint64_t c = C[q.variant];
+    if (plain) {
+      uint64_t want = 1024;
+      while (want < c && want * grid_lanes < q.n) want *= 2;
+      c = std::min<uint64_t>(c, std::max<uint64_t>(want, (q.n + kMaxTable - 1) / kMaxTable));
+      c = (c + o.tile - 1) / o.tile * o.tile;
+      req_chunk[r] = c;
+    }
     const uint64_t nch = (q.n + c - 1) / c;
-    tab_need[q.variant] = std::max<uint32_t>(tab_need[q.variant], (uint32_t)nch);
+    if (!plain) tab_need[q.variant] = std::max<uint32_t>(tab_need[q.variant], (uint32_t)nch);
     for (uint64_t j = 0; j < nch; j++) {
       Lane l;
       l.variant = q.variant;
@@ -252,7 +281,6 @@ extern "C" int slrng_batch_plan(const slrng_request *reqs, size_t n_reqs,
   }
   // tiles: per unit (the whole batch, or one request), per (variant, kind),
   // lanes sorted by length, 64 per tile; tiles heaviest first within a unit
-  const bool plain = o.mode == SLRNG_BATCH_PLAIN;
   std::vector<LaneDesc> h_lanes;
   std::vector<TileDesc> h_tiles;
   h_lanes.reserve(lanes.size());
@@ -302,6 +330,21 @@ extern "C" int slrng_batch_plan(const slrng_request *reqs, size_t n_reqs,
                      });
     for (auto &t : tiles) h_tiles.push_back(t.second);
     u.ntiles = (uint32_t)h_tiles.size() - u.tile0;
+    if (plain) {
+      const size_t r = (size_t)unit_key;
+      const uint64_t c = req_chunk[r];
+      ChunkTable t;
+      rc = chunk_table(b->device, variant_engine(reqs[r].variant), c,
+                       (uint32_t)((reqs[r].n + c - 1) / c), &t);
+      if (rc) {
+        free_batch(b);
+        return rc;
+      }
+      u.req = (int64_t)r;
+      u.variant = reqs[r].variant;
+      u.tab = t.dev;
+      u.tab_n = t.n;
+    }
     b->units.push_back(u);
   }
   if (b->units.empty()) b->units.push_back(slrng_batch::Unit());
@@ -364,14 +407,6 @@ extern "C" int slrng_batch_plan(const slrng_request *reqs, size_t n_reqs,
   b->args.lanes = b->d_lanes;
   b->args.req_state = b->d_req_state;
   b->args.counter = b->d_counter;
-  int cus = 0;
-  e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, b->device);
-  if (e != hipSuccess) {
-    free_batch(b);
-    return hip_fail(e);
-  }
-  const int wpc = o.waves_per_cu ? o.waves_per_cu : 12;
-  b->blocks = (unsigned)std::max(1, cus * wpc / (kBlock / kWave));
   // graph: capture the whole enqueue sequence once
   if (o.mode == SLRNG_BATCH_GRAPH) {
     hipStream_t cs = nullptr;
@@ -411,6 +446,69 @@ extern "C" int slrng_batch_launch(slrng_batch *b, hipStream_t stream) {
     return e == hipSuccess ? SLRNG_OK : hip_fail(e);
   }
   return enqueue_all(b, stream);
+}
+
+extern "C" int slrng_batch_latencies(slrng_batch *b, hipStream_t stream, double *done_ms) {
+  if (!b || !done_ms) return SLRNG_EINVAL;
+  for (uint64_t r = 0; r < b->n_requests; r++) done_ms[r] = 0.0;
+  const bool per_unit = b->opts.mode == SLRNG_BATCH_PLAIN;
+  std::vector<hipEvent_t> ev(per_unit ? b->units.size() + 1 : 2, nullptr);
+  int rc = SLRNG_OK;
+  for (auto &x : ev) {
+    hipError_t e = hipEventCreate(&x);
+    if (e != hipSuccess) {
+      rc = hip_fail(e);
+      break;
+    }
+  }
+  if (!rc) {
+    hipError_t e = hipEventRecord(ev[0], stream);
+    if (e != hipSuccess) rc = hip_fail(e);
+  }
+  if (!rc && !per_unit) {
+    rc = slrng_batch_launch(b, stream);
+    if (!rc) {
+      hipError_t e = hipEventRecord(ev[1], stream);
+      if (e != hipSuccess) rc = hip_fail(e);
+    }
+  } else if (!rc) {
+    for (auto &rl : b->req_launches) {
+      hipError_t e = launch_req_state(rl.first, rl.second, stream);
+      if (e != hipSuccess) {
+        rc = hip_fail(e);
+        break;
+      }
+    }
+    for (size_t i = 0; i < b->units.size() && !rc; i++) {
+      rc = enqueue_unit(b, b->units[i], b->d_counter + (b->units.size() > 1 ? i : 0), stream);
+      if (!rc) {
+        hipError_t e = hipEventRecord(ev[i + 1], stream);
+        if (e != hipSuccess) rc = hip_fail(e);
+      }
+    }
+  }
+  if (!rc) {
+    hipError_t e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) rc = hip_fail(e);
+  }
+  if (!rc) {
+    if (!per_unit) {
+      float ms = 0;
+      hipError_t e = hipEventElapsedTime(&ms, ev[0], ev[1]);
+      if (e != hipSuccess) rc = hip_fail(e);
+      for (uint64_t r = 0; r < b->n_requests && !rc; r++) done_ms[r] = ms;
+    } else {
+      for (size_t i = 0; i < b->units.size() && !rc; i++) {
+        float ms = 0;
+        hipError_t e = hipEventElapsedTime(&ms, ev[0], ev[i + 1]);
+        if (e != hipSuccess) rc = hip_fail(e);
+        else if (b->units[i].req >= 0) done_ms[b->units[i].req] = ms;
+      }
+    }
+  }
+  for (auto &x : ev)
+    if (x) (void)hipEventDestroy(x);
+  return rc;
 }
 
 extern "C" int slrng_batch_info(const slrng_batch *b, uint64_t *n_tiles, uint64_t *n_lanes,
