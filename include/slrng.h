@@ -259,6 +259,77 @@ int slrng_batch_destroy(slrng_batch *b);
 int slrng_batch_run(const slrng_request *reqs, size_t n_reqs, const slrng_batch_opts *opts,
                     hipStream_t stream);
 
+/* ---------------------------------------------------------------- serving
+ *
+ * A request server with continuous batching over device-resident streams.
+ * Stream j (j < n_streams) is positioned as by slrng_streams_create(variant,
+ * seed, n_streams): the SplitMix64 base jumped j times.  Every request takes
+ * the next positions of its stream in admission order, so request r on stream
+ * j receives outputs pos_r .. pos_r + n_r - 1 of that stream, where pos_r is
+ * the total length of the earlier requests on j: its values do not depend on
+ * what else is in flight (the same request alone gives the same values).
+ *
+ * Admission (slrng_server_submit) reserves 8 n bytes of the device output
+ * arena (budget_bytes).  When the arena is full it blocks until space is
+ * released, or returns SLRNG_EAGAIN with SLRNG_SUBMIT_NONBLOCK.  A worker
+ * thread batches every pending request into one iteration (request-state
+ * kernel + persistent generation kernel) and launches it on one of
+ * `inflight` HIP streams while earlier iterations still run; a completion
+ * thread stamps latencies (submit to completion) when an iteration's event
+ * completes.  Outputs are read from the arena pointer that poll/wait return,
+ * then released (slrng_server_release), or released automatically at
+ * completion with SLRNG_SUBMIT_AUTORELEASE (throughput runs).
+ *
+ * slrng_server_poll: 1 when done, 0 while pending, SLRNG_EHIP if its iteration
+ *   failed, SLRNG_EINVAL for an unknown or released ticket; fills the output
+ *   pointer and the stream position.  slrng_server_wait: blocks until done.
+ * slrng_server_release: frees a completed request's arena range (EAGAIN while
+ *   it is still pending or in flight).
+ * slrng_server_drain: waits until every submitted request has completed.
+ * slrng_server_get_stats / _reset_stats: counters; latency percentiles of the
+ *   completed requests; busy_s is the union of the iterations' device time.
+ * slrng_server_replay: submits count requests at the given arrival times
+ *   (seconds from the call), with SLRNG_SUBMIT_AUTORELEASE, then drains (a
+ *   load generator for benchmarks).
+ * slrng_server_destroy: completes everything submitted, stops the threads and
+ *   frees all memory.  submit/poll/wait/release/stats are thread-safe. */
+typedef struct slrng_server slrng_server;
+
+typedef struct slrng_server_opts {
+  uint64_t budget_bytes; /* output arena (device memory) */
+  uint64_t seed;         /* resident streams' seed */
+  uint64_t chunk;        /* lane-chunk length (0 = default) */
+  uint32_t n_streams;    /* resident streams */
+  int32_t variant;
+  int32_t max_batch;     /* requests per iteration (0 = default; 1 = the plain form) */
+  int32_t inflight;      /* iterations in flight, 1..8 (0 = default) */
+  int32_t tile;          /* 16 or 32 (0 = default) */
+  int32_t waves_per_cu;  /* persistent grid (0 = default) */
+} slrng_server_opts;
+
+enum { SLRNG_SUBMIT_NONBLOCK = 1, SLRNG_SUBMIT_AUTORELEASE = 2 };
+
+typedef struct slrng_server_stats {
+  uint64_t submitted, completed, failed, rejected, outputs;
+  uint64_t iterations, max_inflight, max_batch, peak_reserved_bytes, reserved_bytes;
+  double wall_s, busy_s, mean_batch;
+  double p50_us, p99_us, max_us;
+} slrng_server_stats;
+
+int slrng_server_default_opts(slrng_server_opts *opts);
+int slrng_server_create(const slrng_server_opts *opts, slrng_server **out);
+int slrng_server_submit(slrng_server *sv, uint32_t stream_id, uint64_t n, int kind, int flags,
+                        uint64_t *ticket);
+int slrng_server_poll(slrng_server *sv, uint64_t ticket, void **dev_ptr, uint64_t *pos);
+int slrng_server_wait(slrng_server *sv, uint64_t ticket, void **dev_ptr, uint64_t *pos);
+int slrng_server_release(slrng_server *sv, uint64_t ticket);
+int slrng_server_drain(slrng_server *sv);
+int slrng_server_get_stats(slrng_server *sv, slrng_server_stats *out);
+int slrng_server_reset_stats(slrng_server *sv);
+int slrng_server_replay(slrng_server *sv, const double *t_arrival_s, const uint32_t *stream_ids,
+                        const uint64_t *n, const int32_t *kinds, size_t count);
+int slrng_server_destroy(slrng_server *sv);
+
 #ifdef __cplusplus
 }
 #endif

@@ -60,6 +60,25 @@ class _BatchOpts(ctypes.Structure):
                 ("chunk", ctypes.c_uint64 * NUM_VARIANTS)]
 
 
+SLRNG_SUBMIT_NONBLOCK, SLRNG_SUBMIT_AUTORELEASE = 1, 2
+
+
+class _ServerOpts(ctypes.Structure):
+    _fields_ = [("budget_bytes", ctypes.c_uint64), ("seed", ctypes.c_uint64),
+                ("chunk", ctypes.c_uint64), ("n_streams", ctypes.c_uint32),
+                ("variant", ctypes.c_int32), ("max_batch", ctypes.c_int32),
+                ("inflight", ctypes.c_int32), ("tile", ctypes.c_int32),
+                ("waves_per_cu", ctypes.c_int32)]
+
+
+class _ServerStats(ctypes.Structure):
+    _fields_ = [(f, ctypes.c_uint64) for f in
+                ("submitted", "completed", "failed", "rejected", "outputs", "iterations",
+                 "max_inflight", "max_batch", "peak_reserved_bytes", "reserved_bytes")] + \
+               [(f, ctypes.c_double) for f in
+                ("wall_s", "busy_s", "mean_batch", "p50_us", "p99_us", "max_us")]
+
+
 _lib = None
 
 
@@ -106,6 +125,18 @@ def lib():
         "slrng_batch_latencies": ([vp, vp, ctypes.POINTER(ctypes.c_double)], i32),
         "slrng_batch_destroy": ([vp], i32),
         "slrng_batch_run": ([vp, ctypes.c_size_t, ctypes.POINTER(_BatchOpts), vp], i32),
+        "slrng_server_default_opts": ([ctypes.POINTER(_ServerOpts)], i32),
+        "slrng_server_create": ([ctypes.POINTER(_ServerOpts), ctypes.POINTER(vp)], i32),
+        "slrng_server_submit": ([vp, ctypes.c_uint32, u64, i32, i32, u64p], i32),
+        "slrng_server_poll": ([vp, u64, ctypes.POINTER(vp), u64p], i32),
+        "slrng_server_wait": ([vp, u64, ctypes.POINTER(vp), u64p], i32),
+        "slrng_server_release": ([vp, u64], i32),
+        "slrng_server_drain": ([vp], i32),
+        "slrng_server_get_stats": ([vp, ctypes.POINTER(_ServerStats)], i32),
+        "slrng_server_reset_stats": ([vp], i32),
+        "slrng_server_replay": ([vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_uint32),
+                                 u64p, ctypes.POINTER(ctypes.c_int32), ctypes.c_size_t], i32),
+        "slrng_server_destroy": ([vp], i32),
         "slrng_calib_write": ([vp, u64, vp], i32),
         "slrng_calib_copy": ([vp, vp, u64, vp], i32),
     }
@@ -362,6 +393,78 @@ def slrng_batch_run(reqs: np.ndarray, opts=None, stream=None) -> None:
     reqs, ptr, n = _reqs(reqs)
     _check(lib().slrng_batch_run(ptr, n, ctypes.byref(opts) if opts is not None else None,
                                  _stream(stream)), "slrng_batch_run")
+
+
+def slrng_server_default_opts(**overrides):
+    o = _ServerOpts()
+    _check(lib().slrng_server_default_opts(ctypes.byref(o)), "slrng_server_default_opts")
+    for k, v in overrides.items():
+        setattr(o, k, _variant(v) if k == "variant" else v)
+    return o
+
+
+def slrng_server_create(opts=None) -> int:
+    sv = ctypes.c_void_p()
+    _check(lib().slrng_server_create(ctypes.byref(opts) if opts is not None else None,
+                                     ctypes.byref(sv)), "slrng_server_create")
+    return sv.value
+
+
+def slrng_server_submit(sv: int, stream_id: int, n: int, kind: int = SLRNG_U64,
+                        flags: int = 0) -> int:
+    t = ctypes.c_uint64()
+    _check(lib().slrng_server_submit(sv, stream_id, n, kind, flags, ctypes.byref(t)),
+           "slrng_server_submit")
+    return t.value
+
+
+def slrng_server_poll(sv: int, ticket: int):
+    """(status, device pointer, stream position); status 1 done, 0 pending."""
+    p, pos = ctypes.c_void_p(), ctypes.c_uint64()
+    rc = _check(lib().slrng_server_poll(sv, ticket, ctypes.byref(p), ctypes.byref(pos)),
+                "slrng_server_poll")
+    return rc, p.value, pos.value
+
+
+def slrng_server_wait(sv: int, ticket: int):
+    """Blocks until done; returns (device pointer, stream position)."""
+    p, pos = ctypes.c_void_p(), ctypes.c_uint64()
+    _check(lib().slrng_server_wait(sv, ticket, ctypes.byref(p), ctypes.byref(pos)),
+           "slrng_server_wait")
+    return p.value, pos.value
+
+
+def slrng_server_release(sv: int, ticket: int) -> None:
+    _check(lib().slrng_server_release(sv, ticket), "slrng_server_release")
+
+
+def slrng_server_drain(sv: int) -> None:
+    _check(lib().slrng_server_drain(sv), "slrng_server_drain")
+
+
+def slrng_server_get_stats(sv: int) -> dict:
+    st = _ServerStats()
+    _check(lib().slrng_server_get_stats(sv, ctypes.byref(st)), "slrng_server_get_stats")
+    return {f: getattr(st, f) for f, _ in _ServerStats._fields_}
+
+
+def slrng_server_reset_stats(sv: int) -> None:
+    _check(lib().slrng_server_reset_stats(sv), "slrng_server_reset_stats")
+
+
+def slrng_server_replay(sv: int, t_arrival_s, stream_ids, n, kinds) -> None:
+    t = np.ascontiguousarray(t_arrival_s, dtype=np.float64)
+    sid = np.ascontiguousarray(stream_ids, dtype=np.uint32)
+    nn = np.ascontiguousarray(n, dtype=np.uint64)
+    kk = np.ascontiguousarray(kinds, dtype=np.int32)
+    _check(lib().slrng_server_replay(sv, t.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                     sid.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)), _u64p(nn),
+                                     kk.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), t.size),
+           "slrng_server_replay")
+
+
+def slrng_server_destroy(sv: int) -> None:
+    _check(lib().slrng_server_destroy(sv), "slrng_server_destroy")
 
 
 # ---------------------------------------------------------------- object wrapper

@@ -384,6 +384,11 @@ extern "C" int slrng_streams_count(const slrng_streams *h, uint64_t *n) {
   return SLRNG_OK;
 }
 
+namespace slrng {
+// Current word-major state buffer of a handle (S words per state word).
+const uint64_t *streams_state_ptr(const slrng_streams *h) { return h->state[h->cur]; }
+}  // namespace slrng
+
 extern "C" int slrng_streams_variant(const slrng_streams *h, int *v) {
   if (!h || !v) return SLRNG_EINVAL;
   *v = h->variant;

@@ -16,6 +16,8 @@ const Poly &jump_kind_poly(int engine, int jump_kind);
 int levels_for(uint64_t S);
 int get_slot_polys(int device, int engine, uint64_t C, uint64_t D, const uint64_t **out);
 slrng_tuning tuning_for(int v, int kind);
+const uint64_t *streams_state_ptr(const slrng_streams *h);
+int check_batch_opts(const slrng_batch_opts &o);
 void plan_slots(uint64_t S, uint64_t n, const slrng_tuning &t, uint64_t &C, uint64_t &nslots,
                 uint64_t &D);
 

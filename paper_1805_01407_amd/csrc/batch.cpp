@@ -1,12 +1,12 @@
 // Batched generation: host planner and C ABI (slrng_batch_*).
 //
-// Planning (host): validate requests; per request with start > 0 compute the
-// start polynomial x^start mod p (request state kernel); cut requests into
-// lane-chunks; group by (variant, kind); sort by length; pack into tiles of
-// 64; order tiles heaviest first; upload descriptors.  Launch: either one
-// persistent kernel over all tiles (optionally captured once into a hipGraph
-// and replayed), or — the plain form used for comparison — one launch of the
-// same kernel per request.
+// Planning (host): validate requests; for requests that do not start at the
+// SplitMix64 origin compute the start polynomial x^start mod p (applied by the
+// request-state kernel); cut requests into lane-chunks; group by (variant,
+// kind); sort by length; pack into tiles of 64; order tiles heaviest first;
+// upload descriptors.  Launch: either one persistent kernel over all tiles
+// (optionally captured once into a hipGraph and replayed), or — the plain form
+// used for comparison — one launch of the same kernel per request.
 #include <hip/hip_runtime_api.h>
 #include <stdlib.h>
 #include <string.h>
@@ -21,6 +21,7 @@
 #include "../../include/slrng.h"
 #include "api_internal.hpp"
 #include "batch.hpp"
+#include "batch_plan.hpp"
 #include "engines.hpp"
 #include "f2poly.hpp"
 #include "kernels.hpp"
@@ -81,27 +82,194 @@ int chunk_table(int device, int engine, uint64_t C, uint32_t need, ChunkTable *o
 struct Lane {
   LaneDesc d;
   int variant, kind;
+  uint64_t unit;
 };
 
+// Relative cost of one output per variant (engine and scrambler work), for
+// ordering tiles heaviest first.
+uint64_t output_cost(int v) { return (v >= 6 && v <= 8) ? 3 : 2; }
+
 }  // namespace
+
+namespace slrng {
+
+int batch_grid_blocks(const slrng_batch_opts &o, int device, unsigned *blocks) {
+  int cus = 0;
+  hipError_t e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device);
+  if (e != hipSuccess) return hip_fail(e);
+  const int wpc = o.waves_per_cu ? o.waves_per_cu : 12;
+  *blocks = (unsigned)std::max(1, cus * wpc / (kBlock / kWave));
+  return SLRNG_OK;
+}
+
+int build_plan(const PlanReq *reqs, size_t n_reqs, const slrng_batch_opts &o, int device,
+               uint64_t grid_lanes, PlanHost &P) {
+  const bool plain = o.mode == SLRNG_BATCH_PLAIN;
+  // chunk length per variant: the option value, rounded up to the tile and
+  // raised if a request would need more than kMaxTable chunks
+  uint64_t C[kNumVariants];
+  uint64_t maxn[kNumVariants] = {0};
+  for (size_t r = 0; r < n_reqs; r++) maxn[reqs[r].variant] = std::max(maxn[reqs[r].variant], reqs[r].n);
+  for (int v = 0; v < kNumVariants; v++) {
+    uint64_t c = o.chunk[v] ? o.chunk[v] : 16384;
+    if (c > 0xffffffffull) c = 0xffffffffull & ~(uint64_t)63;
+    c = (c + o.tile - 1) / o.tile * o.tile;
+    const uint64_t need = (maxn[v] + kMaxTable - 1) / kMaxTable;
+    if (c < need) c = (need + o.tile - 1) / o.tile * o.tile;
+    if (c > 0xffffffffull) return SLRNG_ERANGE;
+    C[v] = c;
+  }
+  // request states: requests that start past their origin, and every request
+  // whose origin is a resident state
+  std::vector<uint32_t> req_slot(n_reqs, kNoReqState);
+  std::vector<std::vector<uint32_t>> by_var(kNumVariants);
+  uint32_t nslots = 0;
+  for (size_t r = 0; r < n_reqs; r++)
+    if ((reqs[r].start || reqs[r].from_state) && reqs[r].n) {
+      req_slot[r] = nslots++;
+      by_var[reqs[r].variant].push_back((uint32_t)r);
+    }
+  // The plain form runs each request alone, so each request is cut finely
+  // enough to fill the GPU by itself: chunk = the smallest power of two >= 1024
+  // giving at most one chunk per lane of the persistent grid (capped by C_v).
+  std::vector<uint64_t> req_chunk(n_reqs, 0);
+  std::vector<Lane> lanes;
+  uint32_t tab_need[kNumVariants] = {0};
+  P.total_outputs = 0;
+  for (size_t r = 0; r < n_reqs; r++) {
+    const PlanReq &q = reqs[r];
+    if (!q.n) continue;
+    P.total_outputs += q.n;
+    uint64_t c = C[q.variant];
+    if (plain) {
+      uint64_t want = 1024;
+      while (want < c && want * grid_lanes < q.n) want *= 2;
+      c = std::min<uint64_t>(c, std::max<uint64_t>(want, (q.n + kMaxTable - 1) / kMaxTable));
+      c = (c + o.tile - 1) / o.tile * o.tile;
+      req_chunk[r] = c;
+    }
+    const uint64_t nch = (q.n + c - 1) / c;
+    if (!plain) tab_need[q.variant] = std::max<uint32_t>(tab_need[q.variant], (uint32_t)nch);
+    for (uint64_t j = 0; j < nch; j++) {
+      Lane l;
+      l.variant = q.variant;
+      l.kind = q.kind;
+      l.unit = plain ? (uint64_t)r : 0;
+      l.d.seed = q.seed;
+      l.d.out = q.out + j * c * 8;
+      l.d.len = (uint32_t)std::min<uint64_t>(c, q.n - j * c);
+      l.d.jidx = (uint32_t)j;
+      l.d.req = req_slot[r];
+      l.d.pad = 0;
+      lanes.push_back(l);
+    }
+  }
+  for (int v = 0; v < kNumVariants; v++) {
+    P.tab[v] = nullptr;
+    P.tab_n[v] = 0;
+    if (!tab_need[v]) continue;
+    ChunkTable t;
+    int rc = chunk_table(device, variant_engine(v), C[v], tab_need[v], &t);
+    if (rc) return rc;
+    P.tab[v] = t.dev;
+    P.tab_n[v] = t.n;
+  }
+  // tiles: per unit (the whole batch, or one request), per (variant, kind),
+  // lanes sorted by length, 64 per tile; tiles heaviest first within a unit
+  std::stable_sort(lanes.begin(), lanes.end(), [](const Lane &x, const Lane &y) {
+    if (x.unit != y.unit) return x.unit < y.unit;
+    if (x.variant != y.variant) return x.variant < y.variant;
+    if (x.kind != y.kind) return x.kind < y.kind;
+    return x.d.len > y.d.len;
+  });
+  P.tiles.clear();
+  P.lanes.clear();
+  P.units.clear();
+  P.lanes.reserve(lanes.size());
+  size_t i = 0;
+  while (i < lanes.size()) {
+    const uint64_t unit = lanes[i].unit;
+    PlanUnit u;
+    u.tile0 = (uint32_t)P.tiles.size();
+    std::vector<std::pair<uint64_t, TileDesc>> tiles;
+    while (i < lanes.size() && lanes[i].unit == unit) {
+      size_t e2 = i;
+      while (e2 < lanes.size() && lanes[e2].unit == unit && lanes[e2].variant == lanes[i].variant &&
+             lanes[e2].kind == lanes[i].kind)
+        e2++;
+      for (size_t s = i; s < e2; s += kWave) {
+        const size_t cnt = std::min<size_t>(kWave, e2 - s);
+        TileDesc td;
+        td.variant = (uint8_t)lanes[s].variant;
+        td.kind = (uint8_t)lanes[s].kind;
+        td.nlanes = (uint8_t)cnt;
+        td.need_jump = 0;
+        td.max_len = lanes[s].d.len;  // sorted: the first is the longest
+        td.min_len = lanes[s + cnt - 1].d.len;
+        td.lane0 = (uint32_t)P.lanes.size();
+        for (size_t q = s; q < s + cnt; q++) {
+          if (lanes[q].d.jidx) td.need_jump = 1;
+          P.lanes.push_back(lanes[q].d);
+        }
+        tiles.push_back({(uint64_t)td.max_len * output_cost(td.variant), td});
+      }
+      i = e2;
+    }
+    std::stable_sort(tiles.begin(), tiles.end(),
+                     [](const std::pair<uint64_t, TileDesc> &x, const std::pair<uint64_t, TileDesc> &y) {
+                       return x.first > y.first;
+                     });
+    for (auto &t : tiles) P.tiles.push_back(t.second);
+    u.ntiles = (uint32_t)P.tiles.size() - u.tile0;
+    if (plain) {
+      const uint64_t c = req_chunk[unit];
+      ChunkTable t;
+      int rc = chunk_table(device, variant_engine(reqs[unit].variant), c,
+                           (uint32_t)((reqs[unit].n + c - 1) / c), &t);
+      if (rc) return rc;
+      u.req = (int64_t)reqs[unit].tag;
+      u.variant = reqs[unit].variant;
+      u.tab = t.dev;
+      u.tab_n = t.n;
+    }
+    P.units.push_back(u);
+  }
+  if (P.units.empty()) P.units.push_back(PlanUnit());
+  // request states, grouped by variant (one kernel launch per variant)
+  PlanReqStates &rs = P.rs;
+  rs = PlanReqStates();
+  rs.nslots = nslots;
+  for (int v = 0; v < kNumVariants; v++) {
+    if (by_var[v].empty()) continue;
+    const Field &f = engine_field(variant_engine(v));
+    for (uint32_t r : by_var[v]) {
+      rs.seeds.push_back(reqs[r].seed);
+      rs.origin_idx.push_back(reqs[r].origin_idx);
+      rs.slot.push_back(req_slot[r]);
+      Poly pr;
+      if (reqs[r].start) {
+        uint64_t J[1] = {reqs[r].start};
+        f.xpow(J, 1, pr);
+      } else {
+        pr.clear();
+        pr.w[0] = 1;
+      }
+      for (int w = 0; w < 16; w++) rs.polys.push_back(pr.w[w]);
+    }
+    rs.runs.push_back({v, (uint32_t)by_var[v].size()});
+  }
+  return SLRNG_OK;
+}
+
+}  // namespace slrng
 
 // ---------------------------------------------------------------- the batch object
 
 struct slrng_batch {
   int device = 0;
   slrng_batch_opts opts;
-  uint64_t n_requests = 0, total_outputs = 0;
-  // one plan per launch unit: a single unit for the batched forms, one per
-  // request for the plain form
-  struct Unit {
-    uint32_t tile0 = 0, ntiles = 0;
-    int64_t req = -1;           // plain form: the request
-    int variant = -1;           // plain form: the request's variant
-    const uint64_t *tab = nullptr;  // plain form: its chunk table
-    uint32_t tab_n = 0;
-  };
-  std::vector<Unit> units;
-  uint32_t ntiles = 0, nlanes = 0;
+  uint64_t n_requests = 0;
+  PlanHost plan;
   TileDesc *d_tiles = nullptr;
   LaneDesc *d_lanes = nullptr;
   uint64_t *d_req_state = nullptr;
@@ -130,14 +298,24 @@ extern "C" int slrng_batch_default_opts(slrng_batch_opts *o) {
   if (!o) return SLRNG_EINVAL;
   memset(o, 0, sizeof(*o));
   o->mode = SLRNG_BATCH_GRAPH;
-  o->tile = 16;
-  o->waves_per_cu = 12;
-  for (int v = 0; v < SLRNG_NUM_VARIANTS; v++) o->chunk[v] = (v == 9 || v == 10 || v == 11 || v == 13) ? 65536 : 16384;
+  o->tile = 32;
+  o->waves_per_cu = 8;
+  for (int v = 0; v < SLRNG_NUM_VARIANTS; v++)
+    o->chunk[v] = (v == 9 || v == 10 || v == 11 || v == 13) ? 65536 : 8192;
   return SLRNG_OK;
 }
 
-static int enqueue_unit(slrng_batch *b, const slrng_batch::Unit &u, unsigned *counter,
-                        hipStream_t st) {
+namespace slrng {
+int check_batch_opts(const slrng_batch_opts &o) {
+  if (o.mode != SLRNG_BATCH_GRAPH && o.mode != SLRNG_BATCH_PERSISTENT && o.mode != SLRNG_BATCH_PLAIN)
+    return SLRNG_EINVAL;
+  if (o.tile != 16 && o.tile != 32) return SLRNG_EINVAL;
+  if (o.waves_per_cu < 0 || o.waves_per_cu > 64) return SLRNG_EINVAL;
+  return SLRNG_OK;
+}
+}  // namespace slrng
+
+static int enqueue_unit(slrng_batch *b, const PlanUnit &u, unsigned *counter, hipStream_t st) {
   if (u.ntiles == 0) return SLRNG_OK;
   BatchArgs a = b->args;
   if (u.variant >= 0) {
@@ -154,17 +332,20 @@ static int enqueue_unit(slrng_batch *b, const slrng_batch::Unit &u, unsigned *co
   return e == hipSuccess ? SLRNG_OK : hip_fail(e);
 }
 
-// Enqueue the whole batch on `st` (no graph).
-static int enqueue_all(slrng_batch *b, hipStream_t st) {
+static int enqueue_req_states(slrng_batch *b, hipStream_t st) {
   for (auto &rl : b->req_launches) {
     hipError_t e = launch_req_state(rl.first, rl.second, st);
     if (e != hipSuccess) return hip_fail(e);
   }
-  for (size_t i = 0; i < b->units.size(); i++) {
-    int rc = enqueue_unit(b, b->units[i], b->d_counter + (b->units.size() > 1 ? i : 0), st);
-    if (rc) return rc;
-  }
   return SLRNG_OK;
+}
+
+// Enqueue the whole batch on `st` (no graph).
+static int enqueue_all(slrng_batch *b, hipStream_t st) {
+  int rc = enqueue_req_states(b, st);
+  for (size_t i = 0; i < b->plan.units.size() && !rc; i++)
+    rc = enqueue_unit(b, b->plan.units[i], b->d_counter + (b->plan.units.size() > 1 ? i : 0), st);
+  return rc;
 }
 
 extern "C" int slrng_batch_plan(const slrng_request *reqs, size_t n_reqs,
@@ -174,183 +355,34 @@ extern "C" int slrng_batch_plan(const slrng_request *reqs, size_t n_reqs,
   slrng_batch_opts o;
   if (opts) o = *opts;
   else slrng_batch_default_opts(&o);
-  if (o.mode != SLRNG_BATCH_GRAPH && o.mode != SLRNG_BATCH_PERSISTENT && o.mode != SLRNG_BATCH_PLAIN)
-    return SLRNG_EINVAL;
-  if (o.tile != 16 && o.tile != 32) return SLRNG_EINVAL;
-  if (o.waves_per_cu < 0 || o.waves_per_cu > 64) return SLRNG_EINVAL;
+  int rc = check_batch_opts(o);
+  if (rc) return rc;
   if (n_reqs > (1u << 24)) return SLRNG_ERANGE;
+  std::vector<PlanReq> pr(n_reqs);
   for (size_t r = 0; r < n_reqs; r++) {
     const slrng_request &q = reqs[r];
     if (!valid_variant(q.variant) || (q.kind != SLRNG_U64 && q.kind != SLRNG_F64)) return SLRNG_EINVAL;
     if (q.n && (!q.dev_out || ((uintptr_t)q.dev_out & 7))) return SLRNG_EINVAL;
     if (q.n > UINT64_MAX / 8) return SLRNG_ERANGE;
+    pr[r] = PlanReq{q.variant, q.kind, q.n, (uint64_t)(uintptr_t)q.dev_out, q.start, false, q.seed, 0,
+                    (uint64_t)r};
   }
   slrng_batch *b = new (std::nothrow) slrng_batch();
   if (!b) return SLRNG_ENOMEM;
   b->opts = o;
   b->n_requests = n_reqs;
-  int rc = SLRNG_OK;
   hipError_t e = hipGetDevice(&b->device);
   if (e != hipSuccess) {
     free_batch(b);
     return hip_fail(e);
   }
-  // chunk length per variant: the option value, rounded up to the tile and
-  // raised if a request would need more than kMaxTable chunks
-  uint64_t C[kNumVariants];
-  uint64_t maxn[kNumVariants] = {0};
-  for (size_t r = 0; r < n_reqs; r++) maxn[reqs[r].variant] = std::max(maxn[reqs[r].variant], reqs[r].n);
-  for (int v = 0; v < kNumVariants; v++) {
-    uint64_t c = o.chunk[v] ? o.chunk[v] : 16384;
-    if (c > 0xffffffffull) c = 0xffffffffull & ~(uint64_t)63;
-    c = (c + o.tile - 1) / o.tile * o.tile;
-    const uint64_t need = (maxn[v] + kMaxTable - 1) / kMaxTable;
-    if (c < need) c = (need + o.tile - 1) / o.tile * o.tile;
-    if (c > 0xffffffffull) {
-      free_batch(b);
-      return SLRNG_ERANGE;
-    }
-    C[v] = c;
-  }
-  // requests with a start offset: request-state slots and start polynomials
-  std::vector<uint32_t> req_slot(n_reqs, kNoReqState);
-  std::vector<std::vector<uint32_t>> by_var(kNumVariants);
-  uint32_t nslots = 0;
-  for (size_t r = 0; r < n_reqs; r++)
-    if (reqs[r].start && reqs[r].n) {
-      req_slot[r] = nslots++;
-      by_var[reqs[r].variant].push_back((uint32_t)r);
-    }
-  int cus = 0;
-  e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, b->device);
-  if (e != hipSuccess) {
+  rc = batch_grid_blocks(o, b->device, &b->blocks);
+  if (!rc) rc = build_plan(pr.data(), n_reqs, o, b->device, (uint64_t)b->blocks * kBlock, b->plan);
+  if (rc) {
     free_batch(b);
-    return hip_fail(e);
+    return rc;
   }
-  const int wpc = o.waves_per_cu ? o.waves_per_cu : 12;
-  b->blocks = (unsigned)std::max(1, cus * wpc / (kBlock / kWave));
-  const bool plain = o.mode == SLRNG_BATCH_PLAIN;
-  // The plain form runs each request alone, so each request is cut finely
-  // enough to fill the GPU by itself: chunk = the smallest power of two >= 1024
-  // giving at most one chunk per lane of the persistent grid (capped by C_v).
-  const uint64_t grid_lanes = (uint64_t)b->blocks * kBlock;
-  std::vector<uint64_t> req_chunk(n_reqs, 0);
-  // lanes
-  std::vector<Lane> lanes;
-  uint32_t tab_need[kNumVariants] = {0};
-  for (size_t r = 0; r < n_reqs; r++) {
-    const slrng_request &q = reqs[r];
-    if (!q.n) continue;
-    b->total_outputs += q.n;
-    uint64_t c = C[q.variant];
-    if (plain) {
-      uint64_t want = 1024;
-      while (want < c && want * grid_lanes < q.n) want *= 2;
-      c = std::min<uint64_t>(c, std::max<uint64_t>(want, (q.n + kMaxTable - 1) / kMaxTable));
-      c = (c + o.tile - 1) / o.tile * o.tile;
-      req_chunk[r] = c;
-    }
-    const uint64_t nch = (q.n + c - 1) / c;
-    if (!plain) tab_need[q.variant] = std::max<uint32_t>(tab_need[q.variant], (uint32_t)nch);
-    for (uint64_t j = 0; j < nch; j++) {
-      Lane l;
-      l.variant = q.variant;
-      l.kind = q.kind;
-      l.d.seed = q.seed;
-      l.d.out = (uint64_t)(uintptr_t)q.dev_out + j * c * 8;
-      l.d.len = (uint32_t)std::min<uint64_t>(c, q.n - j * c);
-      l.d.jidx = (uint32_t)j;
-      l.d.req = req_slot[r];
-      l.d.pad = (uint32_t)r;  // request index, used to split the plain form
-      lanes.push_back(l);
-    }
-  }
-  // tables
-  for (int v = 0; v < kNumVariants; v++) {
-    b->args.tab[v] = nullptr;
-    b->args.tab_n[v] = 0;
-    if (!tab_need[v]) continue;
-    ChunkTable t;
-    rc = chunk_table(b->device, variant_engine(v), C[v], tab_need[v], &t);
-    if (rc) {
-      free_batch(b);
-      return rc;
-    }
-    b->args.tab[v] = t.dev;
-    b->args.tab_n[v] = t.n;
-  }
-  // tiles: per unit (the whole batch, or one request), per (variant, kind),
-  // lanes sorted by length, 64 per tile; tiles heaviest first within a unit
-  std::vector<LaneDesc> h_lanes;
-  std::vector<TileDesc> h_tiles;
-  h_lanes.reserve(lanes.size());
-  auto key_of = [&](const Lane &l) -> std::tuple<uint64_t, int, int> {
-    return std::make_tuple(plain ? (uint64_t)l.d.pad : 0ull, l.variant, l.kind);
-  };
-  std::stable_sort(lanes.begin(), lanes.end(), [&](const Lane &x, const Lane &y) {
-    auto kx = key_of(x), ky = key_of(y);
-    if (kx != ky) return kx < ky;
-    return x.d.len > y.d.len;
-  });
-  // relative cost of one output per variant (engine and scrambler work)
-  auto cost = [](int v) -> uint64_t { return v >= 6 && v <= 8 ? 3 : (v >= 9 ? 2 : 2); };
-  size_t i = 0;
-  while (i < lanes.size()) {
-    const auto unit_key = std::get<0>(key_of(lanes[i]));
-    slrng_batch::Unit u;
-    u.tile0 = (uint32_t)h_tiles.size();
-    std::vector<std::pair<uint64_t, TileDesc>> tiles;
-    while (i < lanes.size() && std::get<0>(key_of(lanes[i])) == unit_key) {
-      const auto k = key_of(lanes[i]);
-      size_t e2 = i;
-      while (e2 < lanes.size() && key_of(lanes[e2]) == k) e2++;
-      for (size_t s = i; s < e2; s += kWave) {
-        const size_t cnt = std::min<size_t>(kWave, e2 - s);
-        TileDesc td;
-        td.variant = (uint8_t)lanes[s].variant;
-        td.kind = (uint8_t)lanes[s].kind;
-        td.nlanes = (uint8_t)cnt;
-        td.max_len = lanes[s].d.len;  // sorted: the first is the longest
-        td.min_len = lanes[s + cnt - 1].d.len;
-        td.lane0 = (uint32_t)(h_lanes.size());
-        td.need_jump = 0;
-        for (size_t q = s; q < s + cnt; q++) {
-          LaneDesc d = lanes[q].d;
-          if (d.jidx) td.need_jump = 1;
-          d.pad = 0;
-          h_lanes.push_back(d);
-        }
-        tiles.push_back({(uint64_t)td.max_len * cost(td.variant), td});
-      }
-      i = e2;
-    }
-    std::stable_sort(tiles.begin(), tiles.end(),
-                     [](const std::pair<uint64_t, TileDesc> &x, const std::pair<uint64_t, TileDesc> &y) {
-                       return x.first > y.first;
-                     });
-    for (auto &t : tiles) h_tiles.push_back(t.second);
-    u.ntiles = (uint32_t)h_tiles.size() - u.tile0;
-    if (plain) {
-      const size_t r = (size_t)unit_key;
-      const uint64_t c = req_chunk[r];
-      ChunkTable t;
-      rc = chunk_table(b->device, variant_engine(reqs[r].variant), c,
-                       (uint32_t)((reqs[r].n + c - 1) / c), &t);
-      if (rc) {
-        free_batch(b);
-        return rc;
-      }
-      u.req = (int64_t)r;
-      u.variant = reqs[r].variant;
-      u.tab = t.dev;
-      u.tab_n = t.n;
-    }
-    b->units.push_back(u);
-  }
-  if (b->units.empty()) b->units.push_back(slrng_batch::Unit());
-  b->ntiles = (uint32_t)h_tiles.size();
-  b->nlanes = (uint32_t)h_lanes.size();
-  // device buffers
+  const PlanHost &P = b->plan;
   auto upload = [&](void **dst, const void *src, size_t bytes) -> int {
     if (!bytes) return SLRNG_OK;
     hipError_t e3 = hipMalloc(dst, bytes);
@@ -358,42 +390,30 @@ extern "C" int slrng_batch_plan(const slrng_request *reqs, size_t n_reqs,
     e3 = hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice);
     return e3 == hipSuccess ? SLRNG_OK : hip_fail(e3);
   };
-  rc = upload((void **)&b->d_tiles, h_tiles.data(), h_tiles.size() * sizeof(TileDesc));
-  if (!rc) rc = upload((void **)&b->d_lanes, h_lanes.data(), h_lanes.size() * sizeof(LaneDesc));
+  rc = upload((void **)&b->d_tiles, P.tiles.data(), P.tiles.size() * sizeof(TileDesc));
+  if (!rc) rc = upload((void **)&b->d_lanes, P.lanes.data(), P.lanes.size() * sizeof(LaneDesc));
   if (!rc) {
-    std::vector<unsigned> zeros(b->units.size(), 0);
+    std::vector<unsigned> zeros(P.units.size(), 0);
     rc = upload((void **)&b->d_counter, zeros.data(), zeros.size() * sizeof(unsigned));
   }
-  if (!rc && nslots) {
-    e = hipMalloc(&b->d_req_state, (size_t)nslots * 16 * 8);
+  if (!rc && P.rs.nslots) {
+    e = hipMalloc(&b->d_req_state, (size_t)P.rs.nslots * 16 * 8);
     if (e != hipSuccess) rc = hip_fail(e);
-    std::vector<uint64_t> seeds, polys;
-    std::vector<uint32_t> slots;
-    for (int v = 0; v < kNumVariants && !rc; v++) {
-      if (by_var[v].empty()) continue;
-      const Field &f = engine_field(variant_engine(v));
-      for (uint32_t r : by_var[v]) {
-        seeds.push_back(reqs[r].seed);
-        slots.push_back(req_slot[r]);
-        Poly pr;
-        uint64_t J[1] = {reqs[r].start};
-        f.xpow(J, 1, pr);
-        for (int w = 0; w < 16; w++) polys.push_back(pr.w[w]);
-      }
-    }
-    if (!rc) rc = upload((void **)&b->d_req_seed, seeds.data(), seeds.size() * 8);
-    if (!rc) rc = upload((void **)&b->d_req_poly, polys.data(), polys.size() * 8);
-    if (!rc) rc = upload((void **)&b->d_req_slot, slots.data(), slots.size() * 4);
+    if (!rc) rc = upload((void **)&b->d_req_seed, P.rs.seeds.data(), P.rs.seeds.size() * 8);
+    if (!rc) rc = upload((void **)&b->d_req_poly, P.rs.polys.data(), P.rs.polys.size() * 8);
+    if (!rc) rc = upload((void **)&b->d_req_slot, P.rs.slot.data(), P.rs.slot.size() * 4);
     uint32_t off = 0;
-    for (int v = 0; v < kNumVariants && !rc; v++) {
-      if (by_var[v].empty()) continue;
+    for (size_t k = 0; k < P.rs.runs.size() && !rc; k++) {
       ReqArgs ra;
       ra.seeds = b->d_req_seed + off;
+      ra.origin_state = nullptr;
+      ra.origin_stride = 0;
+      ra.origin_idx = nullptr;
       ra.polys = b->d_req_poly + (size_t)off * 16;
       ra.slot = b->d_req_slot + off;
       ra.req_state = b->d_req_state;
-      ra.m = (uint32_t)by_var[v].size();
-      b->req_launches.push_back({v, ra});
+      ra.m = P.rs.runs[k].second;
+      b->req_launches.push_back({P.rs.runs[k].first, ra});
       off += ra.m;
     }
   }
@@ -402,11 +422,15 @@ extern "C" int slrng_batch_plan(const slrng_request *reqs, size_t n_reqs,
     return rc;
   }
   b->args.tiles = b->d_tiles;
-  b->args.ntiles = b->ntiles;
+  b->args.ntiles = (uint32_t)P.tiles.size();
   b->args.pad = 0;
   b->args.lanes = b->d_lanes;
   b->args.req_state = b->d_req_state;
   b->args.counter = b->d_counter;
+  for (int v = 0; v < kNumVariants; v++) {
+    b->args.tab[v] = P.tab[v];
+    b->args.tab_n[v] = P.tab_n[v];
+  }
   // graph: capture the whole enqueue sequence once
   if (o.mode == SLRNG_BATCH_GRAPH) {
     hipStream_t cs = nullptr;
@@ -452,7 +476,8 @@ extern "C" int slrng_batch_latencies(slrng_batch *b, hipStream_t stream, double 
   if (!b || !done_ms) return SLRNG_EINVAL;
   for (uint64_t r = 0; r < b->n_requests; r++) done_ms[r] = 0.0;
   const bool per_unit = b->opts.mode == SLRNG_BATCH_PLAIN;
-  std::vector<hipEvent_t> ev(per_unit ? b->units.size() + 1 : 2, nullptr);
+  const auto &units = b->plan.units;
+  std::vector<hipEvent_t> ev(per_unit ? units.size() + 1 : 2, nullptr);
   int rc = SLRNG_OK;
   for (auto &x : ev) {
     hipError_t e = hipEventCreate(&x);
@@ -472,15 +497,9 @@ extern "C" int slrng_batch_latencies(slrng_batch *b, hipStream_t stream, double 
       if (e != hipSuccess) rc = hip_fail(e);
     }
   } else if (!rc) {
-    for (auto &rl : b->req_launches) {
-      hipError_t e = launch_req_state(rl.first, rl.second, stream);
-      if (e != hipSuccess) {
-        rc = hip_fail(e);
-        break;
-      }
-    }
-    for (size_t i = 0; i < b->units.size() && !rc; i++) {
-      rc = enqueue_unit(b, b->units[i], b->d_counter + (b->units.size() > 1 ? i : 0), stream);
+    rc = enqueue_req_states(b, stream);
+    for (size_t i = 0; i < units.size() && !rc; i++) {
+      rc = enqueue_unit(b, units[i], b->d_counter + (units.size() > 1 ? i : 0), stream);
       if (!rc) {
         hipError_t e = hipEventRecord(ev[i + 1], stream);
         if (e != hipSuccess) rc = hip_fail(e);
@@ -498,11 +517,11 @@ extern "C" int slrng_batch_latencies(slrng_batch *b, hipStream_t stream, double 
       if (e != hipSuccess) rc = hip_fail(e);
       for (uint64_t r = 0; r < b->n_requests && !rc; r++) done_ms[r] = ms;
     } else {
-      for (size_t i = 0; i < b->units.size() && !rc; i++) {
+      for (size_t i = 0; i < units.size() && !rc; i++) {
         float ms = 0;
         hipError_t e = hipEventElapsedTime(&ms, ev[0], ev[i + 1]);
         if (e != hipSuccess) rc = hip_fail(e);
-        else if (b->units[i].req >= 0) done_ms[b->units[i].req] = ms;
+        else if (units[i].req >= 0) done_ms[units[i].req] = ms;
       }
     }
   }
@@ -514,9 +533,9 @@ extern "C" int slrng_batch_latencies(slrng_batch *b, hipStream_t stream, double 
 extern "C" int slrng_batch_info(const slrng_batch *b, uint64_t *n_tiles, uint64_t *n_lanes,
                                 uint64_t *total_outputs) {
   if (!b) return SLRNG_EINVAL;
-  if (n_tiles) *n_tiles = b->ntiles;
-  if (n_lanes) *n_lanes = b->nlanes;
-  if (total_outputs) *total_outputs = b->total_outputs;
+  if (n_tiles) *n_tiles = b->plan.tiles.size();
+  if (n_lanes) *n_lanes = b->plan.lanes.size();
+  if (total_outputs) *total_outputs = b->plan.total_outputs;
   return SLRNG_OK;
 }
 

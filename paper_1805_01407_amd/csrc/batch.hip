@@ -152,7 +152,13 @@ __global__ __launch_bounds__(kBlock) void k_req_state(ReqArgs a) {
   if (first >= a.m) return;
   const bool live = i < a.m;
   u64 s[K];
-  splitmix64_fill<K>(live ? a.seeds[i] : 0, s);
+  if (a.origin_state) {
+    const u64 j = live ? a.origin_idx[i] : 0;
+#pragma unroll
+    for (int w = 0; w < K; w++) s[w] = live ? a.origin_state[(u64)w * a.origin_stride + j] : 0;
+  } else {
+    splitmix64_fill<K>(live ? a.seeds[i] : 0, s);
+  }
   const unsigned pi = live ? i : 0;
   jump_lane<V>(s, [&](int wi) { return a.polys[(u64)pi * 16 + wi]; });
   if (live) {

@@ -49,13 +49,18 @@ struct BatchArgs {
   unsigned *counter;                  // tile claim counter (zeroed by k_batch_reset)
 };
 
-// Request start states for requests with start > 0: state of request r =
-// SplitMix64(seed) jumped by `start` (per-request polynomial, 16 words).
+// Request start states: the origin of request i (SplitMix64(seeds[i]), or, when
+// origin_state is set, word w of resident stream origin_idx[i] at
+// origin_state[w*origin_stride + origin_idx[i]]) jumped by its start position
+// (per-request polynomial, 16 words), written to req_state[slot[i]].
 struct ReqArgs {
-  const uint64_t *seeds;    // [m]
-  const uint64_t *polys;    // [m][16]
-  const uint32_t *slot;     // [m] index into req_state
-  uint64_t *req_state;      // [..][16]
+  const uint64_t *seeds;         // [m] (seed origins)
+  const uint64_t *origin_state;  // resident states, word-major, or null
+  uint64_t origin_stride;
+  const uint32_t *origin_idx;    // [m] (state origins)
+  const uint64_t *polys;         // [m][16]
+  const uint32_t *slot;          // [m] index into req_state
+  uint64_t *req_state;           // [..][16]
   uint32_t m;
 };
 

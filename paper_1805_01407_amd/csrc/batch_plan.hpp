@@ -1,0 +1,64 @@
+// Host planner of batched generation (internal): turns requests into tiles of
+// lane-chunks, shared by the batch API and the server.
+#pragma once
+#include <stdint.h>
+
+#include <vector>
+
+#include "../../include/slrng.h"
+#include "batch.hpp"
+
+namespace slrng {
+
+// One request as the planner sees it.  The origin is either SplitMix64(seed)
+// or the resident state `origin_idx` of a stream array (from_state).
+struct PlanReq {
+  int variant;
+  int kind;
+  uint64_t n;
+  uint64_t out;  // device address of the first output
+  uint64_t start;
+  bool from_state;
+  uint64_t seed;
+  uint32_t origin_idx;
+  uint64_t tag;  // caller's request index (the plain form's unit)
+};
+
+struct PlanUnit {
+  uint32_t tile0 = 0, ntiles = 0;
+  int64_t req = -1;               // plain form: the request index
+  int variant = -1;               // plain form: the request's variant
+  const uint64_t *tab = nullptr;  // plain form: its chunk table
+  uint32_t tab_n = 0;
+};
+
+// Requests whose start state is computed by the request-state kernel.
+struct PlanReqStates {
+  std::vector<uint64_t> seeds;       // per entry (seed origins)
+  std::vector<uint32_t> origin_idx;  // per entry (state origins)
+  std::vector<uint64_t> polys;       // 16 words per entry
+  std::vector<uint32_t> slot;        // request-state slot per entry
+  std::vector<std::pair<int, uint32_t>> runs;  // (variant, entries) in order
+  uint32_t nslots = 0;
+};
+
+struct PlanHost {
+  std::vector<TileDesc> tiles;
+  std::vector<LaneDesc> lanes;
+  std::vector<PlanUnit> units;
+  PlanReqStates rs;
+  const uint64_t *tab[kNumVariants] = {nullptr};
+  uint32_t tab_n[kNumVariants] = {0};
+  uint64_t total_outputs = 0;
+};
+
+// Builds the plan.  `grid_lanes` is the persistent grid size in lanes (used to
+// size the plain form's chunks); `from_state` requests always get a request
+// state.  Returns SLRNG_OK or an error code.
+int build_plan(const PlanReq *reqs, size_t n, const slrng_batch_opts &o, int device,
+               uint64_t grid_lanes, PlanHost &out);
+
+// The persistent grid (blocks of 4 waves) for the options on `device`.
+int batch_grid_blocks(const slrng_batch_opts &o, int device, unsigned *blocks);
+
+}  // namespace slrng

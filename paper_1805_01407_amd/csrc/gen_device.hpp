@@ -149,7 +149,6 @@ __device__ __forceinline__ void gen_tile_full(u64 (&s)[Params<V>::k], u64 *row) 
 template <int V, int KIND, int T>
 __device__ __forceinline__ int gen_tile_partial(u64 (&s)[Params<V>::k], u64 *row, int m) {
   constexpr int BLK = block_steps<V>();
-#pragma unroll
   for (int t0 = 0; t0 < T; t0 += BLK) {
     if (t0 >= m) break;
     static_for<BLK>([&](auto P) {

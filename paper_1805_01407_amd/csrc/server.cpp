@@ -1,0 +1,663 @@
+// Serving loop with continuous batching (slrng_server_*).
+//
+// The server keeps S streams resident on the device (positioned like
+// slrng_streams_create) and a device output arena of a fixed budget.
+//  * submit: admission reserves the request's output bytes in the arena (or
+//    returns EAGAIN / waits when the budget is full) and assigns it the next
+//    positions of its stream: pos = head[stream], head[stream] += n.  A
+//    request is thus fully defined by (stream, pos, n): its values are the
+//    stream's outputs pos .. pos+n-1, whatever else is in flight.
+//  * iteration thread: takes every pending request (up to max_batch), plans
+//    them as one batch (request start state = resident state jumped by pos,
+//    lane-chunks, tiles), copies the descriptors into one of `inflight`
+//    preallocated slots and launches [request-state kernel -> persistent
+//    generation kernel] on that slot's HIP stream.  Requests that arrive while
+//    earlier iterations run join the next iteration, which may run
+//    concurrently on another slot.
+//  * completion thread: waits for each iteration's event, stamps the
+//    completion time of its requests (latency = completion - submit), frees
+//    auto-released arena ranges and the slot.
+#include <hip/hip_runtime_api.h>
+#include <string.h>
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <condition_variable>
+#include <deque>
+#include <map>
+#include <mutex>
+#include <new>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "../../include/slrng.h"
+#include "api_internal.hpp"
+#include "batch.hpp"
+#include "batch_plan.hpp"
+#include "kernels.hpp"
+
+using namespace slrng;
+
+namespace {
+
+typedef std::chrono::steady_clock Clock;
+
+double secs(Clock::time_point a, Clock::time_point b) {
+  return std::chrono::duration<double>(b - a).count();
+}
+
+constexpr uint64_t kAlign = 256;  // arena allocation granularity (bytes)
+
+// First-fit allocator over [0, size) with coalescing.
+struct Arena {
+  std::map<uint64_t, uint64_t> free_;  // offset -> length
+  uint64_t size = 0, used = 0;
+  void init(uint64_t sz) {
+    size = sz;
+    free_.clear();
+    free_[0] = sz;
+    used = 0;
+  }
+  bool alloc(uint64_t bytes, uint64_t *off) {
+    bytes = (bytes + kAlign - 1) / kAlign * kAlign;
+    for (auto it = free_.begin(); it != free_.end(); ++it) {
+      if (it->second >= bytes) {
+        *off = it->first;
+        const uint64_t rest = it->second - bytes, start = it->first + bytes;
+        free_.erase(it);
+        if (rest) free_[start] = rest;
+        used += bytes;
+        return true;
+      }
+    }
+    return false;
+  }
+  void release(uint64_t off, uint64_t bytes) {
+    bytes = (bytes + kAlign - 1) / kAlign * kAlign;
+    used -= bytes;
+    auto it = free_.emplace(off, bytes).first;
+    auto nx = std::next(it);
+    if (nx != free_.end() && it->first + it->second == nx->first) {
+      it->second += nx->second;
+      free_.erase(nx);
+    }
+    if (it != free_.begin()) {
+      auto pv = std::prev(it);
+      if (pv->first + pv->second == it->first) {
+        pv->second += it->second;
+        free_.erase(it);
+      }
+    }
+  }
+};
+
+enum ReqState { R_PENDING = 0, R_INFLIGHT = 1, R_DONE = 2, R_FAILED = 3 };
+
+struct Req {
+  uint32_t stream;
+  int kind;
+  uint64_t n, pos, off;
+  bool auto_release;
+  int state;
+  Clock::time_point t_submit;
+};
+
+// One in-flight slot: a HIP stream, events and reusable descriptor buffers.
+struct Slot {
+  hipStream_t st = nullptr;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  bool busy = false;
+  size_t cap_tiles = 0, cap_lanes = 0, cap_req = 0;
+  TileDesc *d_tiles = nullptr, *h_tiles = nullptr;
+  LaneDesc *d_lanes = nullptr, *h_lanes = nullptr;
+  uint64_t *d_poly = nullptr, *h_poly = nullptr;
+  uint32_t *d_idx = nullptr, *h_idx = nullptr;
+  uint32_t *d_slot = nullptr, *h_slot = nullptr;
+  uint64_t *d_req_state = nullptr;
+  unsigned *d_counter = nullptr;
+};
+
+struct Iteration {
+  int slot;
+  std::vector<uint64_t> tickets;
+};
+
+}  // namespace
+
+struct slrng_server {
+  slrng_server_opts o;
+  slrng_batch_opts bo;
+  int device = 0;
+  unsigned blocks = 0;
+  slrng_streams *streams = nullptr;
+  uint8_t *arena_dev = nullptr;
+  Arena arena;
+  std::vector<uint64_t> head;
+
+  std::mutex mu;
+  std::condition_variable cv_work, cv_space, cv_done;
+  std::deque<uint64_t> pending;
+  std::unordered_map<uint64_t, Req> reqs;
+  uint64_t next_ticket = 1;
+  std::vector<Slot> slots;
+  std::deque<Iteration> inflight;
+  bool stop = false, worker_done = false;
+  int error = 0;
+  hipEvent_t ref = nullptr;                           // time origin of the busy intervals
+  std::vector<std::pair<double, double>> busy_ivals;  // device [start, end) ms per iteration
+  std::thread worker, completer;
+
+  // statistics
+  Clock::time_point t0;
+  std::vector<double> lat_us;
+  uint64_t submitted = 0, completed = 0, failed = 0, rejected = 0, outputs = 0;
+  uint64_t iterations = 0, max_inflight = 0, peak_reserved = 0, max_batch_seen = 0, batch_sum = 0;
+};
+
+template <typename T>
+static int grow_pair(T **d, T **h, size_t need, size_t &cap) {
+  if (need <= cap) return SLRNG_OK;
+  const size_t n = std::max<size_t>({need, cap * 2, 64});
+  if (*d) (void)hipFree(*d);
+  if (*h) (void)hipHostFree(*h);
+  *d = nullptr;
+  *h = nullptr;
+  cap = 0;
+  hipError_t e = hipMalloc((void **)d, n * sizeof(T));
+  if (e == hipSuccess) e = hipHostMalloc((void **)h, n * sizeof(T), hipHostMallocDefault);
+  if (e != hipSuccess) return hip_fail(e);
+  cap = n;
+  return SLRNG_OK;
+}
+
+// Make the slot's buffers hold `tiles` tiles, `lanes` lanes and `nreq`
+// request states (the slot is idle: its previous iteration has completed).
+static int slot_reserve(Slot &s, size_t tiles, size_t lanes, size_t nreq) {
+  int rc = grow_pair(&s.d_tiles, &s.h_tiles, tiles, s.cap_tiles);
+  if (!rc) rc = grow_pair(&s.d_lanes, &s.h_lanes, lanes, s.cap_lanes);
+  if (!rc && nreq > s.cap_req) {
+    const size_t n = std::max<size_t>({nreq, s.cap_req * 2, 64});
+    size_t c1 = 0, c2 = 0, c3 = 0;
+    rc = grow_pair(&s.d_poly, &s.h_poly, n * 16, c1);
+    if (!rc) rc = grow_pair(&s.d_idx, &s.h_idx, n, c2);
+    if (!rc) rc = grow_pair(&s.d_slot, &s.h_slot, n, c3);
+    if (!rc) {
+      if (s.d_req_state) (void)hipFree(s.d_req_state);
+      s.d_req_state = nullptr;
+      hipError_t e = hipMalloc(&s.d_req_state, n * 16 * 8);
+      if (e != hipSuccess) rc = hip_fail(e);
+      else s.cap_req = n;
+    }
+  }
+  return rc;
+}
+
+static void free_slot(Slot &s) {
+  void *d[] = {s.d_tiles, s.d_lanes, s.d_poly, s.d_idx, s.d_slot, s.d_req_state, s.d_counter};
+  for (void *p : d)
+    if (p) (void)hipFree(p);
+  void *h[] = {s.h_tiles, s.h_lanes, s.h_poly, s.h_idx, s.h_slot};
+  for (void *p : h)
+    if (p) (void)hipHostFree(p);
+  if (s.ev0) (void)hipEventDestroy(s.ev0);
+  if (s.ev1) (void)hipEventDestroy(s.ev1);
+  if (s.st) (void)hipStreamDestroy(s.st);
+}
+
+// Plan and launch one iteration on slot `si` (called by the worker without the lock).
+static int launch_iteration(slrng_server *sv, int si, const std::vector<PlanReq> &pr) {
+  Slot &s = sv->slots[si];
+  PlanHost P;
+  int rc = build_plan(pr.data(), pr.size(), sv->bo, sv->device, (uint64_t)sv->blocks * kBlock, P);
+  if (rc) return rc;
+  rc = slot_reserve(s, P.tiles.size(), P.lanes.size(), P.rs.seeds.size());
+  if (rc) return rc;
+  if (!P.tiles.empty()) memcpy(s.h_tiles, P.tiles.data(), P.tiles.size() * sizeof(TileDesc));
+  if (!P.lanes.empty()) memcpy(s.h_lanes, P.lanes.data(), P.lanes.size() * sizeof(LaneDesc));
+  if (!P.rs.polys.empty()) {
+    memcpy(s.h_poly, P.rs.polys.data(), P.rs.polys.size() * 8);
+    memcpy(s.h_idx, P.rs.origin_idx.data(), P.rs.origin_idx.size() * 4);
+    memcpy(s.h_slot, P.rs.slot.data(), P.rs.slot.size() * 4);
+  }
+  hipStream_t st = s.st;
+  hipError_t e = hipEventRecord(s.ev0, st);
+  if (e == hipSuccess && !P.tiles.empty())
+    e = hipMemcpyAsync(s.d_tiles, s.h_tiles, P.tiles.size() * sizeof(TileDesc), hipMemcpyHostToDevice, st);
+  if (e == hipSuccess && !P.lanes.empty())
+    e = hipMemcpyAsync(s.d_lanes, s.h_lanes, P.lanes.size() * sizeof(LaneDesc), hipMemcpyHostToDevice, st);
+  if (e == hipSuccess && !P.rs.polys.empty())
+    e = hipMemcpyAsync(s.d_poly, s.h_poly, P.rs.polys.size() * 8, hipMemcpyHostToDevice, st);
+  if (e == hipSuccess && !P.rs.origin_idx.empty())
+    e = hipMemcpyAsync(s.d_idx, s.h_idx, P.rs.origin_idx.size() * 4, hipMemcpyHostToDevice, st);
+  if (e == hipSuccess && !P.rs.slot.empty())
+    e = hipMemcpyAsync(s.d_slot, s.h_slot, P.rs.slot.size() * 4, hipMemcpyHostToDevice, st);
+  if (e != hipSuccess) return hip_fail(e);
+  uint32_t off = 0;
+  for (auto &run : P.rs.runs) {
+    ReqArgs ra;
+    ra.seeds = nullptr;
+    ra.origin_state = streams_state_ptr(sv->streams);
+    ra.origin_stride = sv->o.n_streams;
+    ra.origin_idx = s.d_idx + off;
+    ra.polys = s.d_poly + (size_t)off * 16;
+    ra.slot = s.d_slot + off;
+    ra.req_state = s.d_req_state;
+    ra.m = run.second;
+    e = launch_req_state(run.first, ra, st);
+    if (e != hipSuccess) return hip_fail(e);
+    off += run.second;
+  }
+  if (!P.tiles.empty()) {
+    BatchArgs a;
+    memset(&a, 0, sizeof(a));
+    a.tiles = s.d_tiles;
+    a.ntiles = (uint32_t)P.tiles.size();
+    a.lanes = s.d_lanes;
+    a.req_state = s.d_req_state;
+    for (int v = 0; v < kNumVariants; v++) {
+      a.tab[v] = P.tab[v];
+      a.tab_n[v] = P.tab_n[v];
+    }
+    a.counter = s.d_counter;
+    e = launch_batch_reset(s.d_counter, st);
+    if (e != hipSuccess) return hip_fail(e);
+    const unsigned blocks = std::min<unsigned>(sv->blocks, ((unsigned)P.tiles.size() + 3) / 4);
+    e = launch_batch(a, sv->bo.tile, blocks, st);
+    if (e != hipSuccess) return hip_fail(e);
+  }
+  e = hipEventRecord(s.ev1, st);
+  return e == hipSuccess ? SLRNG_OK : hip_fail(e);
+}
+
+static void worker_main(slrng_server *sv) {
+  (void)hipSetDevice(sv->device);
+  std::unique_lock<std::mutex> lk(sv->mu);
+  for (;;) {
+    int si = -1;
+    sv->cv_work.wait(lk, [&] {
+      if (sv->pending.empty()) return sv->stop;
+      for (size_t i = 0; i < sv->slots.size(); i++)
+        if (!sv->slots[i].busy) return true;
+      return false;
+    });
+    if (sv->pending.empty()) {  // stop requested and nothing left to launch
+      sv->worker_done = true;
+      sv->cv_done.notify_all();
+      return;
+    }
+    for (size_t i = 0; i < sv->slots.size(); i++)
+      if (!sv->slots[i].busy) {
+        si = (int)i;
+        break;
+      }
+    if (si < 0) continue;
+    Iteration it;
+    it.slot = si;
+    std::vector<PlanReq> pr;
+    const size_t take = std::min<size_t>(sv->pending.size(), (size_t)sv->o.max_batch);
+    for (size_t k = 0; k < take; k++) {
+      const uint64_t t = sv->pending.front();
+      sv->pending.pop_front();
+      Req &q = sv->reqs[t];
+      q.state = R_INFLIGHT;
+      it.tickets.push_back(t);
+      pr.push_back(PlanReq{sv->o.variant, q.kind, q.n, (uint64_t)(uintptr_t)(sv->arena_dev + q.off), q.pos,
+                           true, 0, q.stream, (uint64_t)k});
+    }
+    sv->slots[si].busy = true;
+    lk.unlock();
+    const int rc = launch_iteration(sv, si, pr);
+    lk.lock();
+    if (rc) {
+      // the launch failed: fail exactly these requests and free the slot
+      sv->error = rc;
+      for (uint64_t t : it.tickets) {
+        auto f = sv->reqs.find(t);
+        if (f == sv->reqs.end()) continue;
+        f->second.state = R_FAILED;
+        sv->failed++;
+        if (f->second.auto_release) {
+          sv->arena.release(f->second.off, f->second.n * 8);
+          sv->reqs.erase(f);
+        }
+      }
+      sv->slots[si].busy = false;
+      sv->cv_done.notify_all();
+      sv->cv_space.notify_all();
+      continue;
+    }
+    sv->iterations++;
+    sv->batch_sum += it.tickets.size();
+    sv->max_batch_seen = std::max<uint64_t>(sv->max_batch_seen, it.tickets.size());
+    sv->inflight.push_back(std::move(it));
+    sv->max_inflight = std::max<uint64_t>(sv->max_inflight, sv->inflight.size());
+    sv->cv_done.notify_all();  // wakes the completion thread
+  }
+}
+
+static void completer_main(slrng_server *sv) {
+  (void)hipSetDevice(sv->device);
+  std::unique_lock<std::mutex> lk(sv->mu);
+  for (;;) {
+    sv->cv_done.wait(lk, [&] { return sv->worker_done || !sv->inflight.empty(); });
+    if (sv->inflight.empty()) return;  // the worker has exited and all work completed
+    Iteration it = sv->inflight.front();
+    sv->inflight.pop_front();
+    Slot &s = sv->slots[it.slot];
+    lk.unlock();
+    hipError_t e = hipEventSynchronize(s.ev1);
+    const Clock::time_point now = Clock::now();
+    float a = 0, b = 0;
+    if (e == hipSuccess) {
+      (void)hipEventElapsedTime(&a, sv->ref, s.ev0);
+      (void)hipEventElapsedTime(&b, sv->ref, s.ev1);
+    }
+    lk.lock();
+    if (e == hipSuccess) sv->busy_ivals.push_back({a, b});
+    for (uint64_t t : it.tickets) {
+      auto f = sv->reqs.find(t);
+      if (f == sv->reqs.end()) continue;
+      Req &q = f->second;
+      if (e == hipSuccess) {
+        q.state = R_DONE;
+        sv->completed++;
+        sv->outputs += q.n;
+        sv->lat_us.push_back(secs(q.t_submit, now) * 1e6);
+      } else {
+        q.state = R_FAILED;
+        sv->failed++;
+        sv->error = hip_fail(e);
+      }
+      if (q.auto_release) {
+        sv->arena.release(q.off, q.n * 8);
+        sv->reqs.erase(f);
+      }
+    }
+    s.busy = false;
+    sv->cv_work.notify_all();
+    sv->cv_space.notify_all();
+    sv->cv_done.notify_all();
+  }
+}
+
+extern "C" int slrng_server_default_opts(slrng_server_opts *o) {
+  if (!o) return SLRNG_EINVAL;
+  memset(o, 0, sizeof(*o));
+  o->budget_bytes = 16ull << 30;
+  o->n_streams = 4096;
+  o->variant = SLRNG_XOSHIRO256_STARSTAR;
+  o->seed = 42;
+  o->max_batch = 4096;
+  o->inflight = 3;
+  o->tile = 32;
+  o->waves_per_cu = 8;
+  o->chunk = 0;
+  return SLRNG_OK;
+}
+
+static void destroy_server(slrng_server *sv) {
+  {
+    std::lock_guard<std::mutex> g(sv->mu);
+    sv->stop = true;
+  }
+  sv->cv_work.notify_all();
+  sv->cv_done.notify_all();
+  sv->cv_space.notify_all();
+  if (sv->worker.joinable()) sv->worker.join();
+  // the worker has launched everything it took; wait for those iterations
+  {
+    std::unique_lock<std::mutex> lk(sv->mu);
+    sv->cv_done.notify_all();
+  }
+  if (sv->completer.joinable()) sv->completer.join();
+  for (auto &s : sv->slots) {
+    if (s.st) (void)hipStreamSynchronize(s.st);
+    free_slot(s);
+  }
+  if (sv->ref) (void)hipEventDestroy(sv->ref);
+  if (sv->arena_dev) (void)hipFree(sv->arena_dev);
+  if (sv->streams) slrng_streams_destroy(sv->streams);
+  delete sv;
+}
+
+extern "C" int slrng_server_create(const slrng_server_opts *opts, slrng_server **out) {
+  if (!out) return SLRNG_EINVAL;
+  *out = nullptr;
+  slrng_server_opts o;
+  if (opts) o = *opts;
+  else slrng_server_default_opts(&o);
+  if (!valid_variant(o.variant) || o.n_streams == 0 || o.budget_bytes < kAlign) return SLRNG_EINVAL;
+  if (o.max_batch <= 0) o.max_batch = 4096;
+  if (o.inflight <= 0) o.inflight = 3;
+  if (o.inflight > 8) return SLRNG_EINVAL;
+  if (o.tile == 0) o.tile = 32;
+  slrng_batch_opts bo;
+  slrng_batch_default_opts(&bo);
+  bo.mode = SLRNG_BATCH_PERSISTENT;
+  bo.tile = o.tile;
+  bo.waves_per_cu = o.waves_per_cu;
+  if (o.chunk) bo.chunk[o.variant] = o.chunk;
+  int rc = check_batch_opts(bo);
+  if (rc) return rc;
+  slrng_server *sv = new (std::nothrow) slrng_server();
+  if (!sv) return SLRNG_ENOMEM;
+  sv->o = o;
+  sv->bo = bo;
+  hipError_t e = hipGetDevice(&sv->device);
+  if (e != hipSuccess) {
+    delete sv;
+    return hip_fail(e);
+  }
+  rc = batch_grid_blocks(bo, sv->device, &sv->blocks);
+  if (!rc) rc = slrng_streams_create(o.variant, o.seed, o.n_streams, nullptr, &sv->streams);
+  if (!rc) {
+    e = hipDeviceSynchronize();
+    if (e != hipSuccess) rc = hip_fail(e);
+  }
+  if (!rc) {
+    e = hipMalloc(&sv->arena_dev, o.budget_bytes);
+    if (e != hipSuccess) rc = e == hipErrorOutOfMemory ? SLRNG_ENOMEM : hip_fail(e);
+  }
+  if (!rc) {
+    sv->arena.init(o.budget_bytes / kAlign * kAlign);
+    sv->head.assign(o.n_streams, 0);
+    sv->slots.resize(o.inflight);
+    for (auto &s : sv->slots) {
+      e = hipStreamCreateWithFlags(&s.st, hipStreamNonBlocking);
+      if (e == hipSuccess) e = hipEventCreate(&s.ev0);
+      if (e == hipSuccess) e = hipEventCreate(&s.ev1);
+      if (e == hipSuccess) e = hipMalloc(&s.d_counter, sizeof(unsigned));
+      if (e != hipSuccess) {
+        rc = hip_fail(e);
+        break;
+      }
+    }
+  }
+  if (!rc) {
+    e = hipEventCreate(&sv->ref);
+    if (e == hipSuccess) e = hipEventRecord(sv->ref, sv->slots[0].st);
+    if (e == hipSuccess) e = hipEventSynchronize(sv->ref);
+    if (e != hipSuccess) rc = hip_fail(e);
+  }
+  if (rc) {
+    sv->worker_done = true;
+    destroy_server(sv);
+    return rc;
+  }
+  sv->t0 = Clock::now();
+  sv->worker = std::thread(worker_main, sv);
+  sv->completer = std::thread(completer_main, sv);
+  *out = sv;
+  return SLRNG_OK;
+}
+
+extern "C" int slrng_server_destroy(slrng_server *sv) {
+  if (!sv) return SLRNG_EINVAL;
+  destroy_server(sv);
+  return SLRNG_OK;
+}
+
+extern "C" int slrng_server_submit(slrng_server *sv, uint32_t stream_id, uint64_t n, int kind,
+                                   int flags, uint64_t *ticket) {
+  if (!sv || !ticket || (kind != SLRNG_U64 && kind != SLRNG_F64)) return SLRNG_EINVAL;
+  if (stream_id >= sv->o.n_streams || n == 0) return SLRNG_EINVAL;
+  if (n > sv->arena.size / 8) return SLRNG_ERANGE;
+  std::unique_lock<std::mutex> lk(sv->mu);
+  uint64_t off = 0;
+  for (;;) {
+    if (sv->stop) return SLRNG_EINVAL;
+    if (sv->arena.alloc(n * 8, &off)) break;
+    if (flags & SLRNG_SUBMIT_NONBLOCK) {
+      sv->rejected++;
+      return SLRNG_EAGAIN;
+    }
+    sv->cv_space.wait(lk);
+  }
+  sv->peak_reserved = std::max(sv->peak_reserved, sv->arena.used);
+  Req q;
+  q.stream = stream_id;
+  q.kind = kind;
+  q.n = n;
+  q.pos = sv->head[stream_id];
+  sv->head[stream_id] += n;
+  q.off = off;
+  q.auto_release = (flags & SLRNG_SUBMIT_AUTORELEASE) != 0;
+  q.state = R_PENDING;
+  q.t_submit = Clock::now();
+  const uint64_t t = sv->next_ticket++;
+  sv->reqs.emplace(t, q);
+  sv->pending.push_back(t);
+  sv->submitted++;
+  *ticket = t;
+  sv->cv_work.notify_one();
+  return SLRNG_OK;
+}
+
+extern "C" int slrng_server_poll(slrng_server *sv, uint64_t ticket, void **dev_ptr, uint64_t *pos) {
+  if (!sv) return SLRNG_EINVAL;
+  std::lock_guard<std::mutex> g(sv->mu);
+  auto f = sv->reqs.find(ticket);
+  if (f == sv->reqs.end()) return SLRNG_EINVAL;
+  if (dev_ptr) *dev_ptr = sv->arena_dev + f->second.off;
+  if (pos) *pos = f->second.pos;
+  if (f->second.state == R_FAILED) return SLRNG_EHIP;
+  return f->second.state == R_DONE ? 1 : 0;
+}
+
+extern "C" int slrng_server_wait(slrng_server *sv, uint64_t ticket, void **dev_ptr, uint64_t *pos) {
+  if (!sv) return SLRNG_EINVAL;
+  std::unique_lock<std::mutex> lk(sv->mu);
+  for (;;) {
+    auto f = sv->reqs.find(ticket);
+    if (f == sv->reqs.end()) return SLRNG_EINVAL;
+    if (dev_ptr) *dev_ptr = sv->arena_dev + f->second.off;
+    if (pos) *pos = f->second.pos;
+    if (f->second.state == R_FAILED) return SLRNG_EHIP;
+    if (f->second.state == R_DONE) return SLRNG_OK;
+    sv->cv_done.wait(lk);
+  }
+}
+
+extern "C" int slrng_server_release(slrng_server *sv, uint64_t ticket) {
+  if (!sv) return SLRNG_EINVAL;
+  std::lock_guard<std::mutex> g(sv->mu);
+  auto f = sv->reqs.find(ticket);
+  if (f == sv->reqs.end() || f->second.auto_release) return SLRNG_EINVAL;
+  if (f->second.state != R_DONE && f->second.state != R_FAILED) return SLRNG_EAGAIN;
+  sv->arena.release(f->second.off, f->second.n * 8);
+  sv->reqs.erase(f);
+  sv->cv_space.notify_all();
+  return SLRNG_OK;
+}
+
+extern "C" int slrng_server_drain(slrng_server *sv) {
+  if (!sv) return SLRNG_EINVAL;
+  std::unique_lock<std::mutex> lk(sv->mu);
+  sv->cv_done.wait(lk, [&] {
+    if (!sv->pending.empty() || !sv->inflight.empty()) return false;
+    for (auto &s : sv->slots)
+      if (s.busy) return false;
+    return true;
+  });
+  return sv->error ? sv->error : SLRNG_OK;
+}
+
+extern "C" int slrng_server_get_stats(slrng_server *sv, slrng_server_stats *out) {
+  if (!sv || !out) return SLRNG_EINVAL;
+  std::vector<double> lat;
+  {
+    std::lock_guard<std::mutex> g(sv->mu);
+    memset(out, 0, sizeof(*out));
+    out->submitted = sv->submitted;
+    out->completed = sv->completed;
+    out->failed = sv->failed;
+    out->rejected = sv->rejected;
+    out->outputs = sv->outputs;
+    out->wall_s = secs(sv->t0, Clock::now());
+    // union of the iterations' device intervals (iterations may overlap)
+    std::vector<std::pair<double, double>> iv = sv->busy_ivals;
+    std::sort(iv.begin(), iv.end());
+    double busy = 0, cs = 0, ce = -1;
+    for (auto &x : iv) {
+      if (x.first > ce) {
+        if (ce > cs) busy += ce - cs;
+        cs = x.first;
+        ce = x.second;
+      } else {
+        ce = std::max(ce, x.second);
+      }
+    }
+    if (ce > cs) busy += ce - cs;
+    out->busy_s = busy * 1e-3;
+    out->iterations = sv->iterations;
+    out->max_inflight = sv->max_inflight;
+    out->peak_reserved_bytes = sv->peak_reserved;
+    out->reserved_bytes = sv->arena.used;
+    out->max_batch = sv->max_batch_seen;
+    out->mean_batch = sv->iterations ? (double)sv->batch_sum / sv->iterations : 0.0;
+    lat = sv->lat_us;
+  }
+  if (!lat.empty()) {
+    std::sort(lat.begin(), lat.end());
+    auto q = [&](double p) { return lat[std::min(lat.size() - 1, (size_t)(p * (lat.size() - 1) + 0.5))]; };
+    out->p50_us = q(0.50);
+    out->p99_us = q(0.99);
+    out->max_us = lat.back();
+  }
+  return SLRNG_OK;
+}
+
+extern "C" int slrng_server_reset_stats(slrng_server *sv) {
+  if (!sv) return SLRNG_EINVAL;
+  std::lock_guard<std::mutex> g(sv->mu);
+  sv->t0 = Clock::now();
+  sv->lat_us.clear();
+  sv->submitted = sv->completed = sv->failed = sv->rejected = sv->outputs = 0;
+  sv->iterations = sv->max_inflight = sv->max_batch_seen = sv->batch_sum = 0;
+  sv->peak_reserved = sv->arena.used;
+  sv->busy_ivals.clear();
+  return SLRNG_OK;
+}
+
+extern "C" int slrng_server_replay(slrng_server *sv, const double *t_arrival_s, const uint32_t *stream_ids,
+                                   const uint64_t *n, const int32_t *kinds, size_t count) {
+  if (!sv || (count && (!t_arrival_s || !stream_ids || !n || !kinds))) return SLRNG_EINVAL;
+  const Clock::time_point start = Clock::now();
+  for (size_t i = 0; i < count; i++) {
+    const auto due = start + std::chrono::duration_cast<Clock::duration>(
+                                 std::chrono::duration<double>(t_arrival_s[i]));
+    // sleep until close to the arrival, then spin for the last stretch
+    while (true) {
+      const auto now = Clock::now();
+      if (now >= due) break;
+      if (due - now > std::chrono::microseconds(200))
+        std::this_thread::sleep_for(due - now - std::chrono::microseconds(100));
+    }
+    uint64_t t = 0;
+    int rc = slrng_server_submit(sv, stream_ids[i], n[i], kinds[i], SLRNG_SUBMIT_AUTORELEASE, &t);
+    if (rc) return rc;
+  }
+  return slrng_server_drain(sv);
+}

@@ -9,6 +9,10 @@ uniform over the eight swept variants, length floor(2^(24 U)) with U uniform
 in [0, 1) (log-uniform in [1, 2^24)), doubles with probability 0.3, origin
 seed r + 1, start position 0.  Outputs are laid out in one arena, each request
 aligned to 256 bytes.
+
+serve_trace: the serving workload — Poisson arrivals at `rate` requests per
+second for `seconds`, each on a stream uniform in [0, streams), asking for
+floor(bytes / 8) uint64 outputs with bytes log-uniform in [64 B, 256 MiB].
 """
 from __future__ import annotations
 
@@ -39,3 +43,21 @@ def batch_requests(count: int = 10000, seed: int = 4, max_log2: int = 24, p_doub
     arena = int(padded.sum())
     return {"variant": variant, "kind": kind, "seed": seeds, "start": start, "n": n,
             "offset": offset, "arena_elems": arena}
+
+
+def serve_trace(rate: float = 20000.0, seconds: float = 60.0, streams: int = 4096,
+                min_bytes: int = 64, max_bytes: int = 1 << 28, seed: int = 5,
+                p_double: float = 0.0):
+    """Returns dict of arrays: arrival time (s), stream id, n, kind."""
+    rng = np.random.default_rng(seed)
+    count = int(rate * seconds * 1.2) + 16
+    gaps = rng.exponential(1.0 / rate, count)
+    t = np.cumsum(gaps)
+    t = t[t < seconds]
+    m = t.size
+    sid = rng.integers(0, streams, m).astype(np.uint32)
+    lo, hi = np.log(min_bytes), np.log(max_bytes)
+    nbytes = np.exp(lo + (hi - lo) * rng.random(m))
+    n = np.maximum(np.floor(nbytes / 8.0), 1).astype(np.uint64)
+    kind = (rng.random(m) < p_double).astype(np.int32)
+    return {"t": t, "stream": sid, "n": n, "kind": kind}

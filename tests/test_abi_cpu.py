@@ -140,3 +140,28 @@ def test_request_record_layout(P):
     r = P.make_requests([1, 2], 1, [5, 6], 0, 7, [8, 16])
     assert r["variant"].tolist() == [1, 2] and r["seed"].tolist() == [5, 6]
     assert r["dev_out"].tolist() == [8, 16]
+
+
+def test_server_argument_errors_before_any_device_call(P):
+    for kw in ({"n_streams": 0}, {"variant": 14}, {"budget_bytes": 16}, {"inflight": 9}):
+        o = P.slrng_server_default_opts(**kw)
+        with pytest.raises(P.SlrngError) as e:
+            P.slrng_server_create(o)
+        assert e.value.name == "EINVAL"
+    L = P.lib()
+    t = ctypes.c_uint64()
+    assert L.slrng_server_submit(None, 0, 1, 0, 0, ctypes.byref(t)) == -1
+    assert L.slrng_server_drain(None) == -1
+    assert L.slrng_server_destroy(None) == -1
+
+
+def test_serve_trace_shape():
+    from paper_1805_01407_amd import workloads as W
+    tr = W.serve_trace(rate=20000, seconds=1.0)
+    m = tr["t"].size
+    assert 19000 < m < 21000
+    assert np.all(np.diff(tr["t"]) >= 0) and tr["t"][-1] < 1.0
+    assert tr["n"].min() >= 8 and tr["n"].max() <= (1 << 28) // 8
+    assert tr["stream"].max() < 4096
+    mean_bytes = float((tr["n"] * 8).mean())
+    assert 8e6 < mean_bytes < 3e7  # log-uniform 64 B .. 256 MiB: mean about 17.6 MB

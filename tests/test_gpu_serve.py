@@ -1,0 +1,163 @@
+"""GPU tests of the serving loop: every served request equals the oracle and the
+same request run alone (a fresh handle advanced to the request's position);
+admission never exceeds the budget; requests submitted while others are in
+flight are batched into overlapping iterations."""
+import ctypes
+import sys
+import threading
+
+import numpy as np
+import pytest
+
+import oracle as O
+
+pytestmark = pytest.mark.gpu
+
+NAME = "xoshiro256**"
+
+
+@pytest.fixture(scope="module")
+def P():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1805_01407_amd as P
+    P.lib()
+    return P
+
+
+def announce(*a):
+    print("[case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+def d2h(ptr, n):
+    """Copy n uint64 from a device address (HIP runtime, the one torch loaded)."""
+    import torch  # noqa: F401
+    hip = ctypes.CDLL("libamdhip64.so.7")
+    hip.hipMemcpy.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int]
+    out = np.zeros(n, dtype=np.uint64)
+    rc = hip.hipMemcpy(out.ctypes.data, ptr, n * 8, 2)  # hipMemcpyDeviceToHost
+    assert rc == 0
+    return out
+
+
+def expected(chain, stream, pos, n, kind=0):
+    g = O.GEN64[NAME]
+    x = O.jump(g, chain[stream], pos) if pos else chain[stream]
+    out, _ = O.generate(g, x, n)
+    if kind == 1:
+        out = ((out >> np.uint64(11)).astype(np.float64) * 2.0**-53).view(np.uint64)
+    return out
+
+
+def test_served_requests_match_oracle_and_alone(P):
+    S = 64
+    chain = O.stream_chain(O.GEN64[NAME], 42, S)
+    opts = P.slrng_server_default_opts(n_streams=S, budget_bytes=256 << 20, seed=42, variant=NAME,
+                                       inflight=3)
+    sv = P.slrng_server_create(opts)
+    results = {}
+    lock = threading.Lock()
+    try:
+        def client(cid):
+            rng = np.random.default_rng(cid)
+            for k in range(60):
+                stream = int(rng.integers(0, 8))  # few streams: many requests per stream
+                n = int(rng.choice([1, 7, 33, 1000, 5000, 20000, 70000]))
+                kind = int(rng.integers(0, 2))
+                t = P.slrng_server_submit(sv, stream, n, kind)
+                with lock:
+                    results[t] = (stream, n, kind)
+        ths = [threading.Thread(target=client, args=(c,)) for c in range(4)]
+        for th in ths:
+            th.start()
+        for th in ths:
+            th.join()
+        announce("served", len(results))
+        got = {}
+        for t, (stream, n, kind) in results.items():
+            ptr, pos = P.slrng_server_wait(sv, t)
+            got[t] = (pos, d2h(ptr, n))
+            P.slrng_server_release(sv, t)
+        st = P.slrng_server_get_stats(sv)
+    finally:
+        P.slrng_server_destroy(sv)
+    # positions on each stream are consecutive in admission (ticket) order
+    heads = {}
+    for t in sorted(results):
+        stream, n, kind = results[t]
+        pos, out = got[t]
+        assert pos == heads.get(stream, 0)
+        heads[stream] = pos + n
+        assert np.array_equal(out, expected(chain, stream, pos, n, kind)), (t, stream, pos, n)
+    assert st["completed"] == len(results) and st["failed"] == 0
+    # the same requests alone: a fresh handle at the stream state, advanced to pos
+    for t in sorted(results)[::17]:
+        stream, n, kind = results[t]
+        pos, out = got[t]
+        with P.Streams(NAME, states=chain[stream]) as h:
+            h.advance(pos)
+            alone = h.generate(n, kind).cpu().numpy().view(np.uint64)[0]
+        assert np.array_equal(alone, out)
+
+
+def test_budget_admission_and_overlap(P):
+    import time
+    S = 16
+    budget = 1 << 20  # 1 MiB arena
+    opts = P.slrng_server_default_opts(n_streams=S, budget_bytes=budget, seed=7, variant=NAME,
+                                       inflight=3)
+    sv = P.slrng_server_create(opts)
+    try:
+        # fill the arena with unreleased requests, then a non-blocking submit
+        # that does not fit is rejected
+        held = [P.slrng_server_submit(sv, i % S, 16384) for i in range(8)]  # 8 x 128 KiB
+        for t in held:
+            P.slrng_server_wait(sv, t)
+        with pytest.raises(P.SlrngError) as e:
+            P.slrng_server_submit(sv, 0, 1, flags=P.SLRNG_SUBMIT_NONBLOCK)
+        assert e.value.name == "EAGAIN"
+        # a blocking submit waits until a release makes room
+        done = []
+
+        def blocked():
+            done.append(P.slrng_server_submit(sv, 1, 16384))
+        th = threading.Thread(target=blocked)
+        th.start()
+        time.sleep(0.2)
+        assert not done
+        P.slrng_server_release(sv, held[0])
+        th.join(timeout=30)
+        assert done
+        P.slrng_server_wait(sv, done[0])
+        P.slrng_server_release(sv, done[0])
+        for t in held[1:]:
+            P.slrng_server_release(sv, t)
+        # a burst of auto-released requests: iterations overlap on the device
+        P.slrng_server_reset_stats(sv)
+        for i in range(3000):
+            P.slrng_server_submit(sv, i % S, 8000, flags=P.SLRNG_SUBMIT_AUTORELEASE)
+        P.slrng_server_drain(sv)
+        st = P.slrng_server_get_stats(sv)
+    finally:
+        P.slrng_server_destroy(sv)
+    assert st["completed"] == 3000 and st["failed"] == 0
+    assert st["peak_reserved_bytes"] <= budget
+    assert st["max_inflight"] >= 2
+    assert st["iterations"] < 3000  # requests were batched
+
+
+def test_replay_small_trace(P):
+    from paper_1805_01407_amd import workloads as W
+    tr = W.serve_trace(rate=20000, seconds=0.5, streams=256, max_bytes=1 << 16, seed=11)
+    opts = P.slrng_server_default_opts(n_streams=256, budget_bytes=1 << 30, seed=42, variant=NAME)
+    sv = P.slrng_server_create(opts)
+    try:
+        P.slrng_server_replay(sv, tr["t"], tr["stream"], tr["n"], tr["kind"])
+        st = P.slrng_server_get_stats(sv)
+    finally:
+        P.slrng_server_destroy(sv)
+    assert st["completed"] == tr["t"].size and st["failed"] == 0
+    assert st["outputs"] == int(tr["n"].sum())
+    assert 0 < st["p50_us"] <= st["p99_us"] <= st["max_us"]
