@@ -119,6 +119,37 @@ def batched_section(P, torch, stream, launches: int = 3) -> dict:
     return out
 
 
+def serving_section(P, seconds: float) -> dict:
+    """The serving workload: Poisson arrivals at 20,000 requests/s on 4,096
+    device-resident xoshiro256** streams (seed 42), sizes log-uniform in
+    64 B .. 256 MiB, admission under a 16 GB output budget; continuous batching
+    against the plain form (one launch per request), on the same trace."""
+    from paper_1805_01407_amd import workloads as W
+    tr = W.serve_trace(seconds=seconds)
+    out = {"seconds": seconds, "requests": int(tr["t"].size), "outputs": int(tr["n"].sum()),
+           "offered_GBs": round(8 * float(tr["n"].sum()) / seconds / 1e9, 1)}
+    for label, kw in (("continuous_batching", {}), ("plain_per_request", {"max_batch": 1})):
+        sv = P.slrng_server_create(P.slrng_server_default_opts(**kw))
+        try:
+            t0 = time.perf_counter()
+            P.slrng_server_replay(sv, tr["t"], tr["stream"], tr["n"], tr["kind"])
+            wall = time.perf_counter() - t0
+            st = P.slrng_server_get_stats(sv)
+        finally:
+            P.slrng_server_destroy(sv)
+        kgbs = 8 * st["outputs"] / max(st["kernel_s"], 1e-12) / 1e9
+        out[label] = {"latency_p50_us": round(st["p50_us"], 1), "latency_p99_us": round(st["p99_us"], 1),
+                      "latency_max_us": round(st["max_us"], 1), "outputs_per_s": st["outputs"] / wall,
+                      "wall_s": round(wall, 3), "iterations": st["iterations"],
+                      "mean_batch": round(st["mean_batch"], 2), "max_inflight": st["max_inflight"],
+                      "peak_reserved_GB": round(st["peak_reserved_bytes"] / 1e9, 2),
+                      "kernel_active_s": round(st["kernel_s"], 4),
+                      "kernel_active_GBs": round(kgbs, 1),
+                      "kernel_active_frac_of_hbm_peak": round(kgbs / HBM_PEAK_GBS, 4),
+                      "completed": st["completed"], "failed": st["failed"]}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -128,6 +159,8 @@ def main():
     ap.add_argument("--n", type=int, default=65536)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-requests section")
+    ap.add_argument("--serve-seconds", type=float, default=10.0,
+                    help="length of the serving trace (0 skips the serving section)")
     ap.add_argument("--cpu-streams", type=int, default=512, help="streams per oracle batch")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     args = ap.parse_args()
@@ -213,6 +246,7 @@ def main():
     del buf_u, buf_f
     torch.cuda.empty_cache()
     batched = None if args.no_batch else batched_section(P, torch, stream)
+    served = None if args.serve_seconds <= 0 else serving_section(P, args.serve_seconds)
 
     cpu = None if args.no_cpu else cpu_baseline(args.cpu_streams, N, args.cpu_seconds)
 
@@ -238,6 +272,7 @@ def main():
         "write_ceiling_GBs": ceiling,
         "gen_GBs_per_generator": per_variant,
         "batched_requests": batched,
+        "serving": served,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

@@ -287,7 +287,8 @@ int slrng_batch_run(const slrng_request *reqs, size_t n_reqs, const slrng_batch_
  *   it is still pending or in flight).
  * slrng_server_drain: waits until every submitted request has completed.
  * slrng_server_get_stats / _reset_stats: counters; latency percentiles of the
- *   completed requests; busy_s is the union of the iterations' device time.
+ *   completed requests; busy_s is the union of the iterations' device time
+ *   (copies and kernels), kernel_s that of the generation kernels alone.
  * slrng_server_replay: submits count requests at the given arrival times
  *   (seconds from the call), with SLRNG_SUBMIT_AUTORELEASE, then drains (a
  *   load generator for benchmarks).
@@ -305,6 +306,10 @@ typedef struct slrng_server_opts {
   int32_t inflight;      /* iterations in flight, 1..8 (0 = default) */
   int32_t tile;          /* 16 or 32 (0 = default) */
   int32_t waves_per_cu;  /* persistent grid (0 = default) */
+  int32_t window_us;     /* batching window: an iteration waits until its oldest
+                            request is this old (default 250; 0 = launch at once) ... */
+  int32_t reserved;
+  uint64_t window_bytes; /* ... or until this many bytes are pending */
 } slrng_server_opts;
 
 enum { SLRNG_SUBMIT_NONBLOCK = 1, SLRNG_SUBMIT_AUTORELEASE = 2 };
@@ -314,6 +319,7 @@ typedef struct slrng_server_stats {
   uint64_t iterations, max_inflight, max_batch, peak_reserved_bytes, reserved_bytes;
   double wall_s, busy_s, mean_batch;
   double p50_us, p99_us, max_us;
+  double kernel_s; /* union of the generation kernels' device time */
 } slrng_server_stats;
 
 int slrng_server_default_opts(slrng_server_opts *opts);

@@ -68,7 +68,8 @@ class _ServerOpts(ctypes.Structure):
                 ("chunk", ctypes.c_uint64), ("n_streams", ctypes.c_uint32),
                 ("variant", ctypes.c_int32), ("max_batch", ctypes.c_int32),
                 ("inflight", ctypes.c_int32), ("tile", ctypes.c_int32),
-                ("waves_per_cu", ctypes.c_int32)]
+                ("waves_per_cu", ctypes.c_int32), ("window_us", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("window_bytes", ctypes.c_uint64)]
 
 
 class _ServerStats(ctypes.Structure):
@@ -76,7 +77,7 @@ class _ServerStats(ctypes.Structure):
                 ("submitted", "completed", "failed", "rejected", "outputs", "iterations",
                  "max_inflight", "max_batch", "peak_reserved_bytes", "reserved_bytes")] + \
                [(f, ctypes.c_double) for f in
-                ("wall_s", "busy_s", "mean_batch", "p50_us", "p99_us", "max_us")]
+                ("wall_s", "busy_s", "mean_batch", "p50_us", "p99_us", "max_us", "kernel_s")]
 
 
 _lib = None

@@ -36,7 +36,7 @@ using namespace slrng;
 
 namespace {
 
-constexpr uint32_t kMaxTable = 8192;  // chunk-table entries per variant
+constexpr uint32_t kMaxTable = 65536;  // chunk-table entries per variant
 
 // Chunk tables x^(j C) mod p for j < entries, word-major, per (device, engine, C).
 struct ChunkTable {
@@ -79,12 +79,6 @@ int chunk_table(int device, int engine, uint64_t C, uint32_t need, ChunkTable *o
   return SLRNG_OK;
 }
 
-struct Lane {
-  LaneDesc d;
-  int variant, kind;
-  uint64_t unit;
-};
-
 // Relative cost of one output per variant (engine and scrambler work), for
 // ordering tiles heaviest first.
 uint64_t output_cost(int v) { return (v >= 6 && v <= 8) ? 3 : 2; }
@@ -103,16 +97,24 @@ int batch_grid_blocks(const slrng_batch_opts &o, int device, unsigned *blocks) {
 }
 
 int build_plan(const PlanReq *reqs, size_t n_reqs, const slrng_batch_opts &o, int device,
-               uint64_t grid_lanes, PlanHost &P) {
+               uint64_t grid_lanes, PlanHost &P, bool fit) {
   const bool plain = o.mode == SLRNG_BATCH_PLAIN;
   // chunk length per variant: the option value, rounded up to the tile and
   // raised if a request would need more than kMaxTable chunks
   uint64_t C[kNumVariants];
   uint64_t maxn[kNumVariants] = {0};
   for (size_t r = 0; r < n_reqs; r++) maxn[reqs[r].variant] = std::max(maxn[reqs[r].variant], reqs[r].n);
+  uint64_t total[kNumVariants] = {0};
+  for (size_t r = 0; r < n_reqs; r++) total[reqs[r].variant] += reqs[r].n;
   for (int v = 0; v < kNumVariants; v++) {
     uint64_t c = o.chunk[v] ? o.chunk[v] : 16384;
     if (c > 0xffffffffull) c = 0xffffffffull & ~(uint64_t)63;
+    if (fit) {
+      const uint64_t floor_c = std::max<uint64_t>(512, 2 * 64 * (uint64_t)variant_words(v));
+      uint64_t want = floor_c;
+      while (want < c && want * grid_lanes < total[v]) want *= 2;
+      c = std::min(c, want);
+    }
     c = (c + o.tile - 1) / o.tile * o.tile;
     const uint64_t need = (maxn[v] + kMaxTable - 1) / kMaxTable;
     if (c < need) c = (need + o.tile - 1) / o.tile * o.tile;
@@ -132,10 +134,27 @@ int build_plan(const PlanReq *reqs, size_t n_reqs, const slrng_batch_opts &o, in
   // The plain form runs each request alone, so each request is cut finely
   // enough to fill the GPU by itself: chunk = the smallest power of two >= 1024
   // giving at most one chunk per lane of the persistent grid (capped by C_v).
+  //
+  // Every 64 consecutive chunks of a request form one run tile, described by a
+  // single RunDesc (the lanes derive their chunk on the device).  The request's
+  // remaining chunks (fewer than 64) go to buckets keyed by (unit, variant,
+  // kind) as explicit lane descriptors: full-length chunks first, then the
+  // partial last chunks by decreasing length, 64 to a tile.
+  struct Bucket {
+    uint64_t unit;
+    int variant, kind;
+    std::vector<LaneDesc> full, part;
+  };
+  std::map<std::tuple<uint64_t, int, int>, size_t> bucket_of;
+  std::vector<Bucket> buckets;
+  std::map<uint64_t, std::vector<std::pair<uint64_t, TileDesc>>> unit_tiles;
   std::vector<uint64_t> req_chunk(n_reqs, 0);
-  std::vector<Lane> lanes;
   uint32_t tab_need[kNumVariants] = {0};
   P.total_outputs = 0;
+  P.tiles.clear();
+  P.lanes.clear();
+  P.runs.clear();
+  P.units.clear();
   for (size_t r = 0; r < n_reqs; r++) {
     const PlanReq &q = reqs[r];
     if (!q.n) continue;
@@ -150,18 +169,48 @@ int build_plan(const PlanReq *reqs, size_t n_reqs, const slrng_batch_opts &o, in
     }
     const uint64_t nch = (q.n + c - 1) / c;
     if (!plain) tab_need[q.variant] = std::max<uint32_t>(tab_need[q.variant], (uint32_t)nch);
-    for (uint64_t j = 0; j < nch; j++) {
-      Lane l;
-      l.variant = q.variant;
-      l.kind = q.kind;
-      l.unit = plain ? (uint64_t)r : 0;
-      l.d.seed = q.seed;
-      l.d.out = q.out + j * c * 8;
-      l.d.len = (uint32_t)std::min<uint64_t>(c, q.n - j * c);
-      l.d.jidx = (uint32_t)j;
-      l.d.req = req_slot[r];
-      l.d.pad = 0;
-      lanes.push_back(l);
+    const uint64_t unit = plain ? (uint64_t)r : 0ull;
+    auto &ut = unit_tiles[unit];
+    const uint64_t nrun = nch / kWave;
+    for (uint64_t k = 0; k < nrun; k++) {
+      const uint64_t j0 = k * kWave;
+      RunDesc rd;
+      rd.seed = q.seed;
+      rd.out0 = q.out + j0 * c * 8;
+      rd.n_rem = q.n - j0 * c;
+      rd.c = (uint32_t)c;
+      rd.j0 = (uint32_t)j0;
+      rd.req = req_slot[r];
+      rd.pad = 0;
+      TileDesc td;
+      td.variant = (uint8_t)q.variant;
+      td.kind = (uint8_t)q.kind;
+      td.nlanes = (uint8_t)kWave;
+      td.flags = kTileRun | kTileJump;
+      td.max_len = (uint32_t)c;
+      td.min_len = (uint32_t)std::min<uint64_t>(c, q.n - (j0 + kWave - 1) * c);
+      td.lane0 = (uint32_t)P.runs.size();
+      P.runs.push_back(rd);
+      ut.push_back({(uint64_t)td.max_len * output_cost(td.variant), td});
+    }
+    if (nrun * kWave == nch) continue;
+    const auto key = std::make_tuple(unit, q.variant, q.kind);
+    auto it = bucket_of.find(key);
+    if (it == bucket_of.end()) {
+      it = bucket_of.emplace(key, buckets.size()).first;
+      buckets.push_back(Bucket{unit, q.variant, q.kind, {}, {}});
+    }
+    Bucket &bk = buckets[it->second];
+    for (uint64_t j = nrun * kWave; j < nch; j++) {
+      LaneDesc d;
+      d.seed = q.seed;
+      d.out = q.out + j * c * 8;
+      d.len = (uint32_t)std::min<uint64_t>(c, q.n - j * c);
+      d.jidx = (uint32_t)j;
+      d.req = req_slot[r];
+      d.pad = 0;
+      if (d.len == c) bk.full.push_back(d);
+      else bk.part.push_back(d);
     }
   }
   for (int v = 0; v < kNumVariants; v++) {
@@ -174,54 +223,45 @@ int build_plan(const PlanReq *reqs, size_t n_reqs, const slrng_batch_opts &o, in
     P.tab[v] = t.dev;
     P.tab_n[v] = t.n;
   }
-  // tiles: per unit (the whole batch, or one request), per (variant, kind),
-  // lanes sorted by length, 64 per tile; tiles heaviest first within a unit
-  std::stable_sort(lanes.begin(), lanes.end(), [](const Lane &x, const Lane &y) {
-    if (x.unit != y.unit) return x.unit < y.unit;
-    if (x.variant != y.variant) return x.variant < y.variant;
-    if (x.kind != y.kind) return x.kind < y.kind;
-    return x.d.len > y.d.len;
-  });
-  P.tiles.clear();
-  P.lanes.clear();
-  P.units.clear();
-  P.lanes.reserve(lanes.size());
-  size_t i = 0;
-  while (i < lanes.size()) {
-    const uint64_t unit = lanes[i].unit;
-    PlanUnit u;
-    u.tile0 = (uint32_t)P.tiles.size();
-    std::vector<std::pair<uint64_t, TileDesc>> tiles;
-    while (i < lanes.size() && lanes[i].unit == unit) {
-      size_t e2 = i;
-      while (e2 < lanes.size() && lanes[e2].unit == unit && lanes[e2].variant == lanes[i].variant &&
-             lanes[e2].kind == lanes[i].kind)
-        e2++;
-      for (size_t s = i; s < e2; s += kWave) {
-        const size_t cnt = std::min<size_t>(kWave, e2 - s);
-        TileDesc td;
-        td.variant = (uint8_t)lanes[s].variant;
-        td.kind = (uint8_t)lanes[s].kind;
-        td.nlanes = (uint8_t)cnt;
-        td.need_jump = 0;
-        td.max_len = lanes[s].d.len;  // sorted: the first is the longest
-        td.min_len = lanes[s + cnt - 1].d.len;
-        td.lane0 = (uint32_t)P.lanes.size();
-        for (size_t q = s; q < s + cnt; q++) {
-          if (lanes[q].d.jidx) td.need_jump = 1;
-          P.lanes.push_back(lanes[q].d);
-        }
-        tiles.push_back({(uint64_t)td.max_len * output_cost(td.variant), td});
+  // list tiles from the buckets
+  for (auto &kv : bucket_of) {
+    Bucket &bk = buckets[kv.second];
+    auto &ut = unit_tiles[bk.unit];
+    std::stable_sort(bk.part.begin(), bk.part.end(),
+                     [](const LaneDesc &x, const LaneDesc &y) { return x.len > y.len; });
+    const size_t nf = bk.full.size(), nl = nf + bk.part.size();
+    auto lane_at = [&](size_t k) -> const LaneDesc & { return k < nf ? bk.full[k] : bk.part[k - nf]; };
+    for (size_t s0 = 0; s0 < nl; s0 += kWave) {
+      const size_t cnt = std::min<size_t>(kWave, nl - s0);
+      TileDesc td;
+      td.variant = (uint8_t)bk.variant;
+      td.kind = (uint8_t)bk.kind;
+      td.nlanes = (uint8_t)cnt;
+      td.flags = 0;
+      td.max_len = lane_at(s0).len;  // lanes are in decreasing length
+      td.min_len = lane_at(s0 + cnt - 1).len;
+      td.lane0 = (uint32_t)P.lanes.size();
+      for (size_t k = s0; k < s0 + cnt; k++) {
+        const LaneDesc &d = lane_at(k);
+        if (d.jidx) td.flags |= kTileJump;
+        P.lanes.push_back(d);
       }
-      i = e2;
+      ut.push_back({(uint64_t)td.max_len * output_cost(td.variant), td});
     }
+  }
+  // units in order; tiles heaviest first within a unit
+  for (auto &kv : unit_tiles) {
+    auto &tiles = kv.second;
     std::stable_sort(tiles.begin(), tiles.end(),
                      [](const std::pair<uint64_t, TileDesc> &x, const std::pair<uint64_t, TileDesc> &y) {
                        return x.first > y.first;
                      });
+    PlanUnit u;
+    u.tile0 = (uint32_t)P.tiles.size();
     for (auto &t : tiles) P.tiles.push_back(t.second);
-    u.ntiles = (uint32_t)P.tiles.size() - u.tile0;
+    u.ntiles = (uint32_t)tiles.size();
     if (plain) {
+      const uint64_t unit = kv.first;
       const uint64_t c = req_chunk[unit];
       ChunkTable t;
       int rc = chunk_table(device, variant_engine(reqs[unit].variant), c,
@@ -272,6 +312,7 @@ struct slrng_batch {
   PlanHost plan;
   TileDesc *d_tiles = nullptr;
   LaneDesc *d_lanes = nullptr;
+  RunDesc *d_runs = nullptr;
   uint64_t *d_req_state = nullptr;
   uint64_t *d_req_seed = nullptr, *d_req_poly = nullptr;
   uint32_t *d_req_slot = nullptr;
@@ -287,7 +328,7 @@ static void free_batch(slrng_batch *b) {
   if (!b) return;
   if (b->exec) (void)hipGraphExecDestroy(b->exec);
   if (b->graph) (void)hipGraphDestroy(b->graph);
-  void *ptrs[] = {b->d_tiles, b->d_lanes, b->d_req_state, b->d_req_seed, b->d_req_poly,
+  void *ptrs[] = {b->d_tiles, b->d_lanes, b->d_runs, b->d_req_state, b->d_req_seed, b->d_req_poly,
                   b->d_req_slot, b->d_counter};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
@@ -392,6 +433,7 @@ extern "C" int slrng_batch_plan(const slrng_request *reqs, size_t n_reqs,
   };
   rc = upload((void **)&b->d_tiles, P.tiles.data(), P.tiles.size() * sizeof(TileDesc));
   if (!rc) rc = upload((void **)&b->d_lanes, P.lanes.data(), P.lanes.size() * sizeof(LaneDesc));
+  if (!rc) rc = upload((void **)&b->d_runs, P.runs.data(), P.runs.size() * sizeof(RunDesc));
   if (!rc) {
     std::vector<unsigned> zeros(P.units.size(), 0);
     rc = upload((void **)&b->d_counter, zeros.data(), zeros.size() * sizeof(unsigned));
@@ -425,6 +467,7 @@ extern "C" int slrng_batch_plan(const slrng_request *reqs, size_t n_reqs,
   b->args.ntiles = (uint32_t)P.tiles.size();
   b->args.pad = 0;
   b->args.lanes = b->d_lanes;
+  b->args.runs = b->d_runs;
   b->args.req_state = b->d_req_state;
   b->args.counter = b->d_counter;
   for (int v = 0; v < kNumVariants; v++) {
@@ -534,7 +577,7 @@ extern "C" int slrng_batch_info(const slrng_batch *b, uint64_t *n_tiles, uint64_
                                 uint64_t *total_outputs) {
   if (!b) return SLRNG_EINVAL;
   if (n_tiles) *n_tiles = b->plan.tiles.size();
-  if (n_lanes) *n_lanes = b->plan.lanes.size();
+  if (n_lanes) *n_lanes = b->plan.lanes.size() + (uint64_t)b->plan.runs.size() * kWave;
   if (total_outputs) *total_outputs = b->plan.total_outputs;
   return SLRNG_OK;
 }

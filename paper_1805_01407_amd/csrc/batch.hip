@@ -71,7 +71,16 @@ __device__ __forceinline__ void batch_tile(const BatchArgs &a, const TileDesc &t
   constexpr int K = Params<V>::k;
   const bool active = lane < (int)td.nlanes;
   LaneDesc ld;
-  if (active) {
+  if (td.flags & kTileRun) {
+    const RunDesc rd = a.runs[td.lane0];  // uniform
+    const u64 off = (u64)lane * rd.c;
+    ld.seed = rd.seed;
+    ld.out = rd.out0 + off * 8;
+    ld.len = active ? (unsigned)((rd.n_rem - off < (u64)rd.c) ? rd.n_rem - off : rd.c) : 0u;
+    ld.jidx = rd.j0 + (unsigned)lane;
+    ld.req = rd.req;
+    ld.pad = 0;
+  } else if (active) {
     ld = a.lanes[td.lane0 + lane];
   } else {
     ld.seed = 0;
@@ -88,7 +97,7 @@ __device__ __forceinline__ void batch_tile(const BatchArgs &a, const TileDesc &t
   } else {
     splitmix64_fill<K>(ld.seed, s);
   }
-  if (td.need_jump) {
+  if (td.flags & kTileJump) {
     const u64 *tab = a.tab[V];
     const u64 tn = a.tab_n[V];
     const u64 jj = ld.jidx;

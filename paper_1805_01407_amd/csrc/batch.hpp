@@ -19,14 +19,28 @@ namespace slrng {
 
 constexpr uint32_t kNoReqState = 0xffffffffu;
 
+enum : uint8_t { kTileJump = 1, kTileRun = 2 };
+
 struct TileDesc {
   uint8_t variant;
   uint8_t kind;
   uint8_t nlanes;     // 1..64
-  uint8_t need_jump;  // 1 if some lane has a chunk index > 0
+  uint8_t flags;      // kTileJump: some lane has a chunk index > 0; kTileRun: see RunDesc
   uint32_t max_len;   // longest lane-chunk of the tile
   uint32_t min_len;   // shortest lane-chunk of the tile
-  uint32_t lane0;     // first lane descriptor
+  uint32_t lane0;     // first lane descriptor, or the RunDesc of a run tile
+};
+
+// A run tile: lane l takes chunk j0 + l of one request, i.e. outputs
+// [l c, min((l+1) c, n_rem)) counted from out0 (the address of chunk j0).
+struct RunDesc {
+  uint64_t seed;
+  uint64_t out0;
+  uint64_t n_rem;     // outputs of the request from chunk j0 on
+  uint32_t c;         // chunk length
+  uint32_t j0;
+  uint32_t req;       // request-state index, or kNoReqState
+  uint32_t pad;
 };
 
 struct LaneDesc {
@@ -43,6 +57,7 @@ struct BatchArgs {
   uint32_t ntiles;
   uint32_t pad;
   const LaneDesc *lanes;
+  const RunDesc *runs;
   const uint64_t *req_state;          // [r][16] start states of requests with start > 0
   const uint64_t *tab[kNumVariants];  // chunk tables, word-major: word w of entry j at [w*tab_n + j]
   uint32_t tab_n[kNumVariants];

@@ -45,6 +45,7 @@ struct PlanReqStates {
 struct PlanHost {
   std::vector<TileDesc> tiles;
   std::vector<LaneDesc> lanes;
+  std::vector<RunDesc> runs;
   std::vector<PlanUnit> units;
   PlanReqStates rs;
   const uint64_t *tab[kNumVariants] = {nullptr};
@@ -53,10 +54,13 @@ struct PlanHost {
 };
 
 // Builds the plan.  `grid_lanes` is the persistent grid size in lanes (used to
-// size the plain form's chunks); `from_state` requests always get a request
-// state.  Returns SLRNG_OK or an error code.
+// size the plain form's chunks, and with `fit` those of the whole batch: the
+// chunk length shrinks until the batch's lane-chunks cover the grid, down to
+// 2n outputs so that the per-lane jump of n steps stays amortised);
+// `from_state` requests always get a request state.  Returns SLRNG_OK or an
+// error code.
 int build_plan(const PlanReq *reqs, size_t n, const slrng_batch_opts &o, int device,
-               uint64_t grid_lanes, PlanHost &out);
+               uint64_t grid_lanes, PlanHost &out, bool fit = false);
 
 // The persistent grid (blocks of 4 waves) for the options on `device`.
 int batch_grid_blocks(const slrng_batch_opts &o, int device, unsigned *blocks);

@@ -14,7 +14,7 @@ namespace slrng {
 
 // ---------------------------------------------------------------- carry-less multiply
 
-static void clmul_portable(uint64_t a, uint64_t b, uint64_t &lo, uint64_t &hi) {
+static inline void clmul_portable(uint64_t a, uint64_t b, uint64_t &lo, uint64_t &hi) {
   uint64_t l = 0, h = 0;
   for (int i = 0; i < 64; i++) {
     if ((b >> i) & 1) {
@@ -27,8 +27,8 @@ static void clmul_portable(uint64_t a, uint64_t b, uint64_t &lo, uint64_t &hi) {
 }
 
 #if defined(__x86_64__)
-__attribute__((target("pclmul,sse2"))) static void clmul_hw(uint64_t a, uint64_t b, uint64_t &lo,
-                                                            uint64_t &hi) {
+__attribute__((target("pclmul,sse2"))) static inline void clmul_hw(uint64_t a, uint64_t b, uint64_t &lo,
+                                                                   uint64_t &hi) {
   __m128i va = _mm_set_epi64x(0, (long long)a), vb = _mm_set_epi64x(0, (long long)b);
   __m128i r = _mm_clmulepi64_si128(va, vb, 0x00);
   lo = (uint64_t)_mm_cvtsi128_si64(r);
@@ -36,29 +36,28 @@ __attribute__((target("pclmul,sse2"))) static void clmul_hw(uint64_t a, uint64_t
 }
 #endif
 
-typedef void (*clmul_fn)(uint64_t, uint64_t, uint64_t &, uint64_t &);
-
-static clmul_fn pick_clmul() {
+static bool has_pclmul() {
 #if defined(__x86_64__)
   __builtin_cpu_init();
-  if (__builtin_cpu_supports("pclmul")) return clmul_hw;
+  return __builtin_cpu_supports("pclmul");
+#else
+  return false;
 #endif
-  return clmul_portable;
 }
 
-static clmul_fn g_clmul = pick_clmul();
+static const bool g_hw = has_pclmul();
 
 // ---------------------------------------------------------------- reduction tables
 
-// X[i] = x^(n+i) mod p, i < n-1, so a product of degree <= 2n-2 reduces by
-// xoring X[i] for every set coefficient of x^(n+i).
+// X[i] = x^(n+i) mod p for i < n: a product of degree <= 2n-2 reduces by
+// xoring X[i] for every set coefficient of x^(n+i).  R groups them by bytes.
 static void build_reducer(Field &f) {
   std::vector<Poly> &X = f.X;
-  X.resize(f.n > 1 ? f.n - 1 : 0);
+  X.resize(f.n);
   // x^n mod p = p - x^n
   Poly cur = f.p;
   cur.flip(f.n);
-  for (int i = 0; i < f.n - 1; i++) {
+  for (int i = 0; i < f.n; i++) {
     X[i] = cur;
     // multiply by x: shift left one bit, reduce the x^n term
     uint64_t carry = 0;
@@ -72,36 +71,90 @@ static void build_reducer(Field &f) {
       for (int j = 0; j < kPolyWords; j++) cur.w[j] ^= f.p.w[j];
     }
   }
+  const int W = f.n / 64, nb = f.n / 8;
+  f.R.assign((size_t)nb * 256 * W, 0);
+  for (int b = 0; b < nb; b++)
+    for (int v = 1; v < 256; v++) {
+      const int low = __builtin_ctz(v);
+      uint64_t *dst = &f.R[((size_t)b * 256 + v) * W];
+      const uint64_t *prev = &f.R[((size_t)b * 256 + (v & (v - 1))) * W];
+      const Poly &x = X[8 * b + low];
+      for (int w = 0; w < W; w++) dst[w] = prev[w] ^ x.w[w];
+    }
 }
 
-void Field::mulmod(const Poly &a, const Poly &b, Poly &r) const {
-  const int W = (n + 63) / 64;  // words holding degree < n
-  uint64_t prod[2 * kPolyWords] = {0};
+// prod: 2W words, coefficients of degree < 2n; result: W words (degree < n)
+static inline void reduce(const Field &f, const uint64_t *prod, Poly &r) {
+  const int W = f.n / 64, nb = f.n / 8;
+  uint64_t acc[kPolyWords] = {0};
+  for (int w = 0; w < W; w++) acc[w] = prod[w];
+  const uint8_t *hb = reinterpret_cast<const uint8_t *>(prod + W);  // little endian
+  for (int b = 0; b < nb; b++) {
+    const unsigned v = hb[b];
+    if (!v) continue;
+    const uint64_t *t = &f.R[((size_t)b * 256 + v) * W];
+    for (int w = 0; w < W; w++) acc[w] ^= t[w];
+  }
+  r.clear();
+  for (int w = 0; w < W; w++) r.w[w] = acc[w];
+}
+
+#if defined(__x86_64__)
+__attribute__((target("pclmul,sse2"))) static void mul_words_hw(const uint64_t *a, const uint64_t *b, int W,
+                                                                uint64_t *prod) {
+  for (int i = 0; i < 2 * W; i++) prod[i] = 0;
   for (int i = 0; i < W; i++) {
-    if (!a.w[i]) continue;
+    if (!a[i]) continue;
     for (int j = 0; j < W; j++) {
       uint64_t lo, hi;
-      g_clmul(a.w[i], b.w[j], lo, hi);
+      clmul_hw(a[i], b[j], lo, hi);
       prod[i + j] ^= lo;
       prod[i + j + 1] ^= hi;
     }
   }
-  Poly out;
-  out.clear();
-  for (int j = 0; j < W; j++) out.w[j] = prod[j];
-  if (n & 63) {
-    // degree n not word aligned: keep bits < n in the low part
-    out.w[W - 1] &= (1ull << (n & 63)) - 1;
-  }
-  // coefficients of x^(n + i), i = 0 .. n-2
-  for (int i = 0; i < n - 1; i++) {
-    const int d = n + i;
-    if ((prod[d >> 6] >> (d & 63)) & 1) {
-      const Poly &x = X[i];
-      for (int j = 0; j < W; j++) out.w[j] ^= x.w[j];
+}
+
+__attribute__((target("pclmul,sse2"))) static void sqr_words_hw(const uint64_t *a, int W, uint64_t *prod) {
+  // over Z/2Z the cross terms of a square cancel: (sum a_i X^i)^2 = sum a_i^2 X^2i
+  for (int i = 0; i < W; i++) clmul_hw(a[i], a[i], prod[2 * i], prod[2 * i + 1]);
+}
+#endif
+
+static void mul_words_sw(const uint64_t *a, const uint64_t *b, int W, uint64_t *prod) {
+  for (int i = 0; i < 2 * W; i++) prod[i] = 0;
+  for (int i = 0; i < W; i++) {
+    if (!a[i]) continue;
+    for (int j = 0; j < W; j++) {
+      uint64_t lo, hi;
+      clmul_portable(a[i], b[j], lo, hi);
+      prod[i + j] ^= lo;
+      prod[i + j + 1] ^= hi;
     }
   }
-  r = out;
+}
+
+void Field::mulmod(const Poly &a, const Poly &b, Poly &r) const {
+  const int W = n / 64;
+  uint64_t prod[2 * kPolyWords];
+#if defined(__x86_64__)
+  if (g_hw) mul_words_hw(a.w, b.w, W, prod);
+  else mul_words_sw(a.w, b.w, W, prod);
+#else
+  mul_words_sw(a.w, b.w, W, prod);
+#endif
+  reduce(*this, prod, r);
+}
+
+void Field::sqrmod(const Poly &a, Poly &r) const {
+  const int W = n / 64;
+  uint64_t prod[2 * kPolyWords];
+#if defined(__x86_64__)
+  if (g_hw) sqr_words_hw(a.w, W, prod);
+  else mul_words_sw(a.w, a.w, W, prod);
+#else
+  mul_words_sw(a.w, a.w, W, prod);
+#endif
+  reduce(*this, prod, r);
 }
 
 void Field::xpow(const uint64_t *J, int nwords, Poly &r) const {

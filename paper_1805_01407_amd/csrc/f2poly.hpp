@@ -15,7 +15,7 @@
 
 namespace slrng {
 
-constexpr int kMaxN = 1024;                 // largest state (xoroshiro1024)
+constexpr int kMaxN = 1024;                 // largest state (xoroshiro1024); n is a multiple of 64
 constexpr int kPolyWords = kMaxN / 64 + 1;  // degree n needs n+1 bits
 
 // Polynomial of degree <= kMaxN; bit i of w[i/64] is the coefficient of x^i.
@@ -30,10 +30,13 @@ struct Poly {
 struct Field {
   int n = 0;  // degree of p
   Poly p;     // monic, degree n
-  std::vector<Poly> X;  // X[i] = x^(n+i) mod p, the reduction table
+  std::vector<Poly> X;  // X[i] = x^(n+i) mod p, i < n
+  // byte-window reduction: R[(b*256 + v)*W .. +W) = sum of X[8b+i] over the set
+  // bits i of v, W = n/64 words
+  std::vector<uint64_t> R;
   // r = a * b mod p (a, b of degree < n)
   void mulmod(const Poly &a, const Poly &b, Poly &r) const;
-  void sqrmod(const Poly &a, Poly &r) const { mulmod(a, a, r); }
+  void sqrmod(const Poly &a, Poly &r) const;
   // r = x^J mod p for J given as little-endian 64-bit words
   void xpow(const uint64_t *J, int nwords, Poly &r) const;
   // r = x^(2^e) mod p

@@ -107,11 +107,12 @@ struct Req {
 // One in-flight slot: a HIP stream, events and reusable descriptor buffers.
 struct Slot {
   hipStream_t st = nullptr;
-  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  hipEvent_t ev0 = nullptr, evk = nullptr, ev1 = nullptr;  // start, generation kernel start, end
   bool busy = false;
-  size_t cap_tiles = 0, cap_lanes = 0, cap_req = 0;
+  size_t cap_tiles = 0, cap_lanes = 0, cap_runs = 0, cap_req = 0;
   TileDesc *d_tiles = nullptr, *h_tiles = nullptr;
   LaneDesc *d_lanes = nullptr, *h_lanes = nullptr;
+  RunDesc *d_runs = nullptr, *h_runs = nullptr;
   uint64_t *d_poly = nullptr, *h_poly = nullptr;
   uint32_t *d_idx = nullptr, *h_idx = nullptr;
   uint32_t *d_slot = nullptr, *h_slot = nullptr;
@@ -139,6 +140,7 @@ struct slrng_server {
   std::mutex mu;
   std::condition_variable cv_work, cv_space, cv_done;
   std::deque<uint64_t> pending;
+  uint64_t pending_bytes = 0;
   std::unordered_map<uint64_t, Req> reqs;
   uint64_t next_ticket = 1;
   std::vector<Slot> slots;
@@ -146,7 +148,8 @@ struct slrng_server {
   bool stop = false, worker_done = false;
   int error = 0;
   hipEvent_t ref = nullptr;                           // time origin of the busy intervals
-  std::vector<std::pair<double, double>> busy_ivals;  // device [start, end) ms per iteration
+  std::vector<std::pair<double, double>> busy_ivals;    // device [start, end) ms per iteration
+  std::vector<std::pair<double, double>> kernel_ivals;  // generation kernel [start, end) ms
   std::thread worker, completer;
 
   // statistics
@@ -174,9 +177,10 @@ static int grow_pair(T **d, T **h, size_t need, size_t &cap) {
 
 // Make the slot's buffers hold `tiles` tiles, `lanes` lanes and `nreq`
 // request states (the slot is idle: its previous iteration has completed).
-static int slot_reserve(Slot &s, size_t tiles, size_t lanes, size_t nreq) {
+static int slot_reserve(Slot &s, size_t tiles, size_t lanes, size_t runs, size_t nreq) {
   int rc = grow_pair(&s.d_tiles, &s.h_tiles, tiles, s.cap_tiles);
   if (!rc) rc = grow_pair(&s.d_lanes, &s.h_lanes, lanes, s.cap_lanes);
+  if (!rc) rc = grow_pair(&s.d_runs, &s.h_runs, runs, s.cap_runs);
   if (!rc && nreq > s.cap_req) {
     const size_t n = std::max<size_t>({nreq, s.cap_req * 2, 64});
     size_t c1 = 0, c2 = 0, c3 = 0;
@@ -195,13 +199,14 @@ static int slot_reserve(Slot &s, size_t tiles, size_t lanes, size_t nreq) {
 }
 
 static void free_slot(Slot &s) {
-  void *d[] = {s.d_tiles, s.d_lanes, s.d_poly, s.d_idx, s.d_slot, s.d_req_state, s.d_counter};
+  void *d[] = {s.d_tiles, s.d_lanes, s.d_runs, s.d_poly, s.d_idx, s.d_slot, s.d_req_state, s.d_counter};
   for (void *p : d)
     if (p) (void)hipFree(p);
-  void *h[] = {s.h_tiles, s.h_lanes, s.h_poly, s.h_idx, s.h_slot};
+  void *h[] = {s.h_tiles, s.h_lanes, s.h_runs, s.h_poly, s.h_idx, s.h_slot};
   for (void *p : h)
     if (p) (void)hipHostFree(p);
   if (s.ev0) (void)hipEventDestroy(s.ev0);
+  if (s.evk) (void)hipEventDestroy(s.evk);
   if (s.ev1) (void)hipEventDestroy(s.ev1);
   if (s.st) (void)hipStreamDestroy(s.st);
 }
@@ -210,12 +215,14 @@ static void free_slot(Slot &s) {
 static int launch_iteration(slrng_server *sv, int si, const std::vector<PlanReq> &pr) {
   Slot &s = sv->slots[si];
   PlanHost P;
-  int rc = build_plan(pr.data(), pr.size(), sv->bo, sv->device, (uint64_t)sv->blocks * kBlock, P);
+  int rc = build_plan(pr.data(), pr.size(), sv->bo, sv->device, (uint64_t)sv->blocks * kBlock, P,
+                      /*fit=*/true);
   if (rc) return rc;
-  rc = slot_reserve(s, P.tiles.size(), P.lanes.size(), P.rs.seeds.size());
+  rc = slot_reserve(s, P.tiles.size(), P.lanes.size(), P.runs.size(), P.rs.seeds.size());
   if (rc) return rc;
   if (!P.tiles.empty()) memcpy(s.h_tiles, P.tiles.data(), P.tiles.size() * sizeof(TileDesc));
   if (!P.lanes.empty()) memcpy(s.h_lanes, P.lanes.data(), P.lanes.size() * sizeof(LaneDesc));
+  if (!P.runs.empty()) memcpy(s.h_runs, P.runs.data(), P.runs.size() * sizeof(RunDesc));
   if (!P.rs.polys.empty()) {
     memcpy(s.h_poly, P.rs.polys.data(), P.rs.polys.size() * 8);
     memcpy(s.h_idx, P.rs.origin_idx.data(), P.rs.origin_idx.size() * 4);
@@ -227,6 +234,8 @@ static int launch_iteration(slrng_server *sv, int si, const std::vector<PlanReq>
     e = hipMemcpyAsync(s.d_tiles, s.h_tiles, P.tiles.size() * sizeof(TileDesc), hipMemcpyHostToDevice, st);
   if (e == hipSuccess && !P.lanes.empty())
     e = hipMemcpyAsync(s.d_lanes, s.h_lanes, P.lanes.size() * sizeof(LaneDesc), hipMemcpyHostToDevice, st);
+  if (e == hipSuccess && !P.runs.empty())
+    e = hipMemcpyAsync(s.d_runs, s.h_runs, P.runs.size() * sizeof(RunDesc), hipMemcpyHostToDevice, st);
   if (e == hipSuccess && !P.rs.polys.empty())
     e = hipMemcpyAsync(s.d_poly, s.h_poly, P.rs.polys.size() * 8, hipMemcpyHostToDevice, st);
   if (e == hipSuccess && !P.rs.origin_idx.empty())
@@ -255,6 +264,7 @@ static int launch_iteration(slrng_server *sv, int si, const std::vector<PlanReq>
     a.tiles = s.d_tiles;
     a.ntiles = (uint32_t)P.tiles.size();
     a.lanes = s.d_lanes;
+    a.runs = s.d_runs;
     a.req_state = s.d_req_state;
     for (int v = 0; v < kNumVariants; v++) {
       a.tab[v] = P.tab[v];
@@ -262,6 +272,7 @@ static int launch_iteration(slrng_server *sv, int si, const std::vector<PlanReq>
     }
     a.counter = s.d_counter;
     e = launch_batch_reset(s.d_counter, st);
+    if (e == hipSuccess) e = hipEventRecord(s.evk, st);
     if (e != hipSuccess) return hip_fail(e);
     const unsigned blocks = std::min<unsigned>(sv->blocks, ((unsigned)P.tiles.size() + 3) / 4);
     e = launch_batch(a, sv->bo.tile, blocks, st);
@@ -287,6 +298,15 @@ static void worker_main(slrng_server *sv) {
       sv->cv_done.notify_all();
       return;
     }
+    // batching window: hold the iteration until the oldest pending request
+    // has waited window_us, unless enough bytes are pending already
+    if (sv->o.window_us > 0 && !sv->stop) {
+      const auto due = sv->reqs[sv->pending.front()].t_submit + std::chrono::microseconds(sv->o.window_us);
+      if (Clock::now() < due && sv->pending_bytes < sv->o.window_bytes) {
+        sv->cv_work.wait_until(lk, due, [&] { return sv->stop || sv->pending_bytes >= sv->o.window_bytes; });
+        continue;  // re-check slots and pending
+      }
+    }
     for (size_t i = 0; i < sv->slots.size(); i++)
       if (!sv->slots[i].busy) {
         si = (int)i;
@@ -301,6 +321,7 @@ static void worker_main(slrng_server *sv) {
       const uint64_t t = sv->pending.front();
       sv->pending.pop_front();
       Req &q = sv->reqs[t];
+      sv->pending_bytes -= q.n * 8;
       q.state = R_INFLIGHT;
       it.tickets.push_back(t);
       pr.push_back(PlanReq{sv->o.variant, q.kind, q.n, (uint64_t)(uintptr_t)(sv->arena_dev + q.off), q.pos,
@@ -349,13 +370,17 @@ static void completer_main(slrng_server *sv) {
     lk.unlock();
     hipError_t e = hipEventSynchronize(s.ev1);
     const Clock::time_point now = Clock::now();
-    float a = 0, b = 0;
+    float a = 0, k = 0, b = 0;
     if (e == hipSuccess) {
       (void)hipEventElapsedTime(&a, sv->ref, s.ev0);
+      (void)hipEventElapsedTime(&k, sv->ref, s.evk);
       (void)hipEventElapsedTime(&b, sv->ref, s.ev1);
     }
     lk.lock();
-    if (e == hipSuccess) sv->busy_ivals.push_back({a, b});
+    if (e == hipSuccess) {
+      sv->busy_ivals.push_back({a, b});
+      sv->kernel_ivals.push_back({k, b});
+    }
     for (uint64_t t : it.tickets) {
       auto f = sv->reqs.find(t);
       if (f == sv->reqs.end()) continue;
@@ -394,6 +419,8 @@ extern "C" int slrng_server_default_opts(slrng_server_opts *o) {
   o->tile = 32;
   o->waves_per_cu = 8;
   o->chunk = 0;
+  o->window_us = 250;
+  o->window_bytes = 256ull << 20;
   return SLRNG_OK;
 }
 
@@ -467,6 +494,7 @@ extern "C" int slrng_server_create(const slrng_server_opts *opts, slrng_server *
     for (auto &s : sv->slots) {
       e = hipStreamCreateWithFlags(&s.st, hipStreamNonBlocking);
       if (e == hipSuccess) e = hipEventCreate(&s.ev0);
+      if (e == hipSuccess) e = hipEventCreate(&s.evk);
       if (e == hipSuccess) e = hipEventCreate(&s.ev1);
       if (e == hipSuccess) e = hipMalloc(&s.d_counter, sizeof(unsigned));
       if (e != hipSuccess) {
@@ -529,6 +557,7 @@ extern "C" int slrng_server_submit(slrng_server *sv, uint32_t stream_id, uint64_
   const uint64_t t = sv->next_ticket++;
   sv->reqs.emplace(t, q);
   sv->pending.push_back(t);
+  sv->pending_bytes += n * 8;
   sv->submitted++;
   *ticket = t;
   sv->cv_work.notify_one();
@@ -596,21 +625,24 @@ extern "C" int slrng_server_get_stats(slrng_server *sv, slrng_server_stats *out)
     out->rejected = sv->rejected;
     out->outputs = sv->outputs;
     out->wall_s = secs(sv->t0, Clock::now());
-    // union of the iterations' device intervals (iterations may overlap)
-    std::vector<std::pair<double, double>> iv = sv->busy_ivals;
-    std::sort(iv.begin(), iv.end());
-    double busy = 0, cs = 0, ce = -1;
-    for (auto &x : iv) {
-      if (x.first > ce) {
-        if (ce > cs) busy += ce - cs;
-        cs = x.first;
-        ce = x.second;
-      } else {
-        ce = std::max(ce, x.second);
+    // unions of the iterations' device intervals (iterations may overlap)
+    auto union_ms = [](std::vector<std::pair<double, double>> iv) {
+      std::sort(iv.begin(), iv.end());
+      double tot = 0, cs = 0, ce = -1;
+      for (auto &x : iv) {
+        if (x.first > ce) {
+          if (ce > cs) tot += ce - cs;
+          cs = x.first;
+          ce = x.second;
+        } else {
+          ce = std::max(ce, x.second);
+        }
       }
-    }
-    if (ce > cs) busy += ce - cs;
-    out->busy_s = busy * 1e-3;
+      if (ce > cs) tot += ce - cs;
+      return tot;
+    };
+    out->busy_s = union_ms(sv->busy_ivals) * 1e-3;
+    out->kernel_s = union_ms(sv->kernel_ivals) * 1e-3;
     out->iterations = sv->iterations;
     out->max_inflight = sv->max_inflight;
     out->peak_reserved_bytes = sv->peak_reserved;
@@ -638,6 +670,7 @@ extern "C" int slrng_server_reset_stats(slrng_server *sv) {
   sv->iterations = sv->max_inflight = sv->max_batch_seen = sv->batch_sum = 0;
   sv->peak_reserved = sv->arena.used;
   sv->busy_ivals.clear();
+  sv->kernel_ivals.clear();
   return SLRNG_OK;
 }
 
