@@ -106,8 +106,10 @@ def test_budget_admission_and_overlap(P):
     import time
     S = 16
     budget = 1 << 20  # 1 MiB arena
+    # no batching window: every iteration launches as soon as a slot is free,
+    # so a burst keeps several iterations in flight
     opts = P.slrng_server_default_opts(n_streams=S, budget_bytes=budget, seed=7, variant=NAME,
-                                       inflight=3)
+                                       inflight=3, window_us=0)
     sv = P.slrng_server_create(opts)
     try:
         # fill the arena with unreleased requests, then a non-blocking submit
