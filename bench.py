@@ -119,6 +119,70 @@ def batched_section(P, torch, stream, launches: int = 3) -> dict:
     return out
 
 
+def positioning_section(P, torch, stream, reps: int = 5) -> dict:
+    """Jump-ahead at scale: 2^20 xoshiro256++ streams from seed 42 (stream i is
+    the SplitMix64 base state jumped i times by 2^128), every stream then
+    long-jumped once (2^192), then 1,024 outputs per stream (8 GiB).
+
+    Positioning and the long jump are bound by integer VALU work, not by HBM:
+    a uniform jump costs n = 256 engine steps (12 VALU instructions each for
+    xoshiro256 on gfx950) plus, for each set coefficient of the polynomial
+    (about half), a 4-word xor (8 instructions).  The section also times the
+    per-stream advance of every stream by its own random 128-bit distance.  `alu_frac` compares that
+    count with the chip's 32-bit VALU rate: 256 CUs x 128 lanes per clock x
+    2.4 GHz = 78.6 T lane-operations/s (the rate behind the 157.3 TFLOP/s
+    fp32 vector peak, an FMA counting as two)."""
+    name, seed, S, N = "xoshiro256++", 42, 1 << 20, 1024
+    buf = torch.empty((S, N), dtype=torch.int64, device="cuda")
+    ev = lambda: torch.cuda.Event(enable_timing=True)  # noqa: E731
+    acc = {"position": 0.0, "long_jump": 0.0, "generate": 0.0, "advance_each": 0.0}
+    # one random 128-bit distance per stream, for the per-stream advance
+    g = torch.Generator().manual_seed(7)
+    dist = torch.randint(-2**63, 2**63 - 1, (S, 2), generator=g, dtype=torch.int64).cuda()
+    with P.Streams(name, seed, S) as h:
+        for rep in range(reps + 1):
+            e = [ev() for _ in range(4)]
+            e[0].record(stream)
+            P.slrng_streams_seed(h.h, seed, stream)
+            e[1].record(stream)
+            P.slrng_streams_jump(h.h, P.SLRNG_LONG_JUMP, stream)
+            e[2].record(stream)
+            P.slrng_generate(h.h, P.SLRNG_U64, N, buf.data_ptr(), N, stream)
+            e[3].record(stream)
+            P.slrng_streams_advance_each(h.h, dist.data_ptr(), stream)
+            e4 = ev()
+            e4.record(stream)
+            torch.cuda.synchronize()
+            if rep:  # the first round is a warm-up
+                acc["position"] += e[0].elapsed_time(e[1]) / reps
+                acc["long_jump"] += e[1].elapsed_time(e[2]) / reps
+                acc["generate"] += e[2].elapsed_time(e[3]) / reps
+                acc["advance_each"] += e[3].elapsed_time(e4) / reps
+    del buf, dist
+    torch.cuda.empty_cache()
+    n_bits = 256
+    ops_per_jump = n_bits * 12 + (n_bits // 2) * 8
+    # per-stream advance: 13 radix-1024 digits, each a per-lane jump of n
+    # steps at 21 VALU instructions (12 engine, 8 masked accumulate, 1 mask)
+    ops_per_advance = 13 * n_bits * 21
+    lane_ops_peak = 256 * 128 * 2.4e9
+    jump_s = acc["long_jump"] * 1e-3
+    gbs = 8 * S * N / (acc["generate"] * 1e-3) / 1e9
+    return {"generator": name, "streams": S, "outputs_per_stream": N,
+            "position_ms": round(acc["position"], 4),
+            "positioned_streams_per_s": S / (acc["position"] * 1e-3),
+            "long_jump_ms": round(acc["long_jump"], 4),
+            "jumps_per_s": S / jump_s,
+            "ns_per_jump_aggregate": round(jump_s / S * 1e9, 4),
+            "alu_frac": round(S * ops_per_jump / jump_s / lane_ops_peak, 4),
+            "advance_each_ms": round(acc["advance_each"], 4),
+            "advance_each_per_s": S / (acc["advance_each"] * 1e-3),
+            "advance_each_alu_frac": round(S * ops_per_advance / (acc["advance_each"] * 1e-3)
+                                           / lane_ops_peak, 4),
+            "generate_ms": round(acc["generate"], 4), "generate_GBs": round(gbs, 1),
+            "generate_frac_of_hbm_peak": round(gbs / HBM_PEAK_GBS, 4)}
+
+
 def serving_section(P, seconds: float) -> dict:
     """The serving workload: Poisson arrivals at 20,000 requests/s on 4,096
     device-resident xoshiro256** streams (seed 42), sizes log-uniform in
@@ -245,6 +309,7 @@ def main():
         h.close()
     del buf_u, buf_f
     torch.cuda.empty_cache()
+    positioned = positioning_section(P, torch, stream)
     batched = None if args.no_batch else batched_section(P, torch, stream)
     served = None if args.serve_seconds <= 0 else serving_section(P, args.serve_seconds)
 
@@ -271,6 +336,7 @@ def main():
                      "traffic": profiled_traffic()},
         "write_ceiling_GBs": ceiling,
         "gen_GBs_per_generator": per_variant,
+        "jump_ahead_at_scale": positioned,
         "batched_requests": batched,
         "serving": served,
         "cpu_baseline": cpu,

@@ -145,6 +145,17 @@ int slrng_jump_poly(int variant, const uint64_t *J_words, int nj, uint64_t *out,
  * from host memory (host_words[i*k + j]); synchronous on `stream`.  set_state
  * rejects an all-zero state with EZEROSTATE and leaves the handle unchanged.
  *
+ * slrng_streams_advance_each: stream i advances by its own distance
+ * J_i = dev_steps[2i] + 2^64 dev_steps[2i+1] (any 128-bit value; the jump
+ * functions of Section "Combining linear engines and scramblers" with
+ * per-stream distances).  Everything runs on the device: J_i is cut into 13
+ * radix-1024 digits d_l and the stream is jumped by x^(d_l 2^(10 l)) mod p(x)
+ * for each nonzero digit, from a per-engine table of those polynomials built
+ * once per device (13 x 1024 entries of n bits; built on the first call).
+ * dev_steps: device memory, 8-byte aligned, 2 S words, read by work queued on
+ * `stream` (keep it alive until that work is done).  Asynchronous.
+ * EINVAL for a null or misaligned dev_steps.
+ *
  * slrng_streams_destroy: frees the handle (after the device is idle). */
 int slrng_streams_create(int variant, uint64_t seed, uint64_t n_streams, hipStream_t stream,
                          slrng_streams **out);
@@ -156,6 +167,7 @@ int slrng_streams_variant(const slrng_streams *h, int *variant);
 int slrng_streams_jump(slrng_streams *h, int jump_kind, hipStream_t stream);
 int slrng_streams_advance(slrng_streams *h, uint64_t steps_hi, uint64_t steps_lo,
                           hipStream_t stream);
+int slrng_streams_advance_each(slrng_streams *h, const uint64_t *dev_steps, hipStream_t stream);
 int slrng_generate(slrng_streams *h, int kind, uint64_t n, void *dev_out, uint64_t ld,
                    hipStream_t stream);
 int slrng_get_state(const slrng_streams *h, uint64_t *host_words, hipStream_t stream);
@@ -308,7 +320,9 @@ typedef struct slrng_server_opts {
   int32_t waves_per_cu;  /* persistent grid (0 = default) */
   int32_t window_us;     /* batching window: an iteration waits until its oldest
                             request is this old (default 250; 0 = launch at once) ... */
-  int32_t reserved;
+  int32_t min_chunk;     /* smallest lane-chunk (outputs) when the chunk length is
+                            fitted to an iteration (0 = default: the larger of
+                            512 and 2n, n the state bits) */
   uint64_t window_bytes; /* ... or until this many bytes are pending */
 } slrng_server_opts;
 

@@ -14,7 +14,7 @@ from .binding import (  # noqa: F401
     slrng_charpoly, slrng_jump_poly,
     slrng_streams_create, slrng_streams_create_from_states, slrng_streams_count,
     slrng_streams_variant, slrng_streams_seed,
-    slrng_streams_jump, slrng_streams_advance, slrng_generate,
+    slrng_streams_jump, slrng_streams_advance, slrng_streams_advance_each, slrng_generate,
     slrng_get_state, slrng_set_state, slrng_streams_destroy,
     slrng_get_tuning, slrng_set_tuning, slrng_calib_write, slrng_calib_copy,
     SLRNG_U64, SLRNG_F64, SLRNG_JUMP, SLRNG_LONG_JUMP,

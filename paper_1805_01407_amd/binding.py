@@ -69,7 +69,7 @@ class _ServerOpts(ctypes.Structure):
                 ("variant", ctypes.c_int32), ("max_batch", ctypes.c_int32),
                 ("inflight", ctypes.c_int32), ("tile", ctypes.c_int32),
                 ("waves_per_cu", ctypes.c_int32), ("window_us", ctypes.c_int32),
-                ("reserved", ctypes.c_int32), ("window_bytes", ctypes.c_uint64)]
+                ("min_chunk", ctypes.c_int32), ("window_bytes", ctypes.c_uint64)]
 
 
 class _ServerStats(ctypes.Structure):
@@ -113,6 +113,7 @@ def lib():
         "slrng_streams_variant": ([vp, ctypes.POINTER(i32)], i32),
         "slrng_streams_jump": ([vp, i32, vp], i32),
         "slrng_streams_advance": ([vp, u64, u64, vp], i32),
+        "slrng_streams_advance_each": ([vp, vp, vp], i32),
         "slrng_generate": ([vp, i32, u64, vp, u64, vp], i32),
         "slrng_get_state": ([vp, u64p, vp], i32),
         "slrng_set_state": ([vp, u64p, vp], i32),
@@ -264,6 +265,12 @@ def slrng_streams_advance(h: int, steps: int, stream=None) -> None:
     _check(lib().slrng_streams_advance(h, (steps >> 64) & 0xFFFFFFFFFFFFFFFF,
                                        steps & 0xFFFFFFFFFFFFFFFF, _stream(stream)),
            "slrng_streams_advance")
+
+
+def slrng_streams_advance_each(h: int, dev_steps: int, stream=None) -> None:
+    """dev_steps: device address of 2 S uint64 words (low, high) per stream."""
+    _check(lib().slrng_streams_advance_each(h, dev_steps, _stream(stream)),
+           "slrng_streams_advance_each")
 
 
 def slrng_generate(h: int, kind: int, n: int, dev_out: int, ld: int, stream=None) -> None:
@@ -519,6 +526,26 @@ class Streams:
 
     def advance(self, steps: int, stream=None):
         slrng_streams_advance(self.h, steps, stream)
+
+    def advance_each(self, steps, stream=None):
+        """Advance stream i by steps[i] (Python ints or uint64 pairs; any
+        128-bit value).  `steps` may also be a CUDA int64 tensor of shape
+        (S, 2) holding (low, high) words, used in place."""
+        import torch
+        if isinstance(steps, torch.Tensor):
+            assert steps.is_cuda and steps.dtype == torch.int64 and steps.shape == (self.S, 2)
+            buf = steps.contiguous()
+        else:
+            words = np.zeros((self.S, 2), dtype=np.uint64)
+            for i, J in enumerate(steps):
+                J = int(J)
+                words[i, 0] = J & 0xFFFFFFFFFFFFFFFF
+                words[i, 1] = (J >> 64) & 0xFFFFFFFFFFFFFFFF
+            buf = torch.from_numpy(words.view(np.int64)).cuda()
+        slrng_streams_advance_each(self.h, buf.data_ptr(), stream)
+        if buf is not steps:
+            # the staging tensor must outlive the queued kernel
+            torch.cuda.synchronize()
 
     def get_state(self, stream=None) -> np.ndarray:
         return slrng_get_state(self.h, stream)

@@ -153,6 +153,39 @@ int get_pos_tables(int device, int engine, int levels, PosTables **out) {
   return SLRNG_OK;
 }
 
+// Digit tables of slrng_streams_advance_each: entry d of level l is
+// x^(d 2^(10 l)) mod p, word w at [(l W + w) 1024 + d] (W = n/64 words).
+static std::map<std::pair<int, int>, uint64_t *> g_digit;  // (device, engine)
+
+int get_digit_tables(int device, int engine, const uint64_t **out) {
+  std::lock_guard<std::mutex> g(g_tab_mu);
+  auto key = std::make_pair(device, engine);
+  auto it = g_digit.find(key);
+  if (it != g_digit.end()) {
+    *out = it->second;
+    return SLRNG_OK;
+  }
+  const Field &f = engine_field(engine);
+  const int W = f.n / 64;
+  std::vector<uint64_t> h((size_t)kDigitLevels * W * kTabRadix);
+  std::vector<Poly> ent;
+  for (int l = 0; l < kDigitLevels; l++) {
+    power_table(f, 10 * l, ent);
+    for (int d = 0; d < kTabRadix; d++)
+      for (int w = 0; w < W; w++) h[((size_t)l * W + w) * kTabRadix + d] = ent[d].w[w];
+  }
+  uint64_t *dev = nullptr;
+  HIPCHK(hipMalloc(&dev, h.size() * 8));
+  hipError_t e = hipMemcpy(dev, h.data(), h.size() * 8, hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    (void)hipFree(dev);
+    return hip_fail(e);
+  }
+  g_digit[key] = dev;
+  *out = dev;
+  return SLRNG_OK;
+}
+
 // Slot start polynomials x^(j C - delta_d) mod p with delta_d = d C / D, for
 // skew class d < D and slot j < kMaxSlots (entry (d kMaxSlots + j), 16 words;
 // entries with j C < delta_d are unused).
@@ -415,6 +448,16 @@ extern "C" int slrng_streams_advance(slrng_streams *h, uint64_t hi, uint64_t lo,
   Poly r;
   f.xpow(J, 2, r);
   return apply_uniform(h, r, stream);
+}
+
+extern "C" int slrng_streams_advance_each(slrng_streams *h, const uint64_t *dev_steps,
+                                          hipStream_t stream) {
+  if (!h || !dev_steps || ((uintptr_t)dev_steps & 7)) return SLRNG_EINVAL;
+  const uint64_t *tab = nullptr;
+  int rc = get_digit_tables(h->device, h->engine, &tab);
+  if (rc) return rc;
+  hipError_t e = launch_advance_each(h->variant, h->state[h->cur], h->S, dev_steps, tab, stream);
+  return e == hipSuccess ? SLRNG_OK : hip_fail(e);
 }
 
 extern "C" int slrng_generate(slrng_streams *h, int kind, uint64_t n, void *dev_out, uint64_t ld,

@@ -97,7 +97,7 @@ int batch_grid_blocks(const slrng_batch_opts &o, int device, unsigned *blocks) {
 }
 
 int build_plan(const PlanReq *reqs, size_t n_reqs, const slrng_batch_opts &o, int device,
-               uint64_t grid_lanes, PlanHost &P, bool fit) {
+               uint64_t grid_lanes, PlanHost &P, bool fit, uint64_t fit_floor) {
   const bool plain = o.mode == SLRNG_BATCH_PLAIN;
   // chunk length per variant: the option value, rounded up to the tile and
   // raised if a request would need more than kMaxTable chunks
@@ -110,7 +110,8 @@ int build_plan(const PlanReq *reqs, size_t n_reqs, const slrng_batch_opts &o, in
     uint64_t c = o.chunk[v] ? o.chunk[v] : 16384;
     if (c > 0xffffffffull) c = 0xffffffffull & ~(uint64_t)63;
     if (fit) {
-      const uint64_t floor_c = std::max<uint64_t>(512, 2 * 64 * (uint64_t)variant_words(v));
+      const uint64_t floor_c =
+          fit_floor ? fit_floor : std::max<uint64_t>(512, 2 * 64 * (uint64_t)variant_words(v));
       uint64_t want = floor_c;
       while (want < c && want * grid_lanes < total[v]) want *= 2;
       c = std::min(c, want);

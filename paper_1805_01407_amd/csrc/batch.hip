@@ -19,22 +19,11 @@ namespace slrng {
 template <int T, bool A16>
 __device__ __forceinline__ void store_tile_rows(const u64 *lds, int lane, const u64 *rowptr,
                                                 const unsigned *rowlen, int nrows, unsigned t0,
-                                                int m, bool full) {
+                                                int m) {
   constexpr int S = TileGeom<T>::kStride;
   if constexpr (A16) {
     constexpr int LPR = T / 2;
     constexpr int RPI = kWave / LPR;
-    if (full) {  // all 64 rows have T more outputs: no predicates
-      const int r0 = lane / LPR;
-      const int c = 2 * (lane % LPR);
-#pragma unroll
-      for (int q = 0; q < T / 2; q++) {
-        const int r = q * RPI + r0;
-        const u64x2 v = *reinterpret_cast<const u64x2 *>(lds + r * S + c);
-        out_store(reinterpret_cast<u64x2 *>(reinterpret_cast<u64 *>(rowptr[r]) + t0 + c), v);
-      }
-      return;
-    }
 #pragma unroll
     for (int q = 0; q < T / 2; q++) {
       const int r = q * RPI + lane / LPR;
@@ -45,8 +34,8 @@ __device__ __forceinline__ void store_tile_rows(const u64 *lds, int lane, const 
         if (col < len) {
           const u64x2 v = *reinterpret_cast<const u64x2 *>(lds + r * S + c);
           u64 *dst = reinterpret_cast<u64 *>(rowptr[r]) + col;
-          if (col + 1 < len && c + 1 < m) out_store(reinterpret_cast<u64x2 *>(dst), v);
-          else out_store(dst, v.x);
+          if (col + 1 < len && c + 1 < m) out_store_wt(reinterpret_cast<u64x2 *>(dst), v);
+          else out_store_wt(dst, v.x);
         }
       }
     }
@@ -59,10 +48,30 @@ __device__ __forceinline__ void store_tile_rows(const u64 *lds, int lane, const 
       const int c = lane % LPR;
       if (r < nrows && c < m) {
         const unsigned col = t0 + (unsigned)c;
-        if (col < rowlen[r]) out_store(reinterpret_cast<u64 *>(rowptr[r]) + col, lds[r * S + c]);
+        if (col < rowlen[r]) out_store_wt(reinterpret_cast<u64 *>(rowptr[r]) + col, lds[r * S + c]);
       }
     }
   }
+}
+
+// The unpredicated store of a full tile (all 64 rows have T more outputs,
+// 16-byte aligned rows): lane (r0, c) of the 16-byte layout writes rows
+// q*RPI + r0, whose destinations (column c) it holds in dst[q].  All LDS reads
+// first, then the stores, so that the reads overlap.
+template <int T>
+__device__ __forceinline__ void store_tile_full(const u64 *lds, int lane, const u64 (&dst)[T / 2],
+                                                unsigned t0) {
+  constexpr int S = TileGeom<T>::kStride;
+  constexpr int LPR = T / 2;
+  constexpr int RPI = kWave / LPR;
+  const int r0 = lane / LPR;
+  const int c = 2 * (lane % LPR);
+  u64x2 v[T / 2];
+#pragma unroll
+  for (int q = 0; q < T / 2; q++) v[q] = *reinterpret_cast<const u64x2 *>(lds + (q * RPI + r0) * S + c);
+  __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+  for (int q = 0; q < T / 2; q++) out_store_wt(reinterpret_cast<u64x2 *>(dst[q] + (u64)t0 * 8), v[q]);
 }
 
 template <int V, int KIND, int T>
@@ -107,6 +116,16 @@ __device__ __forceinline__ void batch_tile(const BatchArgs &a, const TileDesc &t
   rowlen[lane] = ld.len;
   const bool a16 = __all((ld.out & 15) == 0);
   wave_sync();
+  // destinations of the unpredicated path (16-byte layout), loaded once
+  u64 dst[T / 2];
+  {
+    constexpr int LPR = T / 2;
+    constexpr int RPI = kWave / LPR;
+    const int r0 = lane / LPR;
+    const u64 c8 = 16 * (u64)(lane % LPR);
+#pragma unroll
+    for (int q = 0; q < T / 2; q++) dst[q] = rowptr[q * RPI + r0] + c8;
+  }
   u64 *myrow = lds + lane * TileGeom<T>::kStride;
   const int nrows = td.nlanes;
   for (unsigned t0 = 0; t0 < td.max_len; t0 += T) {
@@ -115,8 +134,9 @@ __device__ __forceinline__ void batch_tile(const BatchArgs &a, const TileDesc &t
     else gen_tile_partial<V, KIND, T>(s, myrow, m);
     wave_sync();
     const bool full = nrows == kWave && m == T && t0 + T <= td.min_len;
-    if (a16) store_tile_rows<T, true>(lds, lane, rowptr, rowlen, nrows, t0, m, full);
-    else store_tile_rows<T, false>(lds, lane, rowptr, rowlen, nrows, t0, m, full);
+    if (a16 && full) store_tile_full<T>(lds, lane, dst, t0);
+    else if (a16) store_tile_rows<T, true>(lds, lane, rowptr, rowlen, nrows, t0, m);
+    else store_tile_rows<T, false>(lds, lane, rowptr, rowlen, nrows, t0, m);
     wave_sync();
   }
 }

@@ -52,6 +52,32 @@ SL_HD u64 rotl(u64 x) {
 #endif
 }
 
+// Three-input bitwise functions.  On gfx950 each 32-bit half is one
+// v_bitop3_b32, whose 8-bit immediate is the truth table indexed by
+// 4 a + 2 b + c for input bits (a, b, c): 0x96 is a ^ b ^ c and 0x6a is
+// c ^ (a & b).
+SL_HD u64 xor3(u64 a, u64 b, u64 c) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  const unsigned lo = __builtin_amdgcn_bitop3_b32((unsigned)a, (unsigned)b, (unsigned)c, 0x96);
+  const unsigned hi =
+      __builtin_amdgcn_bitop3_b32((unsigned)(a >> 32), (unsigned)(b >> 32), (unsigned)(c >> 32), 0x96);
+  return ((u64)hi << 32) | lo;
+#else
+  return a ^ b ^ c;
+#endif
+}
+
+// acc ^ (s & m) with the same 32-bit mask m (0 or all ones) for both halves.
+SL_HD u64 xor_and(u64 acc, u64 s, unsigned m) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  const unsigned lo = __builtin_amdgcn_bitop3_b32((unsigned)s, m, (unsigned)acc, 0x6a);
+  const unsigned hi = __builtin_amdgcn_bitop3_b32((unsigned)(s >> 32), m, (unsigned)(acc >> 32), 0x6a);
+  return ((u64)hi << 32) | lo;
+#else
+  return acc ^ (s & (((u64)m << 32) | m));
+#endif
+}
+
 // ** multiplies by 2^s + 1 (S = 5, T = 9 in tab:scr64), which the paper notes
 // can be computed as a shift and a sum.  On the GPU that is one
 // v_lshl_add_u64 (the compiler would otherwise turn it back into 32-bit
@@ -164,32 +190,44 @@ SL_HD void step(u64 (&s)[Params<V>::k]) {
     // the updated pair lands in the slots of s[q] and s[p] of the figure:
     // for two words that is s[0] and s[1]; for 16 words s[P+15] and s[P]
     if constexpr (K == 2) {
-      s[0] = rotl<Q::a>(s0) ^ t ^ (t << Q::b);
+      s[0] = xor3(rotl<Q::a>(s0), t, t << Q::b);
       s[1] = rotl<Q::c>(t);
     } else {
-      s[il] = rotl<Q::a>(s0) ^ t ^ (t << Q::b);
+      s[il] = xor3(rotl<Q::a>(s0), t, t << Q::b);
       s[i0] = rotl<Q::c>(t);
     }
   } else if constexpr (K == 4) {
+    // the figure's six in-place updates, each word written once from the
+    // old values: s2 ^= s0; s3 ^= s1; s1 ^= s2; s0 ^= s3; s2 ^= t; rotate s3
     const u64 t = s[1] << Q::a;
-    s[2] ^= s[0];
-    s[3] ^= s[1];
-    s[1] ^= s[2];
-    s[0] ^= s[3];
-    s[2] ^= t;
-    s[3] = rotl<Q::b>(s[3]);
+    const u64 n0 = xor3(s[0], s[3], s[1]);
+    const u64 n1 = xor3(s[1], s[2], s[0]);
+    const u64 n2 = xor3(s[2], s[0], t);
+    const u64 n3 = rotl<Q::b>(s[3] ^ s[1]);
+    s[0] = n0;
+    s[1] = n1;
+    s[2] = n2;
+    s[3] = n3;
   } else {
+    // likewise for the eight-word figure: s2 ^= s0; s5 ^= s1; s1 ^= s2;
+    // s7 ^= s3; s3 ^= s4; s4 ^= s5; s0 ^= s6; s6 ^= s7; s6 ^= t; rotate s7
     const u64 t = s[1] << Q::a;
-    s[2] ^= s[0];
-    s[5] ^= s[1];
-    s[1] ^= s[2];
-    s[7] ^= s[3];
-    s[3] ^= s[4];
-    s[4] ^= s[5];
-    s[0] ^= s[6];
-    s[6] ^= s[7];
-    s[6] ^= t;
-    s[7] = rotl<Q::b>(s[7]);
+    const u64 n0 = s[0] ^ s[6];
+    const u64 n1 = xor3(s[1], s[2], s[0]);
+    const u64 n2 = s[2] ^ s[0];
+    const u64 n3 = s[3] ^ s[4];
+    const u64 n4 = xor3(s[4], s[5], s[1]);
+    const u64 n5 = s[5] ^ s[1];
+    const u64 n6 = xor3(s[6], s[7], s[3] ^ t);
+    const u64 n7 = rotl<Q::b>(s[7] ^ s[3]);
+    s[0] = n0;
+    s[1] = n1;
+    s[2] = n2;
+    s[3] = n3;
+    s[4] = n4;
+    s[5] = n5;
+    s[6] = n6;
+    s[7] = n7;
   }
 }
 

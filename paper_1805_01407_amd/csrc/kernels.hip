@@ -9,7 +9,8 @@
 //    are contiguous.  Each wave stages a tile of T outputs per lane in LDS
 //    (row = lane) and then reads it back column-wise so that each
 //    global_store_dwordx4 writes whole 128/256-byte runs of a few rows:
-//    fully coalesced, nontemporal (write-once data, no reuse);
+//    fully coalesced, plain write-back stores (nontemporal and write-through
+//    stores measured slower for this stream-major pattern);
 //  * waves never wait on each other: every wave owns its LDS rows and the
 //    LDS exchange inside a wave is ordered by the in-order LDS queue plus
 //    a wavefront-scope fence (no workgroup barrier);
@@ -115,6 +116,41 @@ __global__ __launch_bounds__(kBlock) void k_jump(u64 *__restrict__ state, u64 S,
   }
 }
 
+// Stream i advances by J_i = steps[2i] + 2^64 steps[2i+1]: for each
+// radix-1024 digit d_l of J_i, one per-lane jump by x^(d_l 2^(10 l)) mod p
+// (entry 0 is the polynomial 1, the identity, for lanes whose digit is 0).
+// A level is skipped when the digit is 0 in every lane of the wave.
+template <int V>
+__global__ __launch_bounds__(kBlock) void k_advance_each(u64 *__restrict__ state, u64 S,
+                                                         const u64 *__restrict__ steps,
+                                                         const u64 *__restrict__ tab) {
+  constexpr int K = Params<V>::k;
+  const u64 i = (u64)blockIdx.x * kBlock + threadIdx.x;
+  const u64 first = i - (threadIdx.x % kWave);
+  if (first >= S) return;  // uniform per wave
+  const bool live = i < S;
+  u64 s[K];
+#pragma unroll
+  for (int w = 0; w < K; w++) s[w] = live ? state[(u64)w * S + i] : 0;
+  const u64 lo = live ? steps[2 * i] : 0;
+  const u64 hi = live ? steps[2 * i + 1] : 0;
+  for (int l = 0; l < kDigitLevels; l++) {
+    const int sh = 10 * l;
+    u64 bits;
+    if (sh + 10 <= 64) bits = lo >> sh;
+    else if (sh >= 64) bits = hi >> (sh - 64);
+    else bits = (lo >> sh) | (hi << (64 - sh));
+    const unsigned d = (unsigned)(bits & (kTabRadix - 1));
+    if (!__any(d != 0)) continue;
+    const u64 *t = tab + (u64)l * K * kTabRadix;
+    jump_lane<V>(s, [&](int wi) { return t[(u64)wi * kTabRadix + d]; });
+  }
+  if (live) {
+#pragma unroll
+    for (int w = 0; w < K; w++) state[(u64)w * S + i] = s[w];
+  }
+}
+
 // ---------------------------------------------------------------- calibration
 
 __global__ __launch_bounds__(kBlock) void k_write_ceiling(u64x2 *out, u64 n16) {
@@ -200,6 +236,21 @@ hipError_t launch_jump(int variant, uint64_t *state, uint64_t S, const UPoly &r,
 #define SL_JMP(V) jump_v<V>(state, S, r, st)
   SL_DISPATCH(variant, SL_JMP)
 #undef SL_JMP
+}
+
+template <int V>
+static hipError_t advance_each_v(u64 *state, u64 S, const u64 *steps, const u64 *tab,
+                                 hipStream_t st) {
+  dim3 grid((unsigned)((S + kBlock - 1) / kBlock));
+  hipLaunchKernelGGL((k_advance_each<V>), grid, dim3(kBlock), 0, st, state, S, steps, tab);
+  return hipGetLastError();
+}
+
+hipError_t launch_advance_each(int variant, uint64_t *state, uint64_t S, const uint64_t *steps,
+                               const uint64_t *tab, hipStream_t st) {
+#define SL_ADV(V) advance_each_v<V>(state, S, steps, tab, st)
+  SL_DISPATCH(variant, SL_ADV)
+#undef SL_ADV
 }
 
 hipError_t launch_write_ceiling(void *out, uint64_t bytes, hipStream_t st) {

@@ -59,6 +59,13 @@ hipError_t launch_position(int variant, uint64_t seed, uint64_t S, const uint64_
 // In-place jump of S word-major states by one polynomial.
 hipError_t launch_jump(int variant, uint64_t *state, uint64_t S, const UPoly &r, hipStream_t st);
 
+// In-place advance of stream i by its own 128-bit distance (steps[2i] +
+// 2^64 steps[2i+1]) with the radix-1024 digit tables: word w of entry d of
+// level l at tab[(l*W + w)*1024 + d], W = k words, kDigitLevels levels.
+constexpr int kDigitLevels = 13;  // ceil(128 / 10)
+hipError_t launch_advance_each(int variant, uint64_t *state, uint64_t S, const uint64_t *steps,
+                               const uint64_t *tab, hipStream_t st);
+
 // Calibration: write `bytes` of a constant with the same store path, and a
 // plain copy kernel.
 hipError_t launch_write_ceiling(void *out, uint64_t bytes, hipStream_t st);

@@ -216,7 +216,7 @@ static int launch_iteration(slrng_server *sv, int si, const std::vector<PlanReq>
   Slot &s = sv->slots[si];
   PlanHost P;
   int rc = build_plan(pr.data(), pr.size(), sv->bo, sv->device, (uint64_t)sv->blocks * kBlock, P,
-                      /*fit=*/true);
+                      /*fit=*/true, (uint64_t)sv->o.min_chunk);
   if (rc) return rc;
   rc = slot_reserve(s, P.tiles.size(), P.lanes.size(), P.runs.size(), P.rs.seeds.size());
   if (rc) return rc;
@@ -458,7 +458,7 @@ extern "C" int slrng_server_create(const slrng_server_opts *opts, slrng_server *
   if (!valid_variant(o.variant) || o.n_streams == 0 || o.budget_bytes < kAlign) return SLRNG_EINVAL;
   if (o.max_batch <= 0) o.max_batch = 4096;
   if (o.inflight <= 0) o.inflight = 3;
-  if (o.inflight > 8) return SLRNG_EINVAL;
+  if (o.inflight > 8 || o.min_chunk < 0 || o.window_us < 0) return SLRNG_EINVAL;
   if (o.tile == 0) o.tile = 32;
   slrng_batch_opts bo;
   slrng_batch_default_opts(&bo);
