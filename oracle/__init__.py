@@ -82,6 +82,7 @@ def lib():
         L.orc_charpoly.restype = ctypes.c_long
         L.orc_jump_poly.argtypes = [g, u64p, u64p]
         L.orc_stream_chain.argtypes = [g, ctypes.c_uint64, u64p, ctypes.c_uint64, u64p]
+        L.orc_seed_state.argtypes = [g, ctypes.c_uint64, u64p]
         L.orc_jump_many.argtypes = [g, u64p, ctypes.c_uint64, u64p, ctypes.c_int]
         L.orc_period.argtypes = [g, u64p, ctypes.c_uint64]
         L.orc_period.restype = ctypes.c_uint64
@@ -141,6 +142,27 @@ GEN64 = {
     "xoroshiro1024**": Gen(XOROSHIRO, 64, 16, 25, 27, 36, **SS),
     "xoroshiro1024*": Gen(XOROSHIRO, 64, 16, 25, 27, 36, STAR, ms=STAR_S),
 }
+
+
+# Section "The 32-bit case": tables tab:par32 (engines xoroshiro64 26/9/13,
+# xoshiro128 9/11) and tab:scr32 (scramblers).  The * and ** of xoroshiro64
+# multiply by 0x9E3779BB (** with R = 5, T = 5); ** of xoshiro128 has S = 5,
+# R = 7, T = 9, and its ++ rotates by 7.
+STAR32_S = 0x9E3779BB
+GEN32 = {
+    "xoroshiro64*": Gen(XOROSHIRO, 32, 2, 26, 9, 13, STAR, ms=STAR32_S),
+    "xoroshiro64**": Gen(XOROSHIRO, 32, 2, 26, 9, 13, STARSTAR, r=5, ms=STAR32_S, mt=5),
+    "xoshiro128+": Gen(XOSHIRO, 32, 4, 9, 11, 0, PLUS),
+    "xoshiro128++": Gen(XOSHIRO, 32, 4, 9, 11, 0, PLUSPLUS, 7),
+    "xoshiro128**": Gen(XOSHIRO, 32, 4, 9, 11, 0, STARSTAR, r=7, ms=5, mt=9),
+}
+
+
+def to_float32(v) -> np.ndarray:
+    """Upper 24 bits of 32-bit outputs as floats in [0, 1): (v >> 8) * 2^-24,
+    exact (the 32-bit analogue of the 53-bit doubles)."""
+    v = np.asarray(v, dtype=np.uint64)
+    return ((v >> np.uint64(8)).astype(np.float64) * 2.0**-24).astype(np.float32)
 
 
 def _u64p(a: np.ndarray):
@@ -343,10 +365,18 @@ def stream_chain(g: Gen, seed: int, S: int, J: int | None = None) -> np.ndarray:
     return out
 
 
+def seed_state(g: Gen, seed: int) -> np.ndarray:
+    """The seeded base state: SplitMix64 outputs as the words (64-bit words),
+    or the SplitMix64 output stream cut into 32-bit words, low half first."""
+    x = np.zeros(g.k, dtype=np.uint64)
+    lib().orc_seed_state(ctypes.byref(g.c_struct()), seed & 0xFFFFFFFFFFFFFFFF, _u64p(x))
+    return x
+
+
 def stream_state(g: Gen, seed: int, i: int, extra_steps: int = 0) -> np.ndarray:
     """Stream i of the chain, advanced by extra_steps, computed directly by one
     jump of distance i*2^(n/2) + extra_steps."""
-    base = splitmix_fill(seed, g.k)
+    base = seed_state(g, seed)
     return jump(g, base, i * jump_distance(g, "jump") + extra_steps)
 
 

@@ -35,6 +35,13 @@
  *     implementation, since no test vector is available.
  *   - 53-bit doubles: Section "Choosing a generator" (upper 53 bits); the
  *     value is (x >> 11) * 2^-53, exact.
+ *   - 32-bit generators: Section "The 32-bit case", tables tab:par32 and
+ *     tab:scr32; the paper says the word choices of the 64-bit two-word
+ *     xoroshiro and of xoshiro256 carry over to xoroshiro64 and xoshiro128.
+ *     Seeding them: the paper only remarks that a 32-bit SplitMix is
+ *     immediate to define.  Reading taken here: the state array is filled
+ *     with the output stream of SplitMix64, i.e. each 64-bit output gives two
+ *     32-bit words, low half first (parity unpinned, like SplitMix itself).
  *
  * State convention.  A state is k words in the "logical order" of the block
  * matrices: word j of the row vector x = <x_0 .. x_{k-1}> with the next state
@@ -525,13 +532,31 @@ void orc_jump_poly(const orc_gen *g, u64 *x, const u64 *r)
     for (int j = 0; j < g->k; j++) x[j] = acc[j];
 }
 
-/* Stream chain: base = SplitMix fill of seed; stream i = base * (M^J)^i.
+/* Seeded state of a generator.  64-bit words: consecutive SplitMix64
+ * outputs.  32-bit words: the SplitMix64 output stream split into 32-bit
+ * words, low half first (the reading stated at the top).  Any other word
+ * size (the paper's small instances): one output per word, masked. */
+void orc_seed_state(const orc_gen *g, u64 seed, u64 *x)
+{
+    const int k = g->k;
+    if (g->w == 32) {
+        u64 out[ORC_MAXK];
+        orc_splitmix_fill(seed, out, (k + 1) / 2);
+        for (int j = 0; j < k; j++)
+            x[j] = (j & 1) ? (out[j / 2] >> 32) : (out[j / 2] & 0xffffffffULL);
+        return;
+    }
+    orc_splitmix_fill(seed, x, k);
+    for (int j = 0; j < k; j++) x[j] &= wmask(g->w);
+}
+
+/* Stream chain: base = seeded state; stream i = base * (M^J)^i.
  * p is the characteristic polynomial, r = x^J mod p.  states: S x k. */
 void orc_stream_chain(const orc_gen *g, u64 seed, const u64 *r, u64 S, u64 *states)
 {
     const int k = g->k;
     u64 x[ORC_MAXK];
-    orc_splitmix_fill(seed, x, k);
+    orc_seed_state(g, seed, x);
     for (u64 i = 0; i < S; i++) {
         memcpy(states + i * k, x, (size_t)k * 8);
         orc_jump_poly(g, x, r);
