@@ -31,17 +31,29 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+# Sources of the generation kernel: a change to any of them invalidates the
+# committed counter summary.
+KERNEL_SOURCES = ["kernels.hip", "gen_device.hpp", "engines.hpp", "kernels.hpp"]
+
+
+def kernel_source_sha() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_1805_01407_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
 def profiled_traffic() -> int | None:
     """HBM bytes per generation launch from the committed counter summary
     (FETCH_SIZE and WRITE_SIZE, scaled by a copy kernel), or None when the
-    kernel source has changed since those counters were taken."""
-    import hashlib
+    kernel sources have changed since those counters were taken."""
     path = os.path.join(ROOT, "profiles", "k_generate_full_family_sweep_pmc.md")
-    src = os.path.join(ROOT, "paper_1805_01407_amd", "csrc", "kernels.hip")
     try:
         fields = dict(line.split(": ", 1) for line in open(path).read().splitlines()
                       if line.startswith(("traffic_bytes_per_launch: ", "source_sha256: ")))
-        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+        sha = kernel_source_sha()
     except (OSError, ValueError):
         return None
     if fields.get("source_sha256") != sha:
@@ -183,6 +195,64 @@ def positioning_section(P, torch, stream, reps: int = 5) -> dict:
             "generate_frac_of_hbm_peak": round(gbs / HBM_PEAK_GBS, 4)}
 
 
+SWEEP32 = ["xoroshiro64*", "xoroshiro64**", "xoshiro128+", "xoshiro128++", "xoshiro128**"]
+
+
+def gen32_section(P, torch, stream, rounds: int = 2) -> dict:
+    """The 32-bit generators (Section "The 32-bit case"): for each of the five,
+    65,536 streams (seed 1) x 131,072 outputs as uint32 and as floats from the
+    upper 24 bits: 32 GiB per launch, the same bytes as a 64-bit sweep launch.
+    HIP events around every launch; average write bandwidth per generator."""
+    S, N = 65536, 131072
+    buf = torch.empty((S, N), dtype=torch.int32, device="cuda")
+    hs = {name: P.Streams(name, 1, S) for name in SWEEP32}
+    per = {name: [] for name in SWEEP32}
+    for r in range(rounds + 1):
+        for name in SWEEP32:
+            h = hs[name]
+            for kind in (P.SLRNG_U32, P.SLRNG_F32):
+                h.seed(1, stream)
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+                P.slrng_generate(h.h, kind, N, buf.data_ptr(), N, stream)
+                e1.record(stream)
+                torch.cuda.synchronize()
+                if r:  # round 0 is a warm-up
+                    per[name].append(e0.elapsed_time(e1))
+    for h in hs.values():
+        h.close()
+    del buf
+    torch.cuda.empty_cache()
+    nbytes = 4 * S * N
+    gbs = {name: round(nbytes / (sum(v) / len(v) * 1e-3) / 1e9, 1) for name, v in per.items()}
+    allv = [t for v in per.values() for t in v]
+    avg = nbytes / (sum(allv) / len(allv) * 1e-3) / 1e9
+    return {"streams": S, "outputs_per_stream": N, "bytes_per_launch": nbytes,
+            "outputs_per_s": avg * 1e9 / 4, "GBs": round(avg, 1),
+            "frac_of_hbm_peak": round(avg / HBM_PEAK_GBS, 4), "GBs_per_generator": gbs}
+
+
+def lincomp_section(P, torch, stream, reps: int = 3) -> dict:
+    """On-device linearity check: Berlekamp-Massey on bit 0 of 2n outputs of
+    each of 65,536 xoshiro256+ streams (complexity n = 256 expected, table
+    tab:plusdeg).  Reports the time per check and the streams checked per
+    second."""
+    name, S, nbits = "xoshiro256+", 65536, 512
+    with P.Streams(name, 1, S) as h:
+        h.linear_complexity(0, nbits, stream)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            lc = h.linear_complexity(0, nbits, stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        ok = bool((lc == 256).all().item())
+    return {"generator": name, "streams": S, "bit": 0, "nbits": nbits, "ms": round(ms, 3),
+            "streams_per_s": S / (ms * 1e-3), "all_equal_n": ok}
+
+
 def serving_section(P, seconds: float) -> dict:
     """The serving workload: Poisson arrivals at 20,000 requests/s on 4,096
     device-resident xoshiro256** streams (seed 42), sizes log-uniform in
@@ -310,6 +380,8 @@ def main():
     del buf_u, buf_f
     torch.cuda.empty_cache()
     positioned = positioning_section(P, torch, stream)
+    gen32 = gen32_section(P, torch, stream)
+    lincomp = lincomp_section(P, torch, stream)
     batched = None if args.no_batch else batched_section(P, torch, stream)
     served = None if args.serve_seconds <= 0 else serving_section(P, args.serve_seconds)
 
@@ -337,6 +409,8 @@ def main():
         "write_ceiling_GBs": ceiling,
         "gen_GBs_per_generator": per_variant,
         "jump_ahead_at_scale": positioned,
+        "generators_32bit": gen32,
+        "linearity_check": lincomp,
         "batched_requests": batched,
         "serving": served,
         "cpu_baseline": cpu,

@@ -24,6 +24,14 @@
  *    "Choosing a generator").
  *  - Seeding: the state is filled with consecutive outputs of SplitMix64
  *    seeded with the 64-bit seed (Section "Choosing a generator").
+ *  - 32-bit generators (ids 14 .. 18): states are k = 2 or 4 32-bit words,
+ *    exchanged through the same uint64 host arrays (one word per element,
+ *    upper half zero; set_state rejects larger values with SLRNG_EINVAL).
+ *    Seeding fills the state array with the SplitMix64 output stream, each
+ *    64-bit output giving two words, low half first (the paper only says a
+ *    32-bit SplitMix is immediate to define).  Their outputs are 32-bit
+ *    (SLRNG_U32, SLRNG_F32).  Batches and the server take the 64-bit
+ *    generators only.
  *  - Jumps (Section "Combining linear engines and scramblers": every generator
  *    has jump functions): SLRNG_JUMP advances by 2^(n/2) steps and
  *    SLRNG_LONG_JUMP by 2^(3n/4) steps, n = 64k the state size in bits.
@@ -61,12 +69,23 @@ typedef enum slrng_variant {
   SLRNG_XOROSHIRO1024_STARSTAR = 11, /* rotl(s0 * 5, 7) * 9 */
   SLRNG_XOROSHIRO128_STAR = 12,      /* s0 * 0x9e3779b97f4a7c13 */
   SLRNG_XOROSHIRO1024_STAR = 13,     /* s0 * 0x9e3779b97f4a7c13 */
-  SLRNG_NUM_VARIANTS = 14
+  SLRNG_NUM_VARIANTS = 14,           /* the 64-bit generators are ids 0 .. 13 */
+  /* 32-bit generators (Section "The 32-bit case", tables tab:par32 and
+   * tab:scr32; words read as in fig:xoroshiro128 and fig:xoshiro256) */
+  SLRNG_XOROSHIRO64_STAR = 14,       /* s0 * 0x9E3779BB, engine 26/9/13 */
+  SLRNG_XOROSHIRO64_STARSTAR = 15,   /* rotl(s0 * 0x9E3779BB, 5) * 5 */
+  SLRNG_XOSHIRO128_PLUS = 16,        /* s0 + s3, engine 9/11 */
+  SLRNG_XOSHIRO128_PLUSPLUS = 17,    /* rotl(s0 + s3, 7) + s0 */
+  SLRNG_XOSHIRO128_STARSTAR = 18,    /* rotl(s1 * 5, 7) * 9 */
+  SLRNG_NUM_VARIANTS_ALL = 19
 } slrng_variant;
 
 typedef enum slrng_kind {
-  SLRNG_U64 = 0, /* uint64 outputs */
-  SLRNG_F64 = 1  /* doubles in [0, 1) from the upper 53 bits */
+  SLRNG_U64 = 0, /* uint64 outputs (64-bit generators) */
+  SLRNG_F64 = 1, /* doubles in [0, 1) from the upper 53 bits (64-bit generators) */
+  SLRNG_U32 = 2, /* uint32 outputs (32-bit generators) */
+  SLRNG_F32 = 3  /* floats in [0, 1) from the upper 24 bits, (x >> 8) * 2^-24,
+                    exact (32-bit generators) */
 } slrng_kind;
 
 typedef enum slrng_jump_kind {
@@ -120,7 +139,8 @@ int slrng_jump_poly(int variant, const uint64_t *J_words, int nj, uint64_t *out,
  * base state is the SplitMix64 fill of `seed` and stream i is the base
  * jumped i times by SLRNG_JUMP, i.e. state_i = base * M^(i 2^(n/2)).
  * n_streams in [1, 2^31] (ERANGE otherwise).  The handle owns 2 S k words of
- * device memory.
+ * device memory.  EZEROSTATE if the seed gives the all-zero state (possible
+ * only for xoroshiro64, whose state is a single SplitMix64 output).
  *
  * slrng_streams_create_from_states: S streams with the given logical-order
  * states, host_words[i*k + j] = word j of stream i.  EZEROSTATE if a state is
@@ -136,10 +156,11 @@ int slrng_jump_poly(int variant, const uint64_t *J_words, int nj, uint64_t *out,
  *
  * slrng_generate: for every stream i, out[i*ld + t] = output t, t < n; the
  * stream then stands n steps further (generate(a); generate(b) produces the
- * same values as generate(a + b)).  dev_out: device memory, 8-byte aligned,
+ * same values as generate(a + b)).  dev_out: device memory aligned to the
+ * element (8 bytes for SLRNG_U64 / SLRNG_F64, 4 for SLRNG_U32 / SLRNG_F32),
  * at least (S-1) ld + n elements; ld >= n (EINVAL otherwise), overflow of the
- * extent is ERANGE.  n = 0 is a successful no-op.  kind selects uint64 or
- * doubles; both are bit-exact.
+ * extent is ERANGE.  n = 0 is a successful no-op.  kind must match the
+ * generator's word size (EINVAL otherwise); all kinds are bit-exact.
  *
  * slrng_get_state / slrng_set_state: copy the S x k logical-order states to or
  * from host memory (host_words[i*k + j]); synchronous on `stream`.  set_state
@@ -168,6 +189,18 @@ int slrng_streams_jump(slrng_streams *h, int jump_kind, hipStream_t stream);
 int slrng_streams_advance(slrng_streams *h, uint64_t steps_hi, uint64_t steps_lo,
                           hipStream_t stream);
 int slrng_streams_advance_each(slrng_streams *h, const uint64_t *dev_steps, hipStream_t stream);
+
+/* slrng_linear_complexity: an on-device linearity check.  For every stream
+ * i, dev_lc[i] = the linear complexity of bit `bit` of its next nbits outputs
+ * (the integer outputs, before any conversion), computed with the
+ * Berlekamp-Massey algorithm as in Section "A theoretical analysis of
+ * scramblers" (e.g. bit 0 of the + and * scramblers has the engine's
+ * complexity n, table tab:plusdeg; the result is the true complexity when
+ * nbits >= 2 x complexity).  The streams are not advanced.  bit < 64 (< 32
+ * for the 32-bit generators), nbits a multiple of 32 in [32, 2560]; dev_lc:
+ * device memory, 4-byte aligned, S uint32.  Asynchronous.  EINVAL otherwise. */
+int slrng_linear_complexity(const slrng_streams *h, int bit, uint32_t nbits, uint32_t *dev_lc,
+                            hipStream_t stream);
 int slrng_generate(slrng_streams *h, int kind, uint64_t n, void *dev_out, uint64_t ld,
                    hipStream_t stream);
 int slrng_get_state(const slrng_streams *h, uint64_t *host_words, hipStream_t stream);
@@ -319,7 +352,9 @@ typedef struct slrng_server_opts {
   int32_t tile;          /* 16 or 32 (0 = default) */
   int32_t waves_per_cu;  /* persistent grid (0 = default) */
   int32_t window_us;     /* batching window: an iteration waits until its oldest
-                            request is this old (default 250; 0 = launch at once) ... */
+                            request is this old (default 0: launch as soon as a
+                            slot is free; requests arriving meanwhile wait for
+                            the next iteration) ... */
   int32_t min_chunk;     /* smallest lane-chunk (outputs) when the chunk length is
                             fitted to an iteration (0 = default: the larger of
                             512 and 2n, n the state bits) */

@@ -9,15 +9,15 @@ raises if the library has not been built (``python -m
 paper_1805_01407_amd.build``).
 """
 from .binding import (  # noqa: F401
-    VARIANTS, VARIANT_IDS, SlrngError, Streams, lib, library_path,
+    VARIANTS, VARIANTS32, VARIANT_IDS, SlrngError, Streams, lib, library_path,
     slrng_version, slrng_strerror, slrng_last_hip_error, slrng_state_words,
     slrng_charpoly, slrng_jump_poly,
     slrng_streams_create, slrng_streams_create_from_states, slrng_streams_count,
     slrng_streams_variant, slrng_streams_seed,
-    slrng_streams_jump, slrng_streams_advance, slrng_streams_advance_each, slrng_generate,
+    slrng_streams_jump, slrng_streams_advance, slrng_streams_advance_each, slrng_generate, slrng_linear_complexity,
     slrng_get_state, slrng_set_state, slrng_streams_destroy,
     slrng_get_tuning, slrng_set_tuning, slrng_calib_write, slrng_calib_copy,
-    SLRNG_U64, SLRNG_F64, SLRNG_JUMP, SLRNG_LONG_JUMP,
+    SLRNG_U64, SLRNG_F64, SLRNG_U32, SLRNG_F32, SLRNG_JUMP, SLRNG_LONG_JUMP,
     SLRNG_BATCH_GRAPH, SLRNG_BATCH_PERSISTENT, SLRNG_BATCH_PLAIN, REQUEST_DTYPE, make_requests,
     slrng_batch_default_opts, slrng_batch_plan, slrng_batch_launch, slrng_batch_info,
     slrng_batch_destroy, slrng_batch_run, slrng_batch_latencies, set_batch_defaults,

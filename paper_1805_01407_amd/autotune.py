@@ -51,23 +51,27 @@ def _time_ms(fn, reps: int) -> float:
 
 
 def tune_generate(variants, S=65536, N=65536, reps=5, quick=False, log=print) -> dict:
+    """64-bit generators: S x N outputs; 32-bit ones: S x 2N (the same bytes)."""
     import torch
     from . import binding as B
     buf = torch.empty((S, N), dtype=torch.int64, device="cuda")
     out = {}
-    tiles = (16, 32)
     waves = (4096, 8192) if quick else (2048, 4096, 8192, 16384)
     skews = (1, 4) if quick else (1, 4, 16)
     for name in variants:
-        for kind in (B.SLRNG_U64, B.SLRNG_F64):
+        w32 = name in B.VARIANTS32
+        tiles = (64,) if w32 else (16, 32)
+        n_out = 2 * N if w32 else N
+        kinds = (B.SLRNG_U32, B.SLRNG_F32) if w32 else (B.SLRNG_U64, B.SLRNG_F64)
+        for kind in kinds:
             best = None
             with B.Streams(name, 1, S) as h:
                 for tile in tiles:
                     for tw in waves:
                         for sk in skews:
                             B.slrng_set_tuning(name, kind, tile, tw, 1024, sk)
-                            ms = _time_ms(lambda: B.slrng_generate(h.h, kind, N, buf.data_ptr(), N),
-                                          reps)
+                            ms = _time_ms(lambda: B.slrng_generate(h.h, kind, n_out, buf.data_ptr(),
+                                                                   n_out), reps)
                             if best is None or ms < best[0]:
                                 best = (ms, {"tile": tile, "target_waves": tw, "skew": sk,
                                              "min_chunk": 1024})
@@ -156,7 +160,7 @@ def main(argv=None):
     data = load(args.out) or {}
     entry = data.get(arch, {})
     if args.only in (None, "generate"):
-        entry["generate"] = tune_generate(B.VARIANTS, quick=args.quick)
+        entry["generate"] = tune_generate(B.VARIANTS + B.VARIANTS32, quick=args.quick)
     if args.only in (None, "batch"):
         entry["batch"] = tune_batch(quick=args.quick)
     data[arch] = entry

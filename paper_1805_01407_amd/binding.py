@@ -15,7 +15,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(HERE, "libslrng.so")
 
-SLRNG_U64, SLRNG_F64 = 0, 1
+SLRNG_U64, SLRNG_F64, SLRNG_U32, SLRNG_F32 = 0, 1, 2, 3
 SLRNG_JUMP, SLRNG_LONG_JUMP = 0, 1
 
 VARIANTS = [
@@ -25,7 +25,9 @@ VARIANTS = [
     "xoroshiro1024+", "xoroshiro1024++", "xoroshiro1024**",
     "xoroshiro128*", "xoroshiro1024*",
 ]
-VARIANT_IDS = {name: i for i, name in enumerate(VARIANTS)}
+# 32-bit generators (ids 14 .. 18; uint32 / float outputs)
+VARIANTS32 = ["xoroshiro64*", "xoroshiro64**", "xoshiro128+", "xoshiro128++", "xoshiro128**"]
+VARIANT_IDS = {name: i for i, name in enumerate(VARIANTS + VARIANTS32)}
 _ERRNAMES = {-1: "EINVAL", -2: "ERANGE", -3: "ENOMEM", -4: "EZEROSTATE", -5: "EAGAIN",
              -6: "EHIP", -7: "ENOTIMPL"}
 
@@ -114,6 +116,7 @@ def lib():
         "slrng_streams_jump": ([vp, i32, vp], i32),
         "slrng_streams_advance": ([vp, u64, u64, vp], i32),
         "slrng_streams_advance_each": ([vp, vp, vp], i32),
+        "slrng_linear_complexity": ([vp, i32, ctypes.c_uint32, vp, vp], i32),
         "slrng_generate": ([vp, i32, u64, vp, u64, vp], i32),
         "slrng_get_state": ([vp, u64p, vp], i32),
         "slrng_set_state": ([vp, u64p, vp], i32),
@@ -271,6 +274,12 @@ def slrng_streams_advance_each(h: int, dev_steps: int, stream=None) -> None:
     """dev_steps: device address of 2 S uint64 words (low, high) per stream."""
     _check(lib().slrng_streams_advance_each(h, dev_steps, _stream(stream)),
            "slrng_streams_advance_each")
+
+
+def slrng_linear_complexity(h: int, bit: int, nbits: int, dev_lc: int, stream=None) -> None:
+    """dev_lc: device address of S uint32 results."""
+    _check(lib().slrng_linear_complexity(h, bit, nbits, dev_lc, _stream(stream)),
+           "slrng_linear_complexity")
 
 
 def slrng_generate(h: int, kind: int, n: int, dev_out: int, ld: int, stream=None) -> None:
@@ -506,14 +515,18 @@ class Streams:
     def __exit__(self, *exc):
         self.close()
 
-    def generate(self, n: int, kind: int = SLRNG_U64, out=None, ld: int | None = None,
+    def generate(self, n: int, kind: int | None = None, out=None, ld: int | None = None,
                  stream=None):
-        """Outputs as a torch tensor [S, ld] (int64 bit patterns or float64)."""
+        """Outputs as a torch tensor [S, ld]: int64 / int32 bit patterns, or
+        float64 / float32.  kind defaults to the generator's integers."""
         import torch
+        if kind is None:
+            kind = SLRNG_U32 if self.variant >= len(VARIANTS) else SLRNG_U64
         if ld is None:
             ld = n
         if out is None:
-            dt = torch.int64 if kind == SLRNG_U64 else torch.float64
+            dt = {SLRNG_U64: torch.int64, SLRNG_F64: torch.float64,
+                  SLRNG_U32: torch.int32, SLRNG_F32: torch.float32}[kind]
             out = torch.empty((self.S, max(ld, 1)), dtype=dt, device="cuda")
         slrng_generate(self.h, kind, n, out.data_ptr(), ld, stream)
         return out
@@ -549,6 +562,14 @@ class Streams:
 
     def get_state(self, stream=None) -> np.ndarray:
         return slrng_get_state(self.h, stream)
+
+    def linear_complexity(self, bit: int, nbits: int, stream=None):
+        """Per-stream linear complexity of output bit `bit` over the next
+        nbits outputs (a CUDA int32 tensor of S values); streams unchanged."""
+        import torch
+        out = torch.empty((self.S,), dtype=torch.int32, device="cuda")
+        slrng_linear_complexity(self.h, bit, nbits, out.data_ptr(), stream)
+        return out
 
     def set_state(self, states, stream=None):
         slrng_set_state(self.h, np.asarray(states, dtype=np.uint64).reshape(-1), stream)

@@ -15,8 +15,11 @@
 #include "../../include/slrng_calib.h"
 #include "api_internal.hpp"
 #include "engines.hpp"
+#include "engines32.hpp"
 #include "f2poly.hpp"
 #include "kernels.hpp"
+#include "kernels32.hpp"
+#include "lincomp.hpp"
 
 using namespace slrng;
 
@@ -59,10 +62,21 @@ extern "C" int slrng_last_hip_error(void) { return g_last_hip; }
 
 namespace slrng {
 
-static const int kK[kNumVariants] = {2, 2, 2, 4, 4, 4, 8, 8, 8, 16, 16, 16, 2, 16};
-static const int kEngine[kNumVariants] = {0, 1, 0, 2, 2, 2, 3, 3, 3, 4, 4, 4, 0, 4};
+static const int kK[kEndVariant32] = {2, 2, 2, 4, 4, 4, 8, 8, 8, 16, 16, 16, 2, 16,
+                                      2, 2, 4, 4, 4};
+static const int kEngine[kEndVariant32] = {0, 1, 0, 2, 2, 2, 3, 3, 3, 4, 4, 4, 0, 4,
+                                           5, 5, 6, 6, 6};
 
-bool valid_variant(int v) { return v >= 0 && v < kNumVariants; }
+bool valid_variant(int v) { return v >= 0 && v < kEndVariant32; }
+bool valid_variant64(int v) { return v >= 0 && v < kNumVariants; }
+bool is_variant32(int v) { return v >= kFirstVariant32 && v < kEndVariant32; }
+
+// Kinds a generator accepts, and the index of the kind in its tuning row.
+static bool valid_kind(int v, int kind) {
+  return is_variant32(v) ? (kind == SLRNG_U32 || kind == SLRNG_F32)
+                         : (kind == SLRNG_U64 || kind == SLRNG_F64);
+}
+static int kind_index(int kind) { return kind & 1; }
 int variant_words(int v) { return kK[v]; }
 int variant_engine(int v) { return kEngine[v]; }
 
@@ -219,17 +233,18 @@ int get_slot_polys(int device, int engine, uint64_t C, uint64_t D, const uint64_
 
 // ---------------------------------------------------------------- tuning
 
-static slrng_tuning g_tune[kNumVariants][2];
+static slrng_tuning g_tune[kEndVariant32][2];
 static std::once_flag g_tune_once;
 
 static void init_tuning() {
-  for (int v = 0; v < kNumVariants; v++)
-    for (int k = 0; k < 2; k++) g_tune[v][k] = slrng_tuning{32, 8192, 4, 0, 4096};
+  for (int v = 0; v < kEndVariant32; v++)
+    for (int k = 0; k < 2; k++)
+      g_tune[v][k] = slrng_tuning{is_variant32(v) ? 64 : 32, 8192, 4, 0, 4096};
 }
 
 slrng_tuning tuning_for(int v, int kind) {
   std::call_once(g_tune_once, init_tuning);
-  return g_tune[v][kind];
+  return g_tune[v][kind_index(kind)];
 }
 
 // Slot plan of a generate call: chunks of C outputs (C a multiple of D times
@@ -332,12 +347,20 @@ extern "C" int slrng_streams_destroy(slrng_streams *h) {
 }
 
 static int position(slrng_streams *h, uint64_t seed, hipStream_t stream) {
+  // the base state must not be all zero: only a one-output fill (xoroshiro64)
+  // can be, for one seed
+  uint64_t any = 0;
+  for (int j = 0; j < (is_variant32(h->variant) ? (h->k + 1) / 2 : h->k); j++)
+    any |= splitmix64_mix(seed + (uint64_t)(j + 1) * kGoldenGamma);
+  if (!any) return SLRNG_EZEROSTATE;
   PosTables *t = nullptr;
   const int levels = levels_for(h->S);
   int rc = get_pos_tables(h->device, h->engine, levels, &t);
   if (rc) return rc;
-  hipError_t e = launch_position(h->variant, seed, h->S, t->tab0, t->up, levels,
-                                 h->state[h->cur], stream);
+  hipError_t e =
+      is_variant32(h->variant)
+          ? launch_position32(h->variant, seed, h->S, t->tab0, t->up, levels, h->state[h->cur], stream)
+          : launch_position(h->variant, seed, h->S, t->tab0, t->up, levels, h->state[h->cur], stream);
   return e == hipSuccess ? SLRNG_OK : hip_fail(e);
 }
 
@@ -362,6 +385,14 @@ extern "C" int slrng_streams_seed(slrng_streams *h, uint64_t seed, hipStream_t s
   return position(h, seed, stream);
 }
 
+// 32-bit generators: every word must fit in 32 bits.
+static bool words_fit(int variant, const uint64_t *w, uint64_t S, int k) {
+  if (!is_variant32(variant)) return true;
+  for (uint64_t i = 0; i < S * (uint64_t)k; i++)
+    if (w[i] >> 32) return false;
+  return true;
+}
+
 static bool any_zero_state(const uint64_t *w, uint64_t S, int k) {
   for (uint64_t i = 0; i < S; i++) {
     uint64_t acc = 0;
@@ -373,6 +404,7 @@ static bool any_zero_state(const uint64_t *w, uint64_t S, int k) {
 
 extern "C" int slrng_set_state(slrng_streams *h, const uint64_t *host_words, hipStream_t stream) {
   if (!h || !host_words) return SLRNG_EINVAL;
+  if (!words_fit(h->variant, host_words, h->S, h->k)) return SLRNG_EINVAL;
   if (any_zero_state(host_words, h->S, h->k)) return SLRNG_EZEROSTATE;
   std::vector<uint64_t> soa((size_t)h->S * h->k);
   for (uint64_t i = 0; i < h->S; i++)
@@ -396,6 +428,9 @@ extern "C" int slrng_streams_create_from_states(int variant, const uint64_t *hos
                                                 hipStream_t stream, slrng_streams **out) {
   if (!out || !host_words) return SLRNG_EINVAL;
   *out = nullptr;
+  if (valid_variant(variant) && S > 0 && S <= (1ull << 31) &&
+      !words_fit(variant, host_words, S, variant_words(variant)))
+    return SLRNG_EINVAL;
   if (valid_variant(variant) && S > 0 && S <= (1ull << 31) &&
       any_zero_state(host_words, S, variant_words(variant)))
     return SLRNG_EZEROSTATE;
@@ -431,7 +466,8 @@ extern "C" int slrng_streams_variant(const slrng_streams *h, int *v) {
 static int apply_uniform(slrng_streams *h, const Poly &r, hipStream_t stream) {
   UPoly u;
   for (int i = 0; i < 16; i++) u.w[i] = r.w[i];
-  hipError_t e = launch_jump(h->variant, h->state[h->cur], h->S, u, stream);
+  hipError_t e = is_variant32(h->variant) ? launch_jump32(h->variant, h->state[h->cur], h->S, u, stream)
+                                          : launch_jump(h->variant, h->state[h->cur], h->S, u, stream);
   return e == hipSuccess ? SLRNG_OK : hip_fail(e);
 }
 
@@ -456,21 +492,35 @@ extern "C" int slrng_streams_advance_each(slrng_streams *h, const uint64_t *dev_
   const uint64_t *tab = nullptr;
   int rc = get_digit_tables(h->device, h->engine, &tab);
   if (rc) return rc;
-  hipError_t e = launch_advance_each(h->variant, h->state[h->cur], h->S, dev_steps, tab, stream);
+  hipError_t e =
+      is_variant32(h->variant)
+          ? launch_advance_each32(h->variant, h->state[h->cur], h->S, dev_steps, tab, stream)
+          : launch_advance_each(h->variant, h->state[h->cur], h->S, dev_steps, tab, stream);
+  return e == hipSuccess ? SLRNG_OK : hip_fail(e);
+}
+
+extern "C" int slrng_linear_complexity(const slrng_streams *h, int bit, uint32_t nbits,
+                                       uint32_t *dev_lc, hipStream_t stream) {
+  if (!h || !dev_lc || ((uintptr_t)dev_lc & 3)) return SLRNG_EINVAL;
+  const int wbits = is_variant32(h->variant) ? 32 : 64;
+  if (bit < 0 || bit >= wbits) return SLRNG_EINVAL;
+  if (nbits < 32 || nbits > kLincompMaxBits || nbits % 32) return SLRNG_EINVAL;
+  hipError_t e = launch_lincomp(h->variant, h->state[h->cur], h->S, bit, nbits, dev_lc, stream);
   return e == hipSuccess ? SLRNG_OK : hip_fail(e);
 }
 
 extern "C" int slrng_generate(slrng_streams *h, int kind, uint64_t n, void *dev_out, uint64_t ld,
                               hipStream_t stream) {
-  if (!h || (kind != SLRNG_U64 && kind != SLRNG_F64)) return SLRNG_EINVAL;
+  if (!h || !valid_kind(h->variant, kind)) return SLRNG_EINVAL;
   if (n == 0) return SLRNG_OK;
-  if (!dev_out || ((uintptr_t)dev_out & 7)) return SLRNG_EINVAL;
+  const uint64_t elem = is_variant32(h->variant) ? 4 : 8;
+  if (!dev_out || ((uintptr_t)dev_out & (elem - 1))) return SLRNG_EINVAL;
   if (ld < n) return SLRNG_EINVAL;
   // extent (S-1) ld + n elements, in bytes, must fit in 64 bits
   const uint64_t S1 = h->S - 1;
   if (S1 && ld > (UINT64_MAX - n) / S1) return SLRNG_ERANGE;
   const uint64_t extent = S1 * ld + n;
-  if (extent > UINT64_MAX / 8) return SLRNG_ERANGE;
+  if (extent > UINT64_MAX / elem) return SLRNG_ERANGE;
   const slrng_tuning t = tuning_for(h->variant, kind);
   uint64_t C = 0, nslots = 1, D = 1;
   plan_slots(h->S, n, t, C, nslots, D);
@@ -493,7 +543,8 @@ extern "C" int slrng_generate(slrng_streams *h, int kind, uint64_t n, void *dev_
   a.ld = ld;
   a.slot_polys = sp;
   GenConfig cfg{t.tile};
-  hipError_t e = launch_generate(h->variant, kind, a, cfg, stream);
+  hipError_t e = is_variant32(h->variant) ? launch_generate32(h->variant, kind_index(kind), a, stream)
+                                          : launch_generate(h->variant, kind, a, cfg, stream);
   if (e != hipSuccess) return hip_fail(e);
   if (nslots > 1) h->cur = 1 - h->cur;
   return SLRNG_OK;
@@ -502,22 +553,22 @@ extern "C" int slrng_generate(slrng_streams *h, int kind, uint64_t n, void *dev_
 // ---------------------------------------------------------------- tuning ABI
 
 extern "C" int slrng_get_tuning(int variant, int kind, slrng_tuning *out) {
-  if (!valid_variant(variant) || (kind != SLRNG_U64 && kind != SLRNG_F64) || !out)
-    return SLRNG_EINVAL;
+  if (!valid_variant(variant) || !valid_kind(variant, kind) || !out) return SLRNG_EINVAL;
   *out = tuning_for(variant, kind);
   return SLRNG_OK;
 }
 
 extern "C" int slrng_set_tuning(int variant, int kind, const slrng_tuning *t) {
-  if (!valid_variant(variant) || (kind != SLRNG_U64 && kind != SLRNG_F64) || !t)
-    return SLRNG_EINVAL;
-  if ((t->tile != 16 && t->tile != 32) || t->target_waves < 1 || t->target_waves > (1 << 20) ||
+  if (!valid_variant(variant) || !valid_kind(variant, kind) || !t) return SLRNG_EINVAL;
+  // the 32-bit kernels stage tiles of 64 outputs; the 64-bit ones 16 or 32
+  const bool tile_ok = is_variant32(variant) ? t->tile == 64 : (t->tile == 16 || t->tile == 32);
+  if (!tile_ok || t->target_waves < 1 || t->target_waves > (1 << 20) ||
       t->min_chunk < 1 || t->min_chunk > (1ull << 40) || t->reserved != 0)
     return SLRNG_EINVAL;
   if (t->skew != 1 && t->skew != 2 && t->skew != 4 && t->skew != 8 && t->skew != 16)
     return SLRNG_EINVAL;
   tuning_for(variant, kind);
-  g_tune[variant][kind] = *t;
+  g_tune[variant][kind_index(kind)] = *t;
   return SLRNG_OK;
 }
 

@@ -9,7 +9,9 @@
 namespace slrng {
 
 int hip_fail(hipError_t e);  // records the HIP error, returns SLRNG_EHIP
-bool valid_variant(int v);
+bool valid_variant(int v);    // any generator (64- and 32-bit)
+bool valid_variant64(int v);  // the 64-bit generators (batches, server)
+bool is_variant32(int v);
 int variant_words(int v);
 int variant_engine(int v);
 const Poly &jump_kind_poly(int engine, int jump_kind);

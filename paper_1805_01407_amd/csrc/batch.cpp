@@ -403,7 +403,7 @@ extern "C" int slrng_batch_plan(const slrng_request *reqs, size_t n_reqs,
   std::vector<PlanReq> pr(n_reqs);
   for (size_t r = 0; r < n_reqs; r++) {
     const slrng_request &q = reqs[r];
-    if (!valid_variant(q.variant) || (q.kind != SLRNG_U64 && q.kind != SLRNG_F64)) return SLRNG_EINVAL;
+    if (!valid_variant64(q.variant) || (q.kind != SLRNG_U64 && q.kind != SLRNG_F64)) return SLRNG_EINVAL;
     if (q.n && (!q.dev_out || ((uintptr_t)q.dev_out & 7))) return SLRNG_EINVAL;
     if (q.n > UINT64_MAX / 8) return SLRNG_ERANGE;
     pr[r] = PlanReq{q.variant, q.kind, q.n, (uint64_t)(uintptr_t)q.dev_out, q.start, false, q.seed, 0,

@@ -5,6 +5,7 @@
 #include <vector>
 
 #include "engines.hpp"
+#include "engines32.hpp"
 
 #if defined(__x86_64__)
 #include <immintrin.h>
@@ -244,8 +245,28 @@ static Field derive_field() {
   return f;
 }
 
-static std::once_flag g_once[kNumEngines];
-static Field g_fields[kNumEngines];
+// The same for a 32-bit engine (states of 32-bit words held in u64).
+template <int V>
+static Field derive_field32() {
+  constexpr int K = Params32<V>::k;
+  constexpr int n = 32 * K;
+  u32 s[K];
+  splitmix64_fill32<K>(0x5eedull, s);
+  u64 x[K];
+  for (int j = 0; j < K; j++) x[j] = s[j];
+  std::vector<uint8_t> bits(2 * n);
+  for (int t = 0; t < 2 * n; t++) {
+    bits[t] = (uint8_t)(x[0] & 1);
+    host_step32<V>(x);
+  }
+  Field f;
+  f.n = berlekamp_massey(bits.data(), 2 * n, f.p);
+  return f;
+}
+
+constexpr int kNumEnginesAll = kNumEngines + kNumEngines32;
+static std::once_flag g_once[kNumEnginesAll];
+static Field g_fields[kNumEnginesAll];
 
 static void init_engine(int e) {
   switch (e) {
@@ -253,7 +274,9 @@ static void init_engine(int e) {
     case 1: g_fields[1] = derive_field<1>(); break;
     case 2: g_fields[2] = derive_field<3>(); break;
     case 3: g_fields[3] = derive_field<6>(); break;
-    default: g_fields[4] = derive_field<9>(); break;
+    case 4: g_fields[4] = derive_field<9>(); break;
+    case 5: g_fields[5] = derive_field32<14>(); break;
+    default: g_fields[6] = derive_field32<16>(); break;
   }
   build_reducer(g_fields[e]);
 }

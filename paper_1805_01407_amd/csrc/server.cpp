@@ -104,20 +104,32 @@ struct Req {
   Clock::time_point t_submit;
 };
 
-// One in-flight slot: a HIP stream, events and reusable descriptor buffers.
+// One in-flight slot: a HIP stream, events and reusable buffers.  Everything
+// an iteration reads (the tile claim counter, already zero, then the tile,
+// lane and run descriptors and the request-state inputs) is packed into one
+// pinned buffer and uploaded with a single copy.
 struct Slot {
   hipStream_t st = nullptr;
   hipEvent_t ev0 = nullptr, evk = nullptr, ev1 = nullptr;  // start, generation kernel start, end
   bool busy = false;
-  size_t cap_tiles = 0, cap_lanes = 0, cap_runs = 0, cap_req = 0;
-  TileDesc *d_tiles = nullptr, *h_tiles = nullptr;
-  LaneDesc *d_lanes = nullptr, *h_lanes = nullptr;
-  RunDesc *d_runs = nullptr, *h_runs = nullptr;
-  uint64_t *d_poly = nullptr, *h_poly = nullptr;
-  uint32_t *d_idx = nullptr, *h_idx = nullptr;
-  uint32_t *d_slot = nullptr, *h_slot = nullptr;
+  size_t cap_pack = 0, cap_req = 0;
+  uint8_t *d_pack = nullptr, *h_pack = nullptr;
   uint64_t *d_req_state = nullptr;
-  unsigned *d_counter = nullptr;
+};
+
+// Byte offsets of the parts of a packed upload (each 256-byte aligned).
+struct PackLayout {
+  size_t counter = 0, tiles, lanes, runs, poly, idx, slot, total;
+  PackLayout(size_t nt, size_t nl, size_t nr, size_t nreq) {
+    auto up = [](size_t x) { return (x + 255) & ~(size_t)255; };
+    tiles = 256;
+    lanes = up(tiles + nt * sizeof(TileDesc));
+    runs = up(lanes + nl * sizeof(LaneDesc));
+    poly = up(runs + nr * sizeof(RunDesc));
+    idx = up(poly + nreq * 16 * 8);
+    slot = up(idx + nreq * 4);
+    total = up(slot + nreq * 4);
+  }
 };
 
 struct Iteration {
@@ -159,52 +171,37 @@ struct slrng_server {
   uint64_t iterations = 0, max_inflight = 0, peak_reserved = 0, max_batch_seen = 0, batch_sum = 0;
 };
 
-template <typename T>
-static int grow_pair(T **d, T **h, size_t need, size_t &cap) {
-  if (need <= cap) return SLRNG_OK;
-  const size_t n = std::max<size_t>({need, cap * 2, 64});
-  if (*d) (void)hipFree(*d);
-  if (*h) (void)hipHostFree(*h);
-  *d = nullptr;
-  *h = nullptr;
-  cap = 0;
-  hipError_t e = hipMalloc((void **)d, n * sizeof(T));
-  if (e == hipSuccess) e = hipHostMalloc((void **)h, n * sizeof(T), hipHostMallocDefault);
-  if (e != hipSuccess) return hip_fail(e);
-  cap = n;
+// Make the slot's buffers hold a packed upload of `bytes` and `nreq` request
+// states (the slot is idle: its previous iteration has completed, so the
+// pinned buffer is no longer being copied from).
+static int slot_reserve(Slot &s, size_t bytes, size_t nreq) {
+  if (bytes > s.cap_pack) {
+    const size_t n = std::max<size_t>({bytes, s.cap_pack * 2, (size_t)1 << 16});
+    if (s.d_pack) (void)hipFree(s.d_pack);
+    if (s.h_pack) (void)hipHostFree(s.h_pack);
+    s.d_pack = s.h_pack = nullptr;
+    s.cap_pack = 0;
+    hipError_t e = hipMalloc((void **)&s.d_pack, n);
+    if (e == hipSuccess) e = hipHostMalloc((void **)&s.h_pack, n, hipHostMallocDefault);
+    if (e != hipSuccess) return hip_fail(e);
+    s.cap_pack = n;
+  }
+  if (nreq > s.cap_req) {
+    const size_t n = std::max<size_t>({nreq, s.cap_req * 2, 64});
+    if (s.d_req_state) (void)hipFree(s.d_req_state);
+    s.d_req_state = nullptr;
+    s.cap_req = 0;
+    hipError_t e = hipMalloc(&s.d_req_state, n * 16 * 8);
+    if (e != hipSuccess) return hip_fail(e);
+    s.cap_req = n;
+  }
   return SLRNG_OK;
 }
 
-// Make the slot's buffers hold `tiles` tiles, `lanes` lanes and `nreq`
-// request states (the slot is idle: its previous iteration has completed).
-static int slot_reserve(Slot &s, size_t tiles, size_t lanes, size_t runs, size_t nreq) {
-  int rc = grow_pair(&s.d_tiles, &s.h_tiles, tiles, s.cap_tiles);
-  if (!rc) rc = grow_pair(&s.d_lanes, &s.h_lanes, lanes, s.cap_lanes);
-  if (!rc) rc = grow_pair(&s.d_runs, &s.h_runs, runs, s.cap_runs);
-  if (!rc && nreq > s.cap_req) {
-    const size_t n = std::max<size_t>({nreq, s.cap_req * 2, 64});
-    size_t c1 = 0, c2 = 0, c3 = 0;
-    rc = grow_pair(&s.d_poly, &s.h_poly, n * 16, c1);
-    if (!rc) rc = grow_pair(&s.d_idx, &s.h_idx, n, c2);
-    if (!rc) rc = grow_pair(&s.d_slot, &s.h_slot, n, c3);
-    if (!rc) {
-      if (s.d_req_state) (void)hipFree(s.d_req_state);
-      s.d_req_state = nullptr;
-      hipError_t e = hipMalloc(&s.d_req_state, n * 16 * 8);
-      if (e != hipSuccess) rc = hip_fail(e);
-      else s.cap_req = n;
-    }
-  }
-  return rc;
-}
-
 static void free_slot(Slot &s) {
-  void *d[] = {s.d_tiles, s.d_lanes, s.d_runs, s.d_poly, s.d_idx, s.d_slot, s.d_req_state, s.d_counter};
-  for (void *p : d)
-    if (p) (void)hipFree(p);
-  void *h[] = {s.h_tiles, s.h_lanes, s.h_runs, s.h_poly, s.h_idx, s.h_slot};
-  for (void *p : h)
-    if (p) (void)hipHostFree(p);
+  if (s.d_pack) (void)hipFree(s.d_pack);
+  if (s.d_req_state) (void)hipFree(s.d_req_state);
+  if (s.h_pack) (void)hipHostFree(s.h_pack);
   if (s.ev0) (void)hipEventDestroy(s.ev0);
   if (s.evk) (void)hipEventDestroy(s.evk);
   if (s.ev1) (void)hipEventDestroy(s.ev1);
@@ -218,30 +215,31 @@ static int launch_iteration(slrng_server *sv, int si, const std::vector<PlanReq>
   int rc = build_plan(pr.data(), pr.size(), sv->bo, sv->device, (uint64_t)sv->blocks * kBlock, P,
                       /*fit=*/true, (uint64_t)sv->o.min_chunk);
   if (rc) return rc;
-  rc = slot_reserve(s, P.tiles.size(), P.lanes.size(), P.runs.size(), P.rs.seeds.size());
+  const size_t nreq = P.rs.seeds.size();
+  const PackLayout L(P.tiles.size(), P.lanes.size(), P.runs.size(), nreq);
+  rc = slot_reserve(s, L.total, nreq);
   if (rc) return rc;
-  if (!P.tiles.empty()) memcpy(s.h_tiles, P.tiles.data(), P.tiles.size() * sizeof(TileDesc));
-  if (!P.lanes.empty()) memcpy(s.h_lanes, P.lanes.data(), P.lanes.size() * sizeof(LaneDesc));
-  if (!P.runs.empty()) memcpy(s.h_runs, P.runs.data(), P.runs.size() * sizeof(RunDesc));
-  if (!P.rs.polys.empty()) {
-    memcpy(s.h_poly, P.rs.polys.data(), P.rs.polys.size() * 8);
-    memcpy(s.h_idx, P.rs.origin_idx.data(), P.rs.origin_idx.size() * 4);
-    memcpy(s.h_slot, P.rs.slot.data(), P.rs.slot.size() * 4);
+  uint8_t *h = s.h_pack;
+  memset(h + L.counter, 0, 256);  // the claim counter starts at zero
+  if (!P.tiles.empty()) memcpy(h + L.tiles, P.tiles.data(), P.tiles.size() * sizeof(TileDesc));
+  if (!P.lanes.empty()) memcpy(h + L.lanes, P.lanes.data(), P.lanes.size() * sizeof(LaneDesc));
+  if (!P.runs.empty()) memcpy(h + L.runs, P.runs.data(), P.runs.size() * sizeof(RunDesc));
+  if (nreq) {
+    memcpy(h + L.poly, P.rs.polys.data(), P.rs.polys.size() * 8);
+    memcpy(h + L.idx, P.rs.origin_idx.data(), P.rs.origin_idx.size() * 4);
+    memcpy(h + L.slot, P.rs.slot.data(), P.rs.slot.size() * 4);
   }
+  uint8_t *d = s.d_pack;
+  const TileDesc *d_tiles = reinterpret_cast<const TileDesc *>(d + L.tiles);
+  const LaneDesc *d_lanes = reinterpret_cast<const LaneDesc *>(d + L.lanes);
+  const RunDesc *d_runs = reinterpret_cast<const RunDesc *>(d + L.runs);
+  const uint64_t *d_poly = reinterpret_cast<const uint64_t *>(d + L.poly);
+  const uint32_t *d_idx = reinterpret_cast<const uint32_t *>(d + L.idx);
+  const uint32_t *d_slot = reinterpret_cast<const uint32_t *>(d + L.slot);
+  unsigned *d_counter = reinterpret_cast<unsigned *>(d + L.counter);
   hipStream_t st = s.st;
   hipError_t e = hipEventRecord(s.ev0, st);
-  if (e == hipSuccess && !P.tiles.empty())
-    e = hipMemcpyAsync(s.d_tiles, s.h_tiles, P.tiles.size() * sizeof(TileDesc), hipMemcpyHostToDevice, st);
-  if (e == hipSuccess && !P.lanes.empty())
-    e = hipMemcpyAsync(s.d_lanes, s.h_lanes, P.lanes.size() * sizeof(LaneDesc), hipMemcpyHostToDevice, st);
-  if (e == hipSuccess && !P.runs.empty())
-    e = hipMemcpyAsync(s.d_runs, s.h_runs, P.runs.size() * sizeof(RunDesc), hipMemcpyHostToDevice, st);
-  if (e == hipSuccess && !P.rs.polys.empty())
-    e = hipMemcpyAsync(s.d_poly, s.h_poly, P.rs.polys.size() * 8, hipMemcpyHostToDevice, st);
-  if (e == hipSuccess && !P.rs.origin_idx.empty())
-    e = hipMemcpyAsync(s.d_idx, s.h_idx, P.rs.origin_idx.size() * 4, hipMemcpyHostToDevice, st);
-  if (e == hipSuccess && !P.rs.slot.empty())
-    e = hipMemcpyAsync(s.d_slot, s.h_slot, P.rs.slot.size() * 4, hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = hipMemcpyAsync(d, h, L.total, hipMemcpyHostToDevice, st);
   if (e != hipSuccess) return hip_fail(e);
   uint32_t off = 0;
   for (auto &run : P.rs.runs) {
@@ -249,9 +247,9 @@ static int launch_iteration(slrng_server *sv, int si, const std::vector<PlanReq>
     ra.seeds = nullptr;
     ra.origin_state = streams_state_ptr(sv->streams);
     ra.origin_stride = sv->o.n_streams;
-    ra.origin_idx = s.d_idx + off;
-    ra.polys = s.d_poly + (size_t)off * 16;
-    ra.slot = s.d_slot + off;
+    ra.origin_idx = d_idx + off;
+    ra.polys = d_poly + (size_t)off * 16;
+    ra.slot = d_slot + off;
     ra.req_state = s.d_req_state;
     ra.m = run.second;
     e = launch_req_state(run.first, ra, st);
@@ -261,18 +259,17 @@ static int launch_iteration(slrng_server *sv, int si, const std::vector<PlanReq>
   if (!P.tiles.empty()) {
     BatchArgs a;
     memset(&a, 0, sizeof(a));
-    a.tiles = s.d_tiles;
+    a.tiles = d_tiles;
     a.ntiles = (uint32_t)P.tiles.size();
-    a.lanes = s.d_lanes;
-    a.runs = s.d_runs;
+    a.lanes = d_lanes;
+    a.runs = d_runs;
     a.req_state = s.d_req_state;
     for (int v = 0; v < kNumVariants; v++) {
       a.tab[v] = P.tab[v];
       a.tab_n[v] = P.tab_n[v];
     }
-    a.counter = s.d_counter;
-    e = launch_batch_reset(s.d_counter, st);
-    if (e == hipSuccess) e = hipEventRecord(s.evk, st);
+    a.counter = d_counter;  // zeroed by the upload
+    e = hipEventRecord(s.evk, st);
     if (e != hipSuccess) return hip_fail(e);
     const unsigned blocks = std::min<unsigned>(sv->blocks, ((unsigned)P.tiles.size() + 3) / 4);
     e = launch_batch(a, sv->bo.tile, blocks, st);
@@ -419,7 +416,7 @@ extern "C" int slrng_server_default_opts(slrng_server_opts *o) {
   o->tile = 32;
   o->waves_per_cu = 8;
   o->chunk = 0;
-  o->window_us = 250;
+  o->window_us = 0;
   o->window_bytes = 256ull << 20;
   return SLRNG_OK;
 }
@@ -455,7 +452,7 @@ extern "C" int slrng_server_create(const slrng_server_opts *opts, slrng_server *
   slrng_server_opts o;
   if (opts) o = *opts;
   else slrng_server_default_opts(&o);
-  if (!valid_variant(o.variant) || o.n_streams == 0 || o.budget_bytes < kAlign) return SLRNG_EINVAL;
+  if (!valid_variant64(o.variant) || o.n_streams == 0 || o.budget_bytes < kAlign) return SLRNG_EINVAL;
   if (o.max_batch <= 0) o.max_batch = 4096;
   if (o.inflight <= 0) o.inflight = 3;
   if (o.inflight > 8 || o.min_chunk < 0 || o.window_us < 0) return SLRNG_EINVAL;
@@ -496,7 +493,6 @@ extern "C" int slrng_server_create(const slrng_server_opts *opts, slrng_server *
       if (e == hipSuccess) e = hipEventCreate(&s.ev0);
       if (e == hipSuccess) e = hipEventCreate(&s.evk);
       if (e == hipSuccess) e = hipEventCreate(&s.ev1);
-      if (e == hipSuccess) e = hipMalloc(&s.d_counter, sizeof(unsigned));
       if (e != hipSuccess) {
         rc = hip_fail(e);
         break;

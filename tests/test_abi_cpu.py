@@ -54,9 +54,9 @@ def test_version_and_errors(P):
         assert P.slrng_strerror(code).startswith("SLRNG")
     assert "unknown" in P.slrng_strerror(-99)
     with pytest.raises(P.SlrngError):
-        P.slrng_state_words(14)
-    assert [P.slrng_state_words(v) for v in range(14)] == \
-        [2, 2, 2, 4, 4, 4, 8, 8, 8, 16, 16, 16, 2, 16]
+        P.slrng_state_words(19)
+    assert [P.slrng_state_words(v) for v in range(19)] == \
+        [2, 2, 2, 4, 4, 4, 8, 8, 8, 16, 16, 16, 2, 16, 2, 2, 4, 4, 4]
 
 
 @pytest.mark.parametrize("name", list(O.GEN64))
@@ -165,3 +165,41 @@ def test_serve_trace_shape():
     assert tr["stream"].max() < 4096
     mean_bytes = float((tr["n"] * 8).mean())
     assert 8e6 < mean_bytes < 3e7  # log-uniform 64 B .. 256 MiB: mean about 17.6 MB
+
+
+# ---------------------------------------------------------------- 32-bit generators
+
+@pytest.mark.parametrize("name", list(O.GEN32))
+def test_charpoly_and_jump_poly_32_match_oracle(P, name):
+    g = O.GEN32[name]
+    p = O.charpoly(g)
+    assert P.slrng_charpoly(name) == p
+    assert P.slrng_state_words(name) == g.k
+    rnd = random.Random(name)
+    for J in (0, 1, 63, g.n, 1 << (g.n // 2), 1 << (3 * g.n // 4), (1 << 128) - 1,
+              rnd.getrandbits(100)):
+        assert P.slrng_jump_poly(name, J) == O.xpow_mod(J, p), J
+
+
+def test_32bit_argument_errors_before_any_device_call(P):
+    # a 32-bit state word must fit in 32 bits; all-zero states are rejected
+    st = np.ones((3, 4), dtype=np.uint64)
+    st[1, 2] = 1 << 32
+    with pytest.raises(P.SlrngError) as e:
+        P.slrng_streams_create_from_states("xoshiro128**", st.reshape(-1), stream=0)
+    assert e.value.name == "EINVAL"
+    st = np.ones((2, 2), dtype=np.uint64)
+    st[1] = 0
+    with pytest.raises(P.SlrngError) as e:
+        P.slrng_streams_create_from_states("xoroshiro64*", st.reshape(-1), stream=0)
+    assert e.value.name == "EZEROSTATE"
+    # 32-bit kinds and a 64-output tile for the 32-bit generators only
+    t = P.slrng_get_tuning("xoshiro128+", P.SLRNG_U32)
+    assert t["tile"] == 64
+    for bad in ((P.SLRNG_U64, 64), (P.SLRNG_U32, 32)):
+        with pytest.raises(P.SlrngError):
+            P.slrng_set_tuning("xoshiro128+", bad[0], bad[1], 1024, 1024)
+    with pytest.raises(P.SlrngError):
+        P.slrng_get_tuning("xoshiro256+", P.SLRNG_U32)
+    P.slrng_set_tuning("xoshiro128+", P.SLRNG_U32, t["tile"], t["target_waves"], t["min_chunk"],
+                       t["skew"])
