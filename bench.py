@@ -271,6 +271,7 @@ def serving_section(P, seconds: float) -> dict:
             st = P.slrng_server_get_stats(sv)
         finally:
             P.slrng_server_destroy(sv)
+        log(f"bench: serving replay ({label}) done in {wall:.1f} s")
         kgbs = 8 * st["outputs"] / max(st["kernel_s"], 1e-12) / 1e9
         out[label] = {"latency_p50_us": round(st["p50_us"], 1), "latency_p99_us": round(st["p99_us"], 1),
                       "latency_max_us": round(st["max_us"], 1), "outputs_per_s": st["outputs"] / wall,

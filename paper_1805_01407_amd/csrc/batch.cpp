@@ -92,7 +92,39 @@ int batch_grid_blocks(const slrng_batch_opts &o, int device, unsigned *blocks) {
   hipError_t e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device);
   if (e != hipSuccess) return hip_fail(e);
   const int wpc = o.waves_per_cu ? o.waves_per_cu : 12;
-  *blocks = (unsigned)std::max(1, cus * wpc / (kBlock / kWave));
+  // a persistent grid larger than what is resident at once only adds blocks
+  // that start after the tiles are gone
+  int per_cu = 0;
+  e = batch_resident_blocks_per_cu(o.tile, &per_cu);
+  if (e != hipSuccess) return hip_fail(e);
+  const int want = cus * wpc / (kBlock / kWave);
+  const int cap = per_cu > 0 ? cus * per_cu : want;
+  *blocks = (unsigned)std::max(1, std::min(want, cap));
+  return SLRNG_OK;
+}
+
+constexpr uint64_t kFitTilesPerWave = 4;
+
+static uint64_t option_chunk(const slrng_batch_opts &o, int v) {
+  uint64_t c = o.chunk[v] ? o.chunk[v] : 16384;
+  if (c > 0xffffffffull) c = 0xffffffffull & ~(uint64_t)63;
+  return c;
+}
+
+// Smallest fitted chunk: the option, else the larger of 512 and 2n.
+static uint64_t fit_floor_for(int v, uint64_t fit_floor) {
+  return fit_floor ? fit_floor : std::max<uint64_t>(512, 2 * 64 * (uint64_t)variant_words(v));
+}
+
+int warm_fit_tables(int device, int variant, const slrng_batch_opts &o, uint64_t fit_floor) {
+  const uint64_t c = option_chunk(o, variant);
+  for (uint64_t want = fit_floor_for(variant, fit_floor);; want *= 2) {
+    const uint64_t cc = (std::min(c, want) + o.tile - 1) / o.tile * o.tile;
+    ChunkTable t;
+    int rc = chunk_table(device, variant_engine(variant), cc, kMaxTable, &t);
+    if (rc) return rc;
+    if (want >= c) break;
+  }
   return SLRNG_OK;
 }
 
@@ -107,13 +139,12 @@ int build_plan(const PlanReq *reqs, size_t n_reqs, const slrng_batch_opts &o, in
   uint64_t total[kNumVariants] = {0};
   for (size_t r = 0; r < n_reqs; r++) total[reqs[r].variant] += reqs[r].n;
   for (int v = 0; v < kNumVariants; v++) {
-    uint64_t c = o.chunk[v] ? o.chunk[v] : 16384;
-    if (c > 0xffffffffull) c = 0xffffffffull & ~(uint64_t)63;
+    uint64_t c = option_chunk(o, v);
     if (fit) {
-      const uint64_t floor_c =
-          fit_floor ? fit_floor : std::max<uint64_t>(512, 2 * 64 * (uint64_t)variant_words(v));
-      uint64_t want = floor_c;
-      while (want < c && want * grid_lanes < total[v]) want *= 2;
+      uint64_t want = fit_floor_for(v, fit_floor);
+      // about kFitTilesPerWave tiles per resident wave, so that waves that
+      // finish early take more work instead of idling until the slowest ends
+      while (want < c && want * grid_lanes * kFitTilesPerWave < total[v]) want *= 2;
       c = std::min(c, want);
     }
     c = (c + o.tile - 1) / o.tile * o.tile;

@@ -202,6 +202,12 @@ hipError_t launch_batch(const BatchArgs &a, int tile, unsigned blocks, hipStream
   return hipGetLastError();
 }
 
+hipError_t batch_resident_blocks_per_cu(int tile, int *blocks) {
+  return tile == 16
+             ? hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, k_batch<16>, kBlock, 0)
+             : hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, k_batch<32>, kBlock, 0);
+}
+
 hipError_t launch_batch_reset(unsigned *counter, hipStream_t st) {
   hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(64), 0, st, counter);
   return hipGetLastError();

@@ -5,10 +5,13 @@
 // the SplitMix64-seeded origin state of `seed`.  The planner cuts every
 // request into lane-chunks of at most C_v outputs (C_v per variant); chunk j
 // starts from the request's start state jumped by j*C_v steps (one per-lane
-// jump with the table entry x^(j C_v) mod p).  Lane-chunks of the same variant
-// and kind are sorted by length and packed 64 to a tile; one wave processes a
-// tile.  A persistent kernel claims tiles through an atomic counter, heaviest
-// tiles first, and switches on the (wave-uniform) variant and kind.
+// jump with the table entry x^(j C_v) mod p).  Every 64 consecutive chunks of
+// a request form a run tile, described by one RunDesc (each lane derives its
+// chunk); the remaining chunks of all requests are grouped by variant and
+// kind, sorted by length and packed 64 to a list tile of LaneDescs.  One wave
+// processes a tile.  A persistent kernel claims tiles through an atomic
+// counter, heaviest tiles first, and switches on the (wave-uniform) variant
+// and kind.
 #pragma once
 #include <hip/hip_runtime_api.h>
 #include <stdint.h>
@@ -80,6 +83,9 @@ struct ReqArgs {
 };
 
 hipError_t launch_batch(const BatchArgs &a, int tile, unsigned blocks, hipStream_t st);
+// Workgroups of the persistent kernel that fit on one CU at once (LDS and
+// registers decide).
+hipError_t batch_resident_blocks_per_cu(int tile, int *blocks);
 hipError_t launch_batch_reset(unsigned *counter, hipStream_t st);
 hipError_t launch_req_state(int variant, const ReqArgs &a, hipStream_t st);
 

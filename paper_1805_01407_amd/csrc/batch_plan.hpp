@@ -55,12 +55,17 @@ struct PlanHost {
 
 // Builds the plan.  `grid_lanes` is the persistent grid size in lanes (used to
 // size the plain form's chunks, and with `fit` those of the whole batch: the
-// chunk length shrinks until the batch's lane-chunks cover the grid, down to
-// `fit_floor` outputs, by default the larger of 512 and 2n so that the
-// per-lane jump of n steps stays amortised); `from_state` requests always get
-// a request state.  Returns SLRNG_OK or an error code.
+// chunk length shrinks until the batch's lane-chunks cover the grid about
+// four times over, down to `fit_floor` outputs, by default the larger of 512
+// and 2n so that the per-lane jump of n steps stays amortised); `from_state`
+// requests always get a request state.  Returns SLRNG_OK or an error code.
 int build_plan(const PlanReq *reqs, size_t n, const slrng_batch_opts &o, int device,
                uint64_t grid_lanes, PlanHost &out, bool fit = false, uint64_t fit_floor = 0);
+
+// Builds ahead of time the chunk tables (x^(jC) mod p, all entries) of every
+// chunk length that fitting can choose for `variant`, so that no iteration
+// pays for building one.
+int warm_fit_tables(int device, int variant, const slrng_batch_opts &o, uint64_t fit_floor);
 
 // The persistent grid (blocks of 4 waves) for the options on `device`.
 int batch_grid_blocks(const slrng_batch_opts &o, int device, unsigned *blocks);

@@ -169,8 +169,8 @@ __device__ __forceinline__ void out_store(VT *p, VT v) {
 
 // Store with the device-scope cache policy (sc1): the line is written through
 // the XCD's L2 instead of staying dirty there.  For the batched kernel, whose
-// rows are consecutive chunks of one request, this measured ~14% faster than
-// plain stores; for the stream-major generation kernel ~2% slower.
+// rows are consecutive chunks of one request, this measured about 10% faster
+// than plain stores; for the stream-major generation kernel about 2% slower.
 //  * The compiler cannot see that the asm is a store, so it does not insert the
 //    wait states that a VALU write of a store's data registers needs right
 //    after a store of more than 8 bytes (two on this family); the asm carries
@@ -185,11 +185,6 @@ __device__ __forceinline__ void out_store_wt(VT *p, VT v) {
     asm volatile("global_store_dwordx4 %0, %1, off sc1\n\ts_nop 1" ::"v"(p), "v"(v));
   else
     asm volatile("global_store_dwordx2 %0, %1, off sc1\n\ts_nop 1" ::"v"(p), "v"(v));
-}
-
-template <typename VT>
-__device__ __forceinline__ void nt_store(VT *p, VT v) {
-  __builtin_nontemporal_store(v, p);
 }
 
 // Store a staged tile: rows 0..rows_live of the wave, m outputs each, to

@@ -475,6 +475,9 @@ extern "C" int slrng_server_create(const slrng_server_opts *opts, slrng_server *
     return hip_fail(e);
   }
   rc = batch_grid_blocks(bo, sv->device, &sv->blocks);
+  // every chunk table an iteration can pick, built now rather than in the
+  // middle of serving (one table of 65,536 polynomials takes milliseconds)
+  if (!rc) rc = warm_fit_tables(sv->device, o.variant, bo, (uint64_t)o.min_chunk);
   if (!rc) rc = slrng_streams_create(o.variant, o.seed, o.n_streams, nullptr, &sv->streams);
   if (!rc) {
     e = hipDeviceSynchronize();
