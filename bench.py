@@ -9,7 +9,13 @@ Step k uses seed (k mod 8) + 1, so 8 steps cover seeds 1..8.  Inputs are the
 seeds alone; all outputs stay in HBM.
 
 Prints one JSON line (rank 0).  `value` = outputs (uint64 + double) per
-second over the timed steps; `roofline` describes the generation kernel.
+second over the timed steps; `roofline` describes the generation kernel
+(HIP events around each launch; `traffic` from the committed HBM counters).
+The same line carries the other workloads, each run once after the sweep:
+jump-ahead at scale (2^20 streams), the 32-bit generators, the on-device
+linearity check, the batched-requests workload (one graph launch against one
+launch per request), the serving trace (continuous batching against the
+plain form) and the CPU oracle on a bounded sample (`cpu_baseline`).
 """
 from __future__ import annotations
 
@@ -139,11 +145,11 @@ def positioning_section(P, torch, stream, reps: int = 5) -> dict:
     Positioning and the long jump are bound by integer VALU work, not by HBM:
     a uniform jump costs n = 256 engine steps (12 VALU instructions each for
     xoshiro256 on gfx950) plus, for each set coefficient of the polynomial
-    (about half), a 4-word xor (8 instructions).  The section also times the
-    per-stream advance of every stream by its own random 128-bit distance.  `alu_frac` compares that
+    (about half), a 4-word xor (8 instructions).  `alu_frac` compares that
     count with the chip's 32-bit VALU rate: 256 CUs x 128 lanes per clock x
     2.4 GHz = 78.6 T lane-operations/s (the rate behind the 157.3 TFLOP/s
-    fp32 vector peak, an FMA counting as two)."""
+    fp32 vector peak, an FMA counting as two).  The section also times the
+    advance of every stream by its own random 128-bit distance."""
     name, seed, S, N = "xoshiro256++", 42, 1 << 20, 1024
     buf = torch.empty((S, N), dtype=torch.int64, device="cuda")
     ev = lambda: torch.cuda.Event(enable_timing=True)  # noqa: E731
@@ -257,12 +263,18 @@ def serving_section(P, seconds: float) -> dict:
     """The serving workload: Poisson arrivals at 20,000 requests/s on 4,096
     device-resident xoshiro256** streams (seed 42), sizes log-uniform in
     64 B .. 256 MiB, admission under a 16 GB output budget; continuous batching
-    against the plain form (one launch per request), on the same trace."""
+    (default options: an iteration starts as soon as a slot is free) against
+    the plain form (one launch per request), on the same trace, plus one
+    throughput-leaning operating point of continuous batching (iterations
+    gather up to 4 ms or 1 GiB of requests) that shows what the generation
+    kernels reach when iterations are large."""
     from paper_1805_01407_amd import workloads as W
     tr = W.serve_trace(seconds=seconds)
     out = {"seconds": seconds, "requests": int(tr["t"].size), "outputs": int(tr["n"].sum()),
            "offered_GBs": round(8 * float(tr["n"].sum()) / seconds / 1e9, 1)}
-    for label, kw in (("continuous_batching", {}), ("plain_per_request", {"max_batch": 1})):
+    for label, kw in (("continuous_batching", {}), ("plain_per_request", {"max_batch": 1}),
+                      ("continuous_batching_window_4ms", {"window_us": 4000,
+                                                          "window_bytes": 1 << 30})):
         sv = P.slrng_server_create(P.slrng_server_default_opts(**kw))
         try:
             t0 = time.perf_counter()

@@ -149,7 +149,13 @@ int build_plan(const PlanReq *reqs, size_t n_reqs, const slrng_batch_opts &o, in
     }
     c = (c + o.tile - 1) / o.tile * o.tile;
     const uint64_t need = (maxn[v] + kMaxTable - 1) / kMaxTable;
-    if (c < need) c = (need + o.tile - 1) / o.tile * o.tile;
+    if (c < need) {
+      // a power of two, so that the chunk lengths stay within the set whose
+      // tables warm_fit_tables builds ahead of time
+      uint64_t p2 = c;
+      while (p2 < need) p2 *= 2;
+      c = (p2 + o.tile - 1) / o.tile * o.tile;
+    }
     if (c > 0xffffffffull) return SLRNG_ERANGE;
     C[v] = c;
   }

@@ -196,6 +196,71 @@ __global__ __launch_bounds__(kBlock) void k_req_state(ReqArgs a) {
   }
 }
 
+// Basis states of resident streams: B_j[i] = s_j * M^i for i < n, stream-major
+// (word w of B_j[i] at basis[(j * n + i) * K + w]), in logical word order.
+template <int V>
+__global__ __launch_bounds__(kBlock) void k_basis(const u64 *__restrict__ state, u64 S,
+                                                  u64 *__restrict__ basis) {
+  constexpr int K = Params<V>::k;
+  constexpr int N = 64 * K;
+  constexpr int BLK = block_steps<V>();
+  const u64 j = (u64)blockIdx.x * kBlock + threadIdx.x;
+  if (j >= S) return;
+  u64 s[K];
+#pragma unroll
+  for (int w = 0; w < K; w++) s[w] = state[(u64)w * S + j];
+  u64 *out = basis + j * N * K;
+  for (int i0 = 0; i0 < N; i0 += BLK) {
+    static_for<BLK>([&](auto P) {
+      u64 *rec = out + (u64)(i0 + P) * K;
+#pragma unroll
+      for (int w = 0; w < K; w++) rec[w] = s[K == 16 ? ((P + w) & 15) : w];
+      step<V, P>(s);
+    });
+  }
+}
+
+// Request start states from the basis: s_j * M^pos = sum_i r_i B_j[i] with
+// r = x^pos mod p (Cayley-Hamilton).  One wave per request: lane l xors the
+// basis states of the set coefficients l, l + 64, ... (consecutive lanes read
+// consecutive records), then an xor reduction across the wave.
+template <int V>
+__global__ __launch_bounds__(kBlock) void k_req_state_basis(ReqArgs a, const u64 *__restrict__ basis) {
+  constexpr int K = Params<V>::k;
+  constexpr int N = 64 * K;
+  const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+  const unsigned r = blockIdx.x * (kBlock / kWave) + wave;
+  if (r >= a.m) return;  // uniform per wave
+  const u64 *rec = basis + (u64)a.origin_idx[r] * N * K;
+  const u64 *poly = a.polys + (u64)r * 16;
+  unsigned lo[K], hi[K];
+#pragma unroll
+  for (int w = 0; w < K; w++) lo[w] = hi[w] = 0;
+  for (int wi = 0; wi < K; wi++) {  // n / 64 = K words of the polynomial
+    if ((poly[wi] >> lane) & 1) {
+      const u64 *b = rec + (u64)(64 * wi + lane) * K;
+#pragma unroll
+      for (int w = 0; w < K; w++) {
+        const u64 v = b[w];
+        lo[w] ^= (unsigned)v;
+        hi[w] ^= (unsigned)(v >> 32);
+      }
+    }
+  }
+#pragma unroll
+  for (int off = kWave / 2; off > 0; off >>= 1) {
+#pragma unroll
+    for (int w = 0; w < K; w++) {
+      lo[w] ^= (unsigned)__shfl_xor((int)lo[w], off);
+      hi[w] ^= (unsigned)__shfl_xor((int)hi[w], off);
+    }
+  }
+  if (lane == 0) {
+#pragma unroll
+    for (int w = 0; w < K; w++) a.req_state[(u64)a.slot[r] * 16 + w] = ((u64)hi[w] << 32) | lo[w];
+  }
+}
+
 hipError_t launch_batch(const BatchArgs &a, int tile, unsigned blocks, hipStream_t st) {
   if (tile == 16) hipLaunchKernelGGL(k_batch<16>, dim3(blocks), dim3(kBlock), 0, st, a);
   else hipLaunchKernelGGL(k_batch<32>, dim3(blocks), dim3(kBlock), 0, st, a);
@@ -218,6 +283,53 @@ static hipError_t req_v(const ReqArgs &a, hipStream_t st) {
   dim3 grid((a.m + kBlock - 1) / kBlock);
   hipLaunchKernelGGL((k_req_state<V>), grid, dim3(kBlock), 0, st, a);
   return hipGetLastError();
+}
+
+template <int V>
+static hipError_t basis_v(const u64 *state, u64 S, u64 *basis, hipStream_t st) {
+  dim3 grid((unsigned)((S + kBlock - 1) / kBlock));
+  hipLaunchKernelGGL((k_basis<V>), grid, dim3(kBlock), 0, st, state, S, basis);
+  return hipGetLastError();
+}
+
+template <int V>
+static hipError_t req_basis_v(const ReqArgs &a, const u64 *basis, hipStream_t st) {
+  dim3 grid((a.m + (kBlock / kWave) - 1) / (kBlock / kWave));
+  hipLaunchKernelGGL((k_req_state_basis<V>), grid, dim3(kBlock), 0, st, a, basis);
+  return hipGetLastError();
+}
+
+#define SL_DISPATCH64(v, EXPR)           \
+  switch (v) {                           \
+    case 0: return EXPR(0);              \
+    case 1: return EXPR(1);              \
+    case 2: return EXPR(2);              \
+    case 3: return EXPR(3);              \
+    case 4: return EXPR(4);              \
+    case 5: return EXPR(5);              \
+    case 6: return EXPR(6);              \
+    case 7: return EXPR(7);              \
+    case 8: return EXPR(8);              \
+    case 9: return EXPR(9);              \
+    case 10: return EXPR(10);            \
+    case 11: return EXPR(11);            \
+    case 12: return EXPR(12);            \
+    case 13: return EXPR(13);            \
+    default: return hipErrorInvalidValue; \
+  }
+
+hipError_t launch_basis(int variant, const uint64_t *state, uint64_t S, uint64_t *basis,
+                        hipStream_t st) {
+#define SL_B(V) basis_v<V>(state, S, basis, st)
+  SL_DISPATCH64(variant, SL_B)
+#undef SL_B
+}
+
+hipError_t launch_req_state_basis(int variant, const ReqArgs &a, const uint64_t *basis,
+                                  hipStream_t st) {
+#define SL_RB(V) req_basis_v<V>(a, basis, st)
+  SL_DISPATCH64(variant, SL_RB)
+#undef SL_RB
 }
 
 hipError_t launch_req_state(int variant, const ReqArgs &a, hipStream_t st) {

@@ -89,4 +89,13 @@ hipError_t batch_resident_blocks_per_cu(int tile, int *blocks);
 hipError_t launch_batch_reset(unsigned *counter, hipStream_t st);
 hipError_t launch_req_state(int variant, const ReqArgs &a, hipStream_t st);
 
+// Basis states of S resident streams (word-major states): B_j[i] = s_j M^i,
+// i < n, at basis[(j n + i) k + w] (n k words per stream).
+hipError_t launch_basis(int variant, const uint64_t *state, uint64_t S, uint64_t *basis,
+                        hipStream_t st);
+// Request states of resident-origin requests from their streams' bases (one
+// wave per request; uses origin_idx, polys, slot, req_state and m).
+hipError_t launch_req_state_basis(int variant, const ReqArgs &a, const uint64_t *basis,
+                                  hipStream_t st);
+
 }  // namespace slrng

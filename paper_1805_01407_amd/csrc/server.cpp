@@ -49,6 +49,7 @@ double secs(Clock::time_point a, Clock::time_point b) {
 }
 
 constexpr uint64_t kAlign = 256;  // arena allocation granularity (bytes)
+constexpr uint64_t kMaxBasisBytes = 1ull << 30;  // largest basis kept resident
 
 // First-fit allocator over [0, size) with coalescing.
 struct Arena {
@@ -146,6 +147,7 @@ struct slrng_server {
   unsigned blocks = 0;
   slrng_streams *streams = nullptr;
   uint8_t *arena_dev = nullptr;
+  uint64_t *basis = nullptr;  // resident streams' basis states, or null
   Arena arena;
   std::vector<uint64_t> head;
 
@@ -252,7 +254,8 @@ static int launch_iteration(slrng_server *sv, int si, const std::vector<PlanReq>
     ra.slot = d_slot + off;
     ra.req_state = s.d_req_state;
     ra.m = run.second;
-    e = launch_req_state(run.first, ra, st);
+    e = sv->basis ? launch_req_state_basis(run.first, ra, sv->basis, st)
+                  : launch_req_state(run.first, ra, st);
     if (e != hipSuccess) return hip_fail(e);
     off += run.second;
   }
@@ -442,6 +445,7 @@ static void destroy_server(slrng_server *sv) {
   }
   if (sv->ref) (void)hipEventDestroy(sv->ref);
   if (sv->arena_dev) (void)hipFree(sv->arena_dev);
+  if (sv->basis) (void)hipFree(sv->basis);
   if (sv->streams) slrng_streams_destroy(sv->streams);
   delete sv;
 }
@@ -479,6 +483,20 @@ extern "C" int slrng_server_create(const slrng_server_opts *opts, slrng_server *
   // middle of serving (one table of 65,536 polynomials takes milliseconds)
   if (!rc) rc = warm_fit_tables(sv->device, o.variant, bo, (uint64_t)o.min_chunk);
   if (!rc) rc = slrng_streams_create(o.variant, o.seed, o.n_streams, nullptr, &sv->streams);
+  // The basis states s_j M^i (i < n) of every resident stream, when they fit
+  // in kMaxBasisBytes: a request's start state is then a sum of basis states
+  // selected by x^pos mod p, computed by a whole wave at once, instead of n
+  // serial steps of one lane.
+  if (!rc) {
+    const uint64_t k = (uint64_t)variant_words(o.variant);
+    const uint64_t bytes = (uint64_t)o.n_streams * 64 * k * k * 8;
+    if (bytes <= kMaxBasisBytes) {
+      e = hipMalloc(&sv->basis, bytes);
+      if (e == hipSuccess) e = launch_basis(o.variant, streams_state_ptr(sv->streams), o.n_streams,
+                                            sv->basis, nullptr);
+      if (e != hipSuccess) rc = e == hipErrorOutOfMemory ? SLRNG_ENOMEM : hip_fail(e);
+    }
+  }
   if (!rc) {
     e = hipDeviceSynchronize();
     if (e != hipSuccess) rc = hip_fail(e);

@@ -163,3 +163,33 @@ def test_replay_small_trace(P):
     assert st["completed"] == tr["t"].size and st["failed"] == 0
     assert st["outputs"] == int(tr["n"].sum())
     assert 0 < st["p50_us"] <= st["p99_us"] <= st["max_us"]
+
+
+@pytest.mark.parametrize("name", ["xoroshiro128+", "xoshiro512**", "xoroshiro1024++"])
+def test_served_requests_other_generators(P, name):
+    """Request start states come from the resident streams' basis states
+    (s M^i, i < n): two-word, eight-word and the cyclic sixteen-word engines,
+    positions from 0 to past several basis lengths."""
+    S = 8
+    g = O.GEN64[name]
+    chain = O.stream_chain(g, 3, S)
+    opts = P.slrng_server_default_opts(n_streams=S, budget_bytes=64 << 20, seed=3, variant=name)
+    sv = P.slrng_server_create(opts)
+    sizes = [1, 5, 64, 1000, 3, 40000, 777, 2]
+    try:
+        tickets = [(P.slrng_server_submit(sv, (k * 3) % S, n, k % 2), (k * 3) % S, n, k % 2)
+                   for k, n in enumerate(sizes * 3)]
+        got = []
+        for t, st, n, kind in tickets:
+            ptr, pos = P.slrng_server_wait(sv, t)
+            got.append((st, pos, n, kind, d2h(ptr, n)))
+            P.slrng_server_release(sv, t)
+    finally:
+        P.slrng_server_destroy(sv)
+    announce("served", name, len(got))
+    for st, pos, n, kind, out in got:
+        x = O.jump(g, chain[st], pos) if pos else chain[st]
+        e, _ = O.generate(g, x, n)
+        if kind == 1:
+            e = ((e >> np.uint64(11)).astype(np.float64) * 2.0**-53).view(np.uint64)
+        assert np.array_equal(out, e), (name, st, pos, n)
