@@ -223,7 +223,7 @@ def gen32_section(P, torch, stream, rounds: int = 2) -> dict:
                 P.slrng_generate(h.h, kind, N, buf.data_ptr(), N, stream)
                 e1.record(stream)
                 torch.cuda.synchronize()
-                if r:  # round 0 is a warm-up
+                if r:  # the first pass is a warm-up
                     per[name].append(e0.elapsed_time(e1))
     for h in hs.values():
         h.close()
@@ -313,7 +313,7 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py: this build measures one GPU only (the streams are independent and "
+        print("bench.py measures one GPU only (the streams are independent and "
               "would shard by stream range with no exchange); run with --gpus 1",
               file=sys.stderr)
         sys.exit(2)

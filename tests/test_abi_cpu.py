@@ -203,3 +203,13 @@ def test_32bit_argument_errors_before_any_device_call(P):
         P.slrng_get_tuning("xoshiro256+", P.SLRNG_U32)
     P.slrng_set_tuning("xoshiro128+", P.SLRNG_U32, t["tile"], t["target_waves"], t["min_chunk"],
                        t["skew"])
+
+
+def test_bench_refuses_more_than_one_gpu():
+    import subprocess
+    import sys
+    import os
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2 and "one GPU" in r.stderr
