@@ -50,6 +50,8 @@ double secs(Clock::time_point a, Clock::time_point b) {
 
 constexpr uint64_t kAlign = 256;  // arena allocation granularity (bytes)
 constexpr uint64_t kMaxBasisBytes = 1ull << 30;  // largest basis kept resident
+constexpr size_t kInitialPackBytes = 4u << 20;    // per-slot upload buffer at creation
+constexpr size_t kInitialReqs = 1024;             // per-slot request states at creation
 
 // First-fit allocator over [0, size) with coalescing.
 struct Arena {
@@ -330,6 +332,10 @@ static void worker_main(slrng_server *sv) {
     sv->slots[si].busy = true;
     lk.unlock();
     const int rc = launch_iteration(sv, si, pr);
+    // after a failed launch, let whatever was queued on the slot's stream
+    // (the upload reads the slot's pinned buffer) finish before the slot is
+    // handed out again
+    if (rc) (void)hipStreamSynchronize(sv->slots[si].st);
     lk.lock();
     if (rc) {
       // the launch failed: fail exactly these requests and free the slot
@@ -518,6 +524,10 @@ extern "C" int slrng_server_create(const slrng_server_opts *opts, slrng_server *
         rc = hip_fail(e);
         break;
       }
+      // buffers for typical iterations now: pinned allocations take
+      // milliseconds, which the first iterations would otherwise wait for
+      rc = slot_reserve(s, kInitialPackBytes, kInitialReqs);
+      if (rc) break;
     }
   }
   if (!rc) {
