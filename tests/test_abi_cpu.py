@@ -213,3 +213,29 @@ def test_bench_refuses_more_than_one_gpu():
     r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"],
                        capture_output=True, text=True, timeout=120)
     assert r.returncode == 2 and "one GPU" in r.stderr
+
+
+def test_plain_c_program_uses_the_abi(tmp_path):
+    """A C program compiled against include/slrng.h and linked with
+    libslrng.so (no Python in between) gets the same polynomials as the
+    oracle."""
+    import shutil
+    import subprocess
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    lib_dir = os.path.join(root, "paper_1805_01407_amd")
+    if not os.path.exists(os.path.join(lib_dir, "libslrng.so")) or not shutil.which("gcc"):
+        pytest.skip("library not built or no C compiler")
+    exe = str(tmp_path / "abi_host_calls")
+    subprocess.run(["gcc", "-std=c11", "-D__HIP_PLATFORM_AMD__", "-I", os.path.join(root, "include"),
+                    "-I", "/opt/rocm/include", os.path.join(root, "tests", "c", "abi_host_calls.c"),
+                    "-L", lib_dir, "-Wl,-rpath," + lib_dir, "-lslrng", "-o", exe], check=True)
+    out = subprocess.run([exe], capture_output=True, text=True, timeout=120)
+    assert out.returncode == 0, out.stderr
+    lines = dict(line.split(" ", 1) for line in out.stdout.strip().splitlines() if " " in line)
+    g = O.GEN64["xoshiro256**"]
+    p = O.charpoly(g)
+    words = lambda v, k: " ".join(f"{(v >> (64 * i)) & (2**64 - 1):016x}" for i in range(k))  # noqa: E731
+    assert lines["charpoly"] == words(p, 5)
+    assert lines["jump"] == words(O.xpow_mod(1 << 128, p), 4)
+    assert lines["longjump"] == words(O.xpow_mod(1 << 192, p), 4)
+    assert "ZEROSTATE" in out.stdout

@@ -193,3 +193,64 @@ def test_served_requests_other_generators(P, name):
         if kind == 1:
             e = ((e >> np.uint64(11)).astype(np.float64) * 2.0**-53).view(np.uint64)
         assert np.array_equal(out, e), (name, st, pos, n)
+
+
+def test_served_trace_values_at_workload_shape(P):
+    """The first 0.2 s of the serving trace (the bench's recipe: Poisson
+    arrivals at 20,000 requests/s, 4,096 resident xoshiro256** streams,
+    64 B .. 256 MiB) through the default server (16 GiB budget), submitted as
+    one burst so that admission blocks on the budget: every request of at
+    most 1 MiB compared in full with the oracle, larger ones on their first
+    and last 4,096 outputs, all at the positions the server assigned."""
+    import queue
+    from concurrent.futures import ThreadPoolExecutor
+    from paper_1805_01407_amd import workloads as W
+    tr = W.serve_trace(seconds=0.2)
+    g = O.GEN64[NAME]
+    opts = P.slrng_server_default_opts()
+    chain = O.stream_chain(g, opts.seed, opts.n_streams)
+    announce("trace values", tr["t"].size)
+    sv = P.slrng_server_create(opts)
+    results = []
+    work = queue.Queue()
+
+    def consumer():
+        while True:
+            item = work.get()
+            if item is None:
+                return
+            t, st, n = item
+            ptr, pos = P.slrng_server_wait(sv, t)
+            if n <= 131072:
+                results.append((st, pos, n, d2h(ptr, n), None))
+            else:
+                results.append((st, pos, n, d2h(ptr, 4096), d2h(ptr + 8 * (n - 4096), 4096)))
+            P.slrng_server_release(sv, t)
+
+    th = threading.Thread(target=consumer)
+    th.start()
+    try:
+        for i in range(tr["t"].size):
+            st, n = int(tr["stream"][i]), int(tr["n"][i])
+            work.put((P.slrng_server_submit(sv, st, n, 0), st, n))
+        work.put(None)
+        th.join()
+        stats = P.slrng_server_get_stats(sv)
+    finally:
+        P.slrng_server_destroy(sv)
+    assert len(results) == tr["t"].size and stats["failed"] == 0
+    assert stats["peak_reserved_bytes"] <= opts.budget_bytes
+    p = O.charpoly(g)
+
+    def check(res):
+        st, pos, n, head, tail = res
+        x = O.jump_poly(g, chain[st], O.xpow_mod(pos, p)) if pos else chain[st]
+        if tail is None:
+            return np.array_equal(head, O.generate(g, x, n)[0])
+        y = O.jump_poly(g, x, O.xpow_mod(n - 4096, p))
+        return (np.array_equal(head, O.generate(g, x, 4096)[0]) and
+                np.array_equal(tail, O.generate(g, y, 4096)[0]))
+
+    with ThreadPoolExecutor(16) as ex:
+        ok = list(ex.map(check, results))
+    assert all(ok), [results[i][:3] for i, v in enumerate(ok) if not v][:5]
