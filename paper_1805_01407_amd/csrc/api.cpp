@@ -233,8 +233,11 @@ int get_slot_polys(int device, int engine, uint64_t C, uint64_t D, const uint64_
 
 // ---------------------------------------------------------------- tuning
 
+// Launch shapes per (variant, kind), read by every generate call and written
+// by slrng_set_tuning, possibly from other threads: guarded by a mutex.
 static slrng_tuning g_tune[kEndVariant32][2];
 static std::once_flag g_tune_once;
+static std::mutex g_tune_mu;
 
 static void init_tuning() {
   for (int v = 0; v < kEndVariant32; v++)
@@ -244,6 +247,7 @@ static void init_tuning() {
 
 slrng_tuning tuning_for(int v, int kind) {
   std::call_once(g_tune_once, init_tuning);
+  std::lock_guard<std::mutex> g(g_tune_mu);
   return g_tune[v][kind_index(kind)];
 }
 
@@ -281,32 +285,38 @@ struct slrng_streams {
 };
 
 extern "C" int slrng_state_words(int variant) {
-  if (!valid_variant(variant)) return SLRNG_EINVAL;
-  return variant_words(variant);
+  return guarded([&]() -> int {
+    if (!valid_variant(variant)) return SLRNG_EINVAL;
+    return variant_words(variant);
+  });
 }
 
 extern "C" int slrng_charpoly(int variant, uint64_t *out, int out_words) {
-  if (!valid_variant(variant) || !out) return SLRNG_EINVAL;
-  const Field &f = engine_field(variant_engine(variant));
-  if (out_words < f.n / 64 + 1) return SLRNG_EINVAL;
-  for (int i = 0; i <= f.n / 64; i++) out[i] = f.p.w[i];
-  return SLRNG_OK;
+  return guarded([&]() -> int {
+    if (!valid_variant(variant) || !out) return SLRNG_EINVAL;
+    const Field &f = engine_field(variant_engine(variant));
+    if (out_words < f.n / 64 + 1) return SLRNG_EINVAL;
+    for (int i = 0; i <= f.n / 64; i++) out[i] = f.p.w[i];
+    return SLRNG_OK;
+  });
 }
 
 extern "C" int slrng_jump_poly(int variant, const uint64_t *J, int nj, uint64_t *out,
                                int out_words) {
-  if (!valid_variant(variant) || !out || nj < 0 || (nj > 0 && !J)) return SLRNG_EINVAL;
-  const Field &f = engine_field(variant_engine(variant));
-  if (out_words < f.n / 64) return SLRNG_EINVAL;
-  Poly r;
-  if (nj == 0) {
-    r.clear();
-    r.w[0] = 1;
-  } else {
-    f.xpow(J, nj, r);
-  }
-  for (int i = 0; i < f.n / 64; i++) out[i] = r.w[i];
-  return SLRNG_OK;
+  return guarded([&]() -> int {
+    if (!valid_variant(variant) || !out || nj < 0 || (nj > 0 && !J)) return SLRNG_EINVAL;
+    const Field &f = engine_field(variant_engine(variant));
+    if (out_words < f.n / 64) return SLRNG_EINVAL;
+    Poly r;
+    if (nj == 0) {
+      r.clear();
+      r.w[0] = 1;
+    } else {
+      f.xpow(J, nj, r);
+    }
+    for (int i = 0; i < f.n / 64; i++) out[i] = r.w[i];
+    return SLRNG_OK;
+  });
 }
 
 static int alloc_handle(int variant, uint64_t S, slrng_streams **out) {
@@ -339,11 +349,13 @@ static int alloc_handle(int variant, uint64_t S, slrng_streams **out) {
 }
 
 extern "C" int slrng_streams_destroy(slrng_streams *h) {
-  if (!h) return SLRNG_EINVAL;
-  for (int b = 0; b < 2; b++)
-    if (h->state[b]) (void)hipFree(h->state[b]);
-  delete h;
-  return SLRNG_OK;
+  return guarded([&]() -> int {
+    if (!h) return SLRNG_EINVAL;
+    for (int b = 0; b < 2; b++)
+      if (h->state[b]) (void)hipFree(h->state[b]);
+    delete h;
+    return SLRNG_OK;
+  });
 }
 
 static int position(slrng_streams *h, uint64_t seed, hipStream_t stream) {
@@ -366,23 +378,27 @@ static int position(slrng_streams *h, uint64_t seed, hipStream_t stream) {
 
 extern "C" int slrng_streams_create(int variant, uint64_t seed, uint64_t S, hipStream_t stream,
                                     slrng_streams **out) {
-  if (!out) return SLRNG_EINVAL;
-  *out = nullptr;
-  slrng_streams *h = nullptr;
-  int rc = alloc_handle(variant, S, &h);
-  if (rc) return rc;
-  rc = position(h, seed, stream);
-  if (rc) {
-    slrng_streams_destroy(h);
-    return rc;
-  }
-  *out = h;
-  return SLRNG_OK;
+  return guarded([&]() -> int {
+    if (!out) return SLRNG_EINVAL;
+    *out = nullptr;
+    slrng_streams *h = nullptr;
+    int rc = alloc_handle(variant, S, &h);
+    if (rc) return rc;
+    rc = position(h, seed, stream);
+    if (rc) {
+      slrng_streams_destroy(h);
+      return rc;
+    }
+    *out = h;
+    return SLRNG_OK;
+  });
 }
 
 extern "C" int slrng_streams_seed(slrng_streams *h, uint64_t seed, hipStream_t stream) {
-  if (!h) return SLRNG_EINVAL;
-  return position(h, seed, stream);
+  return guarded([&]() -> int {
+    if (!h) return SLRNG_EINVAL;
+    return position(h, seed, stream);
+  });
 }
 
 // 32-bit generators: every word must fit in 32 bits.
@@ -403,53 +419,61 @@ static bool any_zero_state(const uint64_t *w, uint64_t S, int k) {
 }
 
 extern "C" int slrng_set_state(slrng_streams *h, const uint64_t *host_words, hipStream_t stream) {
-  if (!h || !host_words) return SLRNG_EINVAL;
-  if (!words_fit(h->variant, host_words, h->S, h->k)) return SLRNG_EINVAL;
-  if (any_zero_state(host_words, h->S, h->k)) return SLRNG_EZEROSTATE;
-  std::vector<uint64_t> soa((size_t)h->S * h->k);
-  for (uint64_t i = 0; i < h->S; i++)
-    for (int j = 0; j < h->k; j++) soa[(size_t)j * h->S + i] = host_words[i * h->k + j];
-  HIPCHK(hipMemcpyAsync(h->state[h->cur], soa.data(), soa.size() * 8, hipMemcpyHostToDevice, stream));
-  HIPCHK(hipStreamSynchronize(stream));
-  return SLRNG_OK;
+  return guarded([&]() -> int {
+    if (!h || !host_words) return SLRNG_EINVAL;
+    if (!words_fit(h->variant, host_words, h->S, h->k)) return SLRNG_EINVAL;
+    if (any_zero_state(host_words, h->S, h->k)) return SLRNG_EZEROSTATE;
+    std::vector<uint64_t> soa((size_t)h->S * h->k);
+    for (uint64_t i = 0; i < h->S; i++)
+      for (int j = 0; j < h->k; j++) soa[(size_t)j * h->S + i] = host_words[i * h->k + j];
+    HIPCHK(hipMemcpyAsync(h->state[h->cur], soa.data(), soa.size() * 8, hipMemcpyHostToDevice, stream));
+    HIPCHK(hipStreamSynchronize(stream));
+    return SLRNG_OK;
+  });
 }
 
 extern "C" int slrng_get_state(const slrng_streams *h, uint64_t *host_words, hipStream_t stream) {
-  if (!h || !host_words) return SLRNG_EINVAL;
-  std::vector<uint64_t> soa((size_t)h->S * h->k);
-  HIPCHK(hipMemcpyAsync(soa.data(), h->state[h->cur], soa.size() * 8, hipMemcpyDeviceToHost, stream));
-  HIPCHK(hipStreamSynchronize(stream));
-  for (uint64_t i = 0; i < h->S; i++)
-    for (int j = 0; j < h->k; j++) host_words[i * h->k + j] = soa[(size_t)j * h->S + i];
-  return SLRNG_OK;
+  return guarded([&]() -> int {
+    if (!h || !host_words) return SLRNG_EINVAL;
+    std::vector<uint64_t> soa((size_t)h->S * h->k);
+    HIPCHK(hipMemcpyAsync(soa.data(), h->state[h->cur], soa.size() * 8, hipMemcpyDeviceToHost, stream));
+    HIPCHK(hipStreamSynchronize(stream));
+    for (uint64_t i = 0; i < h->S; i++)
+      for (int j = 0; j < h->k; j++) host_words[i * h->k + j] = soa[(size_t)j * h->S + i];
+    return SLRNG_OK;
+  });
 }
 
 extern "C" int slrng_streams_create_from_states(int variant, const uint64_t *host_words, uint64_t S,
                                                 hipStream_t stream, slrng_streams **out) {
-  if (!out || !host_words) return SLRNG_EINVAL;
-  *out = nullptr;
-  if (valid_variant(variant) && S > 0 && S <= (1ull << 31) &&
-      !words_fit(variant, host_words, S, variant_words(variant)))
-    return SLRNG_EINVAL;
-  if (valid_variant(variant) && S > 0 && S <= (1ull << 31) &&
-      any_zero_state(host_words, S, variant_words(variant)))
-    return SLRNG_EZEROSTATE;
-  slrng_streams *h = nullptr;
-  int rc = alloc_handle(variant, S, &h);
-  if (rc) return rc;
-  rc = slrng_set_state(h, host_words, stream);
-  if (rc) {
-    slrng_streams_destroy(h);
-    return rc;
-  }
-  *out = h;
-  return SLRNG_OK;
+  return guarded([&]() -> int {
+    if (!out || !host_words) return SLRNG_EINVAL;
+    *out = nullptr;
+    if (valid_variant(variant) && S > 0 && S <= (1ull << 31) &&
+        !words_fit(variant, host_words, S, variant_words(variant)))
+      return SLRNG_EINVAL;
+    if (valid_variant(variant) && S > 0 && S <= (1ull << 31) &&
+        any_zero_state(host_words, S, variant_words(variant)))
+      return SLRNG_EZEROSTATE;
+    slrng_streams *h = nullptr;
+    int rc = alloc_handle(variant, S, &h);
+    if (rc) return rc;
+    rc = slrng_set_state(h, host_words, stream);
+    if (rc) {
+      slrng_streams_destroy(h);
+      return rc;
+    }
+    *out = h;
+    return SLRNG_OK;
+  });
 }
 
 extern "C" int slrng_streams_count(const slrng_streams *h, uint64_t *n) {
-  if (!h || !n) return SLRNG_EINVAL;
-  *n = h->S;
-  return SLRNG_OK;
+  return guarded([&]() -> int {
+    if (!h || !n) return SLRNG_EINVAL;
+    *n = h->S;
+    return SLRNG_OK;
+  });
 }
 
 namespace slrng {
@@ -458,9 +482,11 @@ const uint64_t *streams_state_ptr(const slrng_streams *h) { return h->state[h->c
 }  // namespace slrng
 
 extern "C" int slrng_streams_variant(const slrng_streams *h, int *v) {
-  if (!h || !v) return SLRNG_EINVAL;
-  *v = h->variant;
-  return SLRNG_OK;
+  return guarded([&]() -> int {
+    if (!h || !v) return SLRNG_EINVAL;
+    *v = h->variant;
+    return SLRNG_OK;
+  });
 }
 
 static int apply_uniform(slrng_streams *h, const Poly &r, hipStream_t stream) {
@@ -472,117 +498,136 @@ static int apply_uniform(slrng_streams *h, const Poly &r, hipStream_t stream) {
 }
 
 extern "C" int slrng_streams_jump(slrng_streams *h, int jump_kind, hipStream_t stream) {
-  if (!h || (jump_kind != SLRNG_JUMP && jump_kind != SLRNG_LONG_JUMP)) return SLRNG_EINVAL;
-  return apply_uniform(h, jump_kind_poly(h->engine, jump_kind), stream);
+  return guarded([&]() -> int {
+    if (!h || (jump_kind != SLRNG_JUMP && jump_kind != SLRNG_LONG_JUMP)) return SLRNG_EINVAL;
+    return apply_uniform(h, jump_kind_poly(h->engine, jump_kind), stream);
+  });
 }
 
 extern "C" int slrng_streams_advance(slrng_streams *h, uint64_t hi, uint64_t lo, hipStream_t stream) {
-  if (!h) return SLRNG_EINVAL;
-  if (hi == 0 && lo == 0) return SLRNG_OK;
-  const Field &f = engine_field(h->engine);
-  uint64_t J[2] = {lo, hi};
-  Poly r;
-  f.xpow(J, 2, r);
-  return apply_uniform(h, r, stream);
+  return guarded([&]() -> int {
+    if (!h) return SLRNG_EINVAL;
+    if (hi == 0 && lo == 0) return SLRNG_OK;
+    const Field &f = engine_field(h->engine);
+    uint64_t J[2] = {lo, hi};
+    Poly r;
+    f.xpow(J, 2, r);
+    return apply_uniform(h, r, stream);
+  });
 }
 
 extern "C" int slrng_streams_advance_each(slrng_streams *h, const uint64_t *dev_steps,
                                           hipStream_t stream) {
-  if (!h || !dev_steps || ((uintptr_t)dev_steps & 7)) return SLRNG_EINVAL;
-  const uint64_t *tab = nullptr;
-  int rc = get_digit_tables(h->device, h->engine, &tab);
-  if (rc) return rc;
-  hipError_t e =
-      is_variant32(h->variant)
-          ? launch_advance_each32(h->variant, h->state[h->cur], h->S, dev_steps, tab, stream)
-          : launch_advance_each(h->variant, h->state[h->cur], h->S, dev_steps, tab, stream);
-  return e == hipSuccess ? SLRNG_OK : hip_fail(e);
+  return guarded([&]() -> int {
+    if (!h || !dev_steps || ((uintptr_t)dev_steps & 7)) return SLRNG_EINVAL;
+    const uint64_t *tab = nullptr;
+    int rc = get_digit_tables(h->device, h->engine, &tab);
+    if (rc) return rc;
+    hipError_t e =
+        is_variant32(h->variant)
+            ? launch_advance_each32(h->variant, h->state[h->cur], h->S, dev_steps, tab, stream)
+            : launch_advance_each(h->variant, h->state[h->cur], h->S, dev_steps, tab, stream);
+    return e == hipSuccess ? SLRNG_OK : hip_fail(e);
+  });
 }
 
 extern "C" int slrng_linear_complexity(const slrng_streams *h, int bit, uint32_t nbits,
                                        uint32_t *dev_lc, hipStream_t stream) {
-  if (!h || !dev_lc || ((uintptr_t)dev_lc & 3)) return SLRNG_EINVAL;
-  const int wbits = is_variant32(h->variant) ? 32 : 64;
-  if (bit < 0 || bit >= wbits) return SLRNG_EINVAL;
-  if (nbits < 32 || nbits > kLincompMaxBits || nbits % 32) return SLRNG_EINVAL;
-  hipError_t e = launch_lincomp(h->variant, h->state[h->cur], h->S, bit, nbits, dev_lc, stream);
-  return e == hipSuccess ? SLRNG_OK : hip_fail(e);
+  return guarded([&]() -> int {
+    if (!h || !dev_lc || ((uintptr_t)dev_lc & 3)) return SLRNG_EINVAL;
+    const int wbits = is_variant32(h->variant) ? 32 : 64;
+    if (bit < 0 || bit >= wbits) return SLRNG_EINVAL;
+    if (nbits < 32 || nbits > kLincompMaxBits || nbits % 32) return SLRNG_EINVAL;
+    hipError_t e = launch_lincomp(h->variant, h->state[h->cur], h->S, bit, nbits, dev_lc, stream);
+    return e == hipSuccess ? SLRNG_OK : hip_fail(e);
+  });
 }
 
 extern "C" int slrng_generate(slrng_streams *h, int kind, uint64_t n, void *dev_out, uint64_t ld,
                               hipStream_t stream) {
-  if (!h || !valid_kind(h->variant, kind)) return SLRNG_EINVAL;
-  if (n == 0) return SLRNG_OK;
-  const uint64_t elem = is_variant32(h->variant) ? 4 : 8;
-  if (!dev_out || ((uintptr_t)dev_out & (elem - 1))) return SLRNG_EINVAL;
-  if (ld < n) return SLRNG_EINVAL;
-  // extent (S-1) ld + n elements, in bytes, must fit in 64 bits
-  const uint64_t S1 = h->S - 1;
-  if (S1 && ld > (UINT64_MAX - n) / S1) return SLRNG_ERANGE;
-  const uint64_t extent = S1 * ld + n;
-  if (extent > UINT64_MAX / elem) return SLRNG_ERANGE;
-  const slrng_tuning t = tuning_for(h->variant, kind);
-  uint64_t C = 0, nslots = 1, D = 1;
-  plan_slots(h->S, n, t, C, nslots, D);
-  const uint64_t *sp = nullptr;
-  if (nslots > 1) {
-    int rc = get_slot_polys(h->device, h->engine, C, D, &sp);
-    if (rc) return rc;
-  }
-  GenArgs a;
-  a.state_in = h->state[h->cur];
-  // with several slots, other waves still read the start states while the
-  // last slot finishes: the final states go to the other buffer
-  a.state_out = nslots > 1 ? h->state[1 - h->cur] : h->state[h->cur];
-  a.S = h->S;
-  a.n = n;
-  a.C = C;
-  a.nslots = nslots;
-  a.D = D;
-  a.out = dev_out;
-  a.ld = ld;
-  a.slot_polys = sp;
-  GenConfig cfg{t.tile};
-  hipError_t e = is_variant32(h->variant) ? launch_generate32(h->variant, kind_index(kind), a, stream)
-                                          : launch_generate(h->variant, kind, a, cfg, stream);
-  if (e != hipSuccess) return hip_fail(e);
-  if (nslots > 1) h->cur = 1 - h->cur;
-  return SLRNG_OK;
+  return guarded([&]() -> int {
+    if (!h || !valid_kind(h->variant, kind)) return SLRNG_EINVAL;
+    if (n == 0) return SLRNG_OK;
+    const uint64_t elem = is_variant32(h->variant) ? 4 : 8;
+    if (!dev_out || ((uintptr_t)dev_out & (elem - 1))) return SLRNG_EINVAL;
+    if (ld < n) return SLRNG_EINVAL;
+    // extent (S-1) ld + n elements, in bytes, must fit in 64 bits
+    const uint64_t S1 = h->S - 1;
+    if (S1 && ld > (UINT64_MAX - n) / S1) return SLRNG_ERANGE;
+    const uint64_t extent = S1 * ld + n;
+    if (extent > UINT64_MAX / elem) return SLRNG_ERANGE;
+    const slrng_tuning t = tuning_for(h->variant, kind);
+    uint64_t C = 0, nslots = 1, D = 1;
+    plan_slots(h->S, n, t, C, nslots, D);
+    const uint64_t *sp = nullptr;
+    if (nslots > 1) {
+      int rc = get_slot_polys(h->device, h->engine, C, D, &sp);
+      if (rc) return rc;
+    }
+    GenArgs a;
+    a.state_in = h->state[h->cur];
+    // with several slots, other waves still read the start states while the
+    // last slot finishes: the final states go to the other buffer
+    a.state_out = nslots > 1 ? h->state[1 - h->cur] : h->state[h->cur];
+    a.S = h->S;
+    a.n = n;
+    a.C = C;
+    a.nslots = nslots;
+    a.D = D;
+    a.out = dev_out;
+    a.ld = ld;
+    a.slot_polys = sp;
+    GenConfig cfg{t.tile};
+    hipError_t e = is_variant32(h->variant) ? launch_generate32(h->variant, kind_index(kind), a, stream)
+                                            : launch_generate(h->variant, kind, a, cfg, stream);
+    if (e != hipSuccess) return hip_fail(e);
+    if (nslots > 1) h->cur = 1 - h->cur;
+    return SLRNG_OK;
+  });
 }
 
 // ---------------------------------------------------------------- tuning ABI
 
 extern "C" int slrng_get_tuning(int variant, int kind, slrng_tuning *out) {
-  if (!valid_variant(variant) || !valid_kind(variant, kind) || !out) return SLRNG_EINVAL;
-  *out = tuning_for(variant, kind);
-  return SLRNG_OK;
+  return guarded([&]() -> int {
+    if (!valid_variant(variant) || !valid_kind(variant, kind) || !out) return SLRNG_EINVAL;
+    *out = tuning_for(variant, kind);
+    return SLRNG_OK;
+  });
 }
 
 extern "C" int slrng_set_tuning(int variant, int kind, const slrng_tuning *t) {
-  if (!valid_variant(variant) || !valid_kind(variant, kind) || !t) return SLRNG_EINVAL;
-  // the 32-bit kernels stage tiles of 64 outputs; the 64-bit ones 16 or 32
-  const bool tile_ok = is_variant32(variant) ? t->tile == 64 : (t->tile == 16 || t->tile == 32);
-  if (!tile_ok || t->target_waves < 1 || t->target_waves > (1 << 20) ||
-      t->min_chunk < 1 || t->min_chunk > (1ull << 40) || t->reserved != 0)
-    return SLRNG_EINVAL;
-  if (t->skew != 1 && t->skew != 2 && t->skew != 4 && t->skew != 8 && t->skew != 16)
-    return SLRNG_EINVAL;
-  tuning_for(variant, kind);
-  g_tune[variant][kind_index(kind)] = *t;
-  return SLRNG_OK;
+  return guarded([&]() -> int {
+    if (!valid_variant(variant) || !valid_kind(variant, kind) || !t) return SLRNG_EINVAL;
+    // the 32-bit kernels stage tiles of 64 outputs; the 64-bit ones 16 or 32
+    const bool tile_ok = is_variant32(variant) ? t->tile == 64 : (t->tile == 16 || t->tile == 32);
+    if (!tile_ok || t->target_waves < 1 || t->target_waves > (1 << 20) ||
+        t->min_chunk < 1 || t->min_chunk > (1ull << 40) || t->reserved != 0)
+      return SLRNG_EINVAL;
+    if (t->skew != 1 && t->skew != 2 && t->skew != 4 && t->skew != 8 && t->skew != 16)
+      return SLRNG_EINVAL;
+    std::call_once(g_tune_once, init_tuning);
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    g_tune[variant][kind_index(kind)] = *t;
+    return SLRNG_OK;
+  });
 }
 
 // ---------------------------------------------------------------- calibration
 
 extern "C" int slrng_calib_write(void *dev_out, uint64_t bytes, hipStream_t stream) {
-  if (!dev_out || bytes % 16 || ((uintptr_t)dev_out & 15)) return SLRNG_EINVAL;
-  hipError_t e = launch_write_ceiling(dev_out, bytes, stream);
-  return e == hipSuccess ? SLRNG_OK : hip_fail(e);
+  return guarded([&]() -> int {
+    if (!dev_out || bytes % 16 || ((uintptr_t)dev_out & 15)) return SLRNG_EINVAL;
+    hipError_t e = launch_write_ceiling(dev_out, bytes, stream);
+    return e == hipSuccess ? SLRNG_OK : hip_fail(e);
+  });
 }
 
 extern "C" int slrng_calib_copy(void *dst, const void *src, uint64_t bytes, hipStream_t stream) {
-  if (!dst || !src || bytes % 16 || ((uintptr_t)dst & 15) || ((uintptr_t)src & 15))
-    return SLRNG_EINVAL;
-  hipError_t e = launch_copy(dst, src, bytes, stream);
-  return e == hipSuccess ? SLRNG_OK : hip_fail(e);
+  return guarded([&]() -> int {
+    if (!dst || !src || bytes % 16 || ((uintptr_t)dst & 15) || ((uintptr_t)src & 15))
+      return SLRNG_EINVAL;
+    hipError_t e = launch_copy(dst, src, bytes, stream);
+    return e == hipSuccess ? SLRNG_OK : hip_fail(e);
+  });
 }

@@ -3,6 +3,8 @@
 #include <hip/hip_runtime_api.h>
 #include <stdint.h>
 
+#include <new>
+
 #include "../../include/slrng.h"
 #include "f2poly.hpp"
 
@@ -22,5 +24,19 @@ const uint64_t *streams_state_ptr(const slrng_streams *h);
 int check_batch_opts(const slrng_batch_opts &o);
 void plan_slots(uint64_t S, uint64_t n, const slrng_tuning &t, uint64_t &C, uint64_t &nslots,
                 uint64_t &D);
+
+// Every C entry point runs its body through guarded(): a C++ exception
+// (allocation failure, thread creation) becomes a return code instead of
+// crossing the C ABI.
+template <typename F>
+int guarded(F &&f) noexcept {
+  try {
+    return f();
+  } catch (const std::bad_alloc &) {
+    return SLRNG_ENOMEM;
+  } catch (...) {
+    return SLRNG_ENOMEM;
+  }
+}
 
 }  // namespace slrng

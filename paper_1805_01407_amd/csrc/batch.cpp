@@ -374,14 +374,16 @@ static void free_batch(slrng_batch *b) {
 }
 
 extern "C" int slrng_batch_default_opts(slrng_batch_opts *o) {
-  if (!o) return SLRNG_EINVAL;
-  memset(o, 0, sizeof(*o));
-  o->mode = SLRNG_BATCH_GRAPH;
-  o->tile = 32;
-  o->waves_per_cu = 8;
-  for (int v = 0; v < SLRNG_NUM_VARIANTS; v++)
-    o->chunk[v] = (v == 9 || v == 10 || v == 11 || v == 13) ? 65536 : 8192;
-  return SLRNG_OK;
+  return guarded([&]() -> int {
+    if (!o) return SLRNG_EINVAL;
+    memset(o, 0, sizeof(*o));
+    o->mode = SLRNG_BATCH_GRAPH;
+    o->tile = 32;
+    o->waves_per_cu = 8;
+    for (int v = 0; v < SLRNG_NUM_VARIANTS; v++)
+      o->chunk[v] = (v == 9 || v == 10 || v == 11 || v == 13) ? 65536 : 8192;
+    return SLRNG_OK;
+  });
 }
 
 namespace slrng {
@@ -429,211 +431,223 @@ static int enqueue_all(slrng_batch *b, hipStream_t st) {
 
 extern "C" int slrng_batch_plan(const slrng_request *reqs, size_t n_reqs,
                                 const slrng_batch_opts *opts, slrng_batch **out) {
-  if (!out || (n_reqs && !reqs)) return SLRNG_EINVAL;
-  *out = nullptr;
-  slrng_batch_opts o;
-  if (opts) o = *opts;
-  else slrng_batch_default_opts(&o);
-  int rc = check_batch_opts(o);
-  if (rc) return rc;
-  if (n_reqs > (1u << 24)) return SLRNG_ERANGE;
-  std::vector<PlanReq> pr(n_reqs);
-  for (size_t r = 0; r < n_reqs; r++) {
-    const slrng_request &q = reqs[r];
-    if (!valid_variant64(q.variant) || (q.kind != SLRNG_U64 && q.kind != SLRNG_F64)) return SLRNG_EINVAL;
-    if (q.n && (!q.dev_out || ((uintptr_t)q.dev_out & 7))) return SLRNG_EINVAL;
-    if (q.n > UINT64_MAX / 8) return SLRNG_ERANGE;
-    pr[r] = PlanReq{q.variant, q.kind, q.n, (uint64_t)(uintptr_t)q.dev_out, q.start, false, q.seed, 0,
-                    (uint64_t)r};
-  }
-  slrng_batch *b = new (std::nothrow) slrng_batch();
-  if (!b) return SLRNG_ENOMEM;
-  b->opts = o;
-  b->n_requests = n_reqs;
-  hipError_t e = hipGetDevice(&b->device);
-  if (e != hipSuccess) {
-    free_batch(b);
-    return hip_fail(e);
-  }
-  rc = batch_grid_blocks(o, b->device, &b->blocks);
-  if (!rc) rc = build_plan(pr.data(), n_reqs, o, b->device, (uint64_t)b->blocks * kBlock, b->plan);
-  if (rc) {
-    free_batch(b);
-    return rc;
-  }
-  const PlanHost &P = b->plan;
-  auto upload = [&](void **dst, const void *src, size_t bytes) -> int {
-    if (!bytes) return SLRNG_OK;
-    hipError_t e3 = hipMalloc(dst, bytes);
-    if (e3 != hipSuccess) return e3 == hipErrorOutOfMemory ? SLRNG_ENOMEM : hip_fail(e3);
-    e3 = hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice);
-    return e3 == hipSuccess ? SLRNG_OK : hip_fail(e3);
-  };
-  rc = upload((void **)&b->d_tiles, P.tiles.data(), P.tiles.size() * sizeof(TileDesc));
-  if (!rc) rc = upload((void **)&b->d_lanes, P.lanes.data(), P.lanes.size() * sizeof(LaneDesc));
-  if (!rc) rc = upload((void **)&b->d_runs, P.runs.data(), P.runs.size() * sizeof(RunDesc));
-  if (!rc) {
-    std::vector<unsigned> zeros(P.units.size(), 0);
-    rc = upload((void **)&b->d_counter, zeros.data(), zeros.size() * sizeof(unsigned));
-  }
-  if (!rc && P.rs.nslots) {
-    e = hipMalloc(&b->d_req_state, (size_t)P.rs.nslots * 16 * 8);
-    if (e != hipSuccess) rc = hip_fail(e);
-    if (!rc) rc = upload((void **)&b->d_req_seed, P.rs.seeds.data(), P.rs.seeds.size() * 8);
-    if (!rc) rc = upload((void **)&b->d_req_poly, P.rs.polys.data(), P.rs.polys.size() * 8);
-    if (!rc) rc = upload((void **)&b->d_req_slot, P.rs.slot.data(), P.rs.slot.size() * 4);
-    uint32_t off = 0;
-    for (size_t k = 0; k < P.rs.runs.size() && !rc; k++) {
-      ReqArgs ra;
-      ra.seeds = b->d_req_seed + off;
-      ra.origin_state = nullptr;
-      ra.origin_stride = 0;
-      ra.origin_idx = nullptr;
-      ra.polys = b->d_req_poly + (size_t)off * 16;
-      ra.slot = b->d_req_slot + off;
-      ra.req_state = b->d_req_state;
-      ra.m = P.rs.runs[k].second;
-      b->req_launches.push_back({P.rs.runs[k].first, ra});
-      off += ra.m;
+  return guarded([&]() -> int {
+    if (!out || (n_reqs && !reqs)) return SLRNG_EINVAL;
+    *out = nullptr;
+    slrng_batch_opts o;
+    if (opts) o = *opts;
+    else slrng_batch_default_opts(&o);
+    int rc = check_batch_opts(o);
+    if (rc) return rc;
+    if (n_reqs > (1u << 24)) return SLRNG_ERANGE;
+    std::vector<PlanReq> pr(n_reqs);
+    for (size_t r = 0; r < n_reqs; r++) {
+      const slrng_request &q = reqs[r];
+      if (!valid_variant64(q.variant) || (q.kind != SLRNG_U64 && q.kind != SLRNG_F64)) return SLRNG_EINVAL;
+      if (q.n && (!q.dev_out || ((uintptr_t)q.dev_out & 7))) return SLRNG_EINVAL;
+      if (q.n > UINT64_MAX / 8) return SLRNG_ERANGE;
+      pr[r] = PlanReq{q.variant, q.kind, q.n, (uint64_t)(uintptr_t)q.dev_out, q.start, false, q.seed, 0,
+                      (uint64_t)r};
     }
-  }
-  if (rc) {
-    free_batch(b);
-    return rc;
-  }
-  b->args.tiles = b->d_tiles;
-  b->args.ntiles = (uint32_t)P.tiles.size();
-  b->args.pad = 0;
-  b->args.lanes = b->d_lanes;
-  b->args.runs = b->d_runs;
-  b->args.req_state = b->d_req_state;
-  b->args.counter = b->d_counter;
-  for (int v = 0; v < kNumVariants; v++) {
-    b->args.tab[v] = P.tab[v];
-    b->args.tab_n[v] = P.tab_n[v];
-  }
-  // graph: capture the whole enqueue sequence once
-  if (o.mode == SLRNG_BATCH_GRAPH) {
-    hipStream_t cs = nullptr;
-    e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+    slrng_batch *b = new (std::nothrow) slrng_batch();
+    if (!b) return SLRNG_ENOMEM;
+    b->opts = o;
+    b->n_requests = n_reqs;
+    hipError_t e = hipGetDevice(&b->device);
     if (e != hipSuccess) {
       free_batch(b);
       return hip_fail(e);
     }
-    e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
-    if (e == hipSuccess) {
-      rc = enqueue_all(b, cs);
-      hipGraph_t g = nullptr;
-      hipError_t e2 = hipStreamEndCapture(cs, &g);
-      if (!rc && e2 != hipSuccess) rc = hip_fail(e2);
-      b->graph = g;
-      if (!rc) {
-        e2 = hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0);
-        if (e2 != hipSuccess) rc = hip_fail(e2);
-      }
-    } else {
-      rc = hip_fail(e);
-    }
-    (void)hipStreamDestroy(cs);
+    rc = batch_grid_blocks(o, b->device, &b->blocks);
+    if (!rc) rc = build_plan(pr.data(), n_reqs, o, b->device, (uint64_t)b->blocks * kBlock, b->plan);
     if (rc) {
       free_batch(b);
       return rc;
     }
-  }
-  *out = b;
-  return SLRNG_OK;
+    const PlanHost &P = b->plan;
+    auto upload = [&](void **dst, const void *src, size_t bytes) -> int {
+      if (!bytes) return SLRNG_OK;
+      hipError_t e3 = hipMalloc(dst, bytes);
+      if (e3 != hipSuccess) return e3 == hipErrorOutOfMemory ? SLRNG_ENOMEM : hip_fail(e3);
+      e3 = hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice);
+      return e3 == hipSuccess ? SLRNG_OK : hip_fail(e3);
+    };
+    rc = upload((void **)&b->d_tiles, P.tiles.data(), P.tiles.size() * sizeof(TileDesc));
+    if (!rc) rc = upload((void **)&b->d_lanes, P.lanes.data(), P.lanes.size() * sizeof(LaneDesc));
+    if (!rc) rc = upload((void **)&b->d_runs, P.runs.data(), P.runs.size() * sizeof(RunDesc));
+    if (!rc) {
+      std::vector<unsigned> zeros(P.units.size(), 0);
+      rc = upload((void **)&b->d_counter, zeros.data(), zeros.size() * sizeof(unsigned));
+    }
+    if (!rc && P.rs.nslots) {
+      e = hipMalloc(&b->d_req_state, (size_t)P.rs.nslots * 16 * 8);
+      if (e != hipSuccess) rc = hip_fail(e);
+      if (!rc) rc = upload((void **)&b->d_req_seed, P.rs.seeds.data(), P.rs.seeds.size() * 8);
+      if (!rc) rc = upload((void **)&b->d_req_poly, P.rs.polys.data(), P.rs.polys.size() * 8);
+      if (!rc) rc = upload((void **)&b->d_req_slot, P.rs.slot.data(), P.rs.slot.size() * 4);
+      uint32_t off = 0;
+      for (size_t k = 0; k < P.rs.runs.size() && !rc; k++) {
+        ReqArgs ra;
+        ra.seeds = b->d_req_seed + off;
+        ra.origin_state = nullptr;
+        ra.origin_stride = 0;
+        ra.origin_idx = nullptr;
+        ra.polys = b->d_req_poly + (size_t)off * 16;
+        ra.slot = b->d_req_slot + off;
+        ra.req_state = b->d_req_state;
+        ra.m = P.rs.runs[k].second;
+        b->req_launches.push_back({P.rs.runs[k].first, ra});
+        off += ra.m;
+      }
+    }
+    if (rc) {
+      free_batch(b);
+      return rc;
+    }
+    b->args.tiles = b->d_tiles;
+    b->args.ntiles = (uint32_t)P.tiles.size();
+    b->args.pad = 0;
+    b->args.lanes = b->d_lanes;
+    b->args.runs = b->d_runs;
+    b->args.req_state = b->d_req_state;
+    b->args.counter = b->d_counter;
+    for (int v = 0; v < kNumVariants; v++) {
+      b->args.tab[v] = P.tab[v];
+      b->args.tab_n[v] = P.tab_n[v];
+    }
+    // graph: capture the whole enqueue sequence once
+    if (o.mode == SLRNG_BATCH_GRAPH) {
+      hipStream_t cs = nullptr;
+      e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+      if (e != hipSuccess) {
+        free_batch(b);
+        return hip_fail(e);
+      }
+      e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+      if (e == hipSuccess) {
+        rc = enqueue_all(b, cs);
+        hipGraph_t g = nullptr;
+        hipError_t e2 = hipStreamEndCapture(cs, &g);
+        if (!rc && e2 != hipSuccess) rc = hip_fail(e2);
+        b->graph = g;
+        if (!rc) {
+          e2 = hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0);
+          if (e2 != hipSuccess) rc = hip_fail(e2);
+        }
+      } else {
+        rc = hip_fail(e);
+      }
+      (void)hipStreamDestroy(cs);
+      if (rc) {
+        free_batch(b);
+        return rc;
+      }
+    }
+    *out = b;
+    return SLRNG_OK;
+  });
 }
 
 extern "C" int slrng_batch_launch(slrng_batch *b, hipStream_t stream) {
-  if (!b) return SLRNG_EINVAL;
-  if (b->exec) {
-    hipError_t e = hipGraphLaunch(b->exec, stream);
-    return e == hipSuccess ? SLRNG_OK : hip_fail(e);
-  }
-  return enqueue_all(b, stream);
+  return guarded([&]() -> int {
+    if (!b) return SLRNG_EINVAL;
+    if (b->exec) {
+      hipError_t e = hipGraphLaunch(b->exec, stream);
+      return e == hipSuccess ? SLRNG_OK : hip_fail(e);
+    }
+    return enqueue_all(b, stream);
+  });
 }
 
 extern "C" int slrng_batch_latencies(slrng_batch *b, hipStream_t stream, double *done_ms) {
-  if (!b || !done_ms) return SLRNG_EINVAL;
-  for (uint64_t r = 0; r < b->n_requests; r++) done_ms[r] = 0.0;
-  const bool per_unit = b->opts.mode == SLRNG_BATCH_PLAIN;
-  const auto &units = b->plan.units;
-  std::vector<hipEvent_t> ev(per_unit ? units.size() + 1 : 2, nullptr);
-  int rc = SLRNG_OK;
-  for (auto &x : ev) {
-    hipError_t e = hipEventCreate(&x);
-    if (e != hipSuccess) {
-      rc = hip_fail(e);
-      break;
+  return guarded([&]() -> int {
+    if (!b || !done_ms) return SLRNG_EINVAL;
+    for (uint64_t r = 0; r < b->n_requests; r++) done_ms[r] = 0.0;
+    const bool per_unit = b->opts.mode == SLRNG_BATCH_PLAIN;
+    const auto &units = b->plan.units;
+    std::vector<hipEvent_t> ev(per_unit ? units.size() + 1 : 2, nullptr);
+    int rc = SLRNG_OK;
+    for (auto &x : ev) {
+      hipError_t e = hipEventCreate(&x);
+      if (e != hipSuccess) {
+        rc = hip_fail(e);
+        break;
+      }
     }
-  }
-  if (!rc) {
-    hipError_t e = hipEventRecord(ev[0], stream);
-    if (e != hipSuccess) rc = hip_fail(e);
-  }
-  if (!rc && !per_unit) {
-    rc = slrng_batch_launch(b, stream);
     if (!rc) {
-      hipError_t e = hipEventRecord(ev[1], stream);
+      hipError_t e = hipEventRecord(ev[0], stream);
       if (e != hipSuccess) rc = hip_fail(e);
     }
-  } else if (!rc) {
-    rc = enqueue_req_states(b, stream);
-    for (size_t i = 0; i < units.size() && !rc; i++) {
-      rc = enqueue_unit(b, units[i], b->d_counter + (units.size() > 1 ? i : 0), stream);
+    if (!rc && !per_unit) {
+      rc = slrng_batch_launch(b, stream);
       if (!rc) {
-        hipError_t e = hipEventRecord(ev[i + 1], stream);
+        hipError_t e = hipEventRecord(ev[1], stream);
         if (e != hipSuccess) rc = hip_fail(e);
       }
-    }
-  }
-  if (!rc) {
-    hipError_t e = hipStreamSynchronize(stream);
-    if (e != hipSuccess) rc = hip_fail(e);
-  }
-  if (!rc) {
-    if (!per_unit) {
-      float ms = 0;
-      hipError_t e = hipEventElapsedTime(&ms, ev[0], ev[1]);
-      if (e != hipSuccess) rc = hip_fail(e);
-      for (uint64_t r = 0; r < b->n_requests && !rc; r++) done_ms[r] = ms;
-    } else {
+    } else if (!rc) {
+      rc = enqueue_req_states(b, stream);
       for (size_t i = 0; i < units.size() && !rc; i++) {
-        float ms = 0;
-        hipError_t e = hipEventElapsedTime(&ms, ev[0], ev[i + 1]);
-        if (e != hipSuccess) rc = hip_fail(e);
-        else if (units[i].req >= 0) done_ms[units[i].req] = ms;
+        rc = enqueue_unit(b, units[i], b->d_counter + (units.size() > 1 ? i : 0), stream);
+        if (!rc) {
+          hipError_t e = hipEventRecord(ev[i + 1], stream);
+          if (e != hipSuccess) rc = hip_fail(e);
+        }
       }
     }
-  }
-  for (auto &x : ev)
-    if (x) (void)hipEventDestroy(x);
-  return rc;
+    if (!rc) {
+      hipError_t e = hipStreamSynchronize(stream);
+      if (e != hipSuccess) rc = hip_fail(e);
+    }
+    if (!rc) {
+      if (!per_unit) {
+        float ms = 0;
+        hipError_t e = hipEventElapsedTime(&ms, ev[0], ev[1]);
+        if (e != hipSuccess) rc = hip_fail(e);
+        for (uint64_t r = 0; r < b->n_requests && !rc; r++) done_ms[r] = ms;
+      } else {
+        for (size_t i = 0; i < units.size() && !rc; i++) {
+          float ms = 0;
+          hipError_t e = hipEventElapsedTime(&ms, ev[0], ev[i + 1]);
+          if (e != hipSuccess) rc = hip_fail(e);
+          else if (units[i].req >= 0) done_ms[units[i].req] = ms;
+        }
+      }
+    }
+    for (auto &x : ev)
+      if (x) (void)hipEventDestroy(x);
+    return rc;
+  });
 }
 
 extern "C" int slrng_batch_info(const slrng_batch *b, uint64_t *n_tiles, uint64_t *n_lanes,
                                 uint64_t *total_outputs) {
-  if (!b) return SLRNG_EINVAL;
-  if (n_tiles) *n_tiles = b->plan.tiles.size();
-  if (n_lanes) *n_lanes = b->plan.lanes.size() + (uint64_t)b->plan.runs.size() * kWave;
-  if (total_outputs) *total_outputs = b->plan.total_outputs;
-  return SLRNG_OK;
+  return guarded([&]() -> int {
+    if (!b) return SLRNG_EINVAL;
+    if (n_tiles) *n_tiles = b->plan.tiles.size();
+    if (n_lanes) *n_lanes = b->plan.lanes.size() + (uint64_t)b->plan.runs.size() * kWave;
+    if (total_outputs) *total_outputs = b->plan.total_outputs;
+    return SLRNG_OK;
+  });
 }
 
 extern "C" int slrng_batch_destroy(slrng_batch *b) {
-  if (!b) return SLRNG_EINVAL;
-  free_batch(b);
-  return SLRNG_OK;
+  return guarded([&]() -> int {
+    if (!b) return SLRNG_EINVAL;
+    free_batch(b);
+    return SLRNG_OK;
+  });
 }
 
 extern "C" int slrng_batch_run(const slrng_request *reqs, size_t n_reqs, const slrng_batch_opts *opts,
                                hipStream_t stream) {
-  slrng_batch *b = nullptr;
-  int rc = slrng_batch_plan(reqs, n_reqs, opts, &b);
-  if (rc) return rc;
-  rc = slrng_batch_launch(b, stream);
-  hipError_t e = hipStreamSynchronize(stream);
-  free_batch(b);
-  if (rc) return rc;
-  return e == hipSuccess ? SLRNG_OK : hip_fail(e);
+  return guarded([&]() -> int {
+    slrng_batch *b = nullptr;
+    int rc = slrng_batch_plan(reqs, n_reqs, opts, &b);
+    if (rc) return rc;
+    rc = slrng_batch_launch(b, stream);
+    hipError_t e = hipStreamSynchronize(stream);
+    free_batch(b);
+    if (rc) return rc;
+    return e == hipSuccess ? SLRNG_OK : hip_fail(e);
+  });
 }

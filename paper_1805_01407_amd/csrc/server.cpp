@@ -414,20 +414,22 @@ static void completer_main(slrng_server *sv) {
 }
 
 extern "C" int slrng_server_default_opts(slrng_server_opts *o) {
-  if (!o) return SLRNG_EINVAL;
-  memset(o, 0, sizeof(*o));
-  o->budget_bytes = 16ull << 30;
-  o->n_streams = 4096;
-  o->variant = SLRNG_XOSHIRO256_STARSTAR;
-  o->seed = 42;
-  o->max_batch = 4096;
-  o->inflight = 3;
-  o->tile = 32;
-  o->waves_per_cu = 8;
-  o->chunk = 0;
-  o->window_us = 0;
-  o->window_bytes = 256ull << 20;
-  return SLRNG_OK;
+  return guarded([&]() -> int {
+    if (!o) return SLRNG_EINVAL;
+    memset(o, 0, sizeof(*o));
+    o->budget_bytes = 16ull << 30;
+    o->n_streams = 4096;
+    o->variant = SLRNG_XOSHIRO256_STARSTAR;
+    o->seed = 42;
+    o->max_batch = 4096;
+    o->inflight = 3;
+    o->tile = 32;
+    o->waves_per_cu = 8;
+    o->chunk = 0;
+    o->window_us = 0;
+    o->window_bytes = 256ull << 20;
+    return SLRNG_OK;
+  });
 }
 
 static void destroy_server(slrng_server *sv) {
@@ -457,267 +459,287 @@ static void destroy_server(slrng_server *sv) {
 }
 
 extern "C" int slrng_server_create(const slrng_server_opts *opts, slrng_server **out) {
-  if (!out) return SLRNG_EINVAL;
-  *out = nullptr;
-  slrng_server_opts o;
-  if (opts) o = *opts;
-  else slrng_server_default_opts(&o);
-  if (!valid_variant64(o.variant) || o.n_streams == 0 || o.budget_bytes < kAlign) return SLRNG_EINVAL;
-  if (o.max_batch <= 0) o.max_batch = 4096;
-  if (o.inflight <= 0) o.inflight = 3;
-  if (o.inflight > 8 || o.min_chunk < 0 || o.window_us < 0) return SLRNG_EINVAL;
-  if (o.tile == 0) o.tile = 32;
-  slrng_batch_opts bo;
-  slrng_batch_default_opts(&bo);
-  bo.mode = SLRNG_BATCH_PERSISTENT;
-  bo.tile = o.tile;
-  bo.waves_per_cu = o.waves_per_cu;
-  if (o.chunk) bo.chunk[o.variant] = o.chunk;
-  int rc = check_batch_opts(bo);
-  if (rc) return rc;
-  slrng_server *sv = new (std::nothrow) slrng_server();
-  if (!sv) return SLRNG_ENOMEM;
-  sv->o = o;
-  sv->bo = bo;
-  hipError_t e = hipGetDevice(&sv->device);
-  if (e != hipSuccess) {
-    delete sv;
-    return hip_fail(e);
-  }
-  rc = batch_grid_blocks(bo, sv->device, &sv->blocks);
-  // every chunk table an iteration can pick, built now rather than in the
-  // middle of serving (one table of 65,536 polynomials takes milliseconds)
-  if (!rc) rc = warm_fit_tables(sv->device, o.variant, bo, (uint64_t)o.min_chunk);
-  if (!rc) rc = slrng_streams_create(o.variant, o.seed, o.n_streams, nullptr, &sv->streams);
-  // The basis states s_j M^i (i < n) of every resident stream, when they fit
-  // in kMaxBasisBytes: a request's start state is then a sum of basis states
-  // selected by x^pos mod p, computed by a whole wave at once, instead of n
-  // serial steps of one lane.
-  if (!rc) {
-    const uint64_t k = (uint64_t)variant_words(o.variant);
-    const uint64_t bytes = (uint64_t)o.n_streams * 64 * k * k * 8;
-    if (bytes <= kMaxBasisBytes) {
-      e = hipMalloc(&sv->basis, bytes);
-      if (e == hipSuccess) e = launch_basis(o.variant, streams_state_ptr(sv->streams), o.n_streams,
-                                            sv->basis, nullptr);
+  return guarded([&]() -> int {
+    if (!out) return SLRNG_EINVAL;
+    *out = nullptr;
+    slrng_server_opts o;
+    if (opts) o = *opts;
+    else slrng_server_default_opts(&o);
+    if (!valid_variant64(o.variant) || o.n_streams == 0 || o.budget_bytes < kAlign) return SLRNG_EINVAL;
+    if (o.max_batch <= 0) o.max_batch = 4096;
+    if (o.inflight <= 0) o.inflight = 3;
+    if (o.inflight > 8 || o.min_chunk < 0 || o.window_us < 0) return SLRNG_EINVAL;
+    if (o.tile == 0) o.tile = 32;
+    slrng_batch_opts bo;
+    slrng_batch_default_opts(&bo);
+    bo.mode = SLRNG_BATCH_PERSISTENT;
+    bo.tile = o.tile;
+    bo.waves_per_cu = o.waves_per_cu;
+    if (o.chunk) bo.chunk[o.variant] = o.chunk;
+    int rc = check_batch_opts(bo);
+    if (rc) return rc;
+    slrng_server *sv = new (std::nothrow) slrng_server();
+    if (!sv) return SLRNG_ENOMEM;
+    sv->o = o;
+    sv->bo = bo;
+    hipError_t e = hipGetDevice(&sv->device);
+    if (e != hipSuccess) {
+      delete sv;
+      return hip_fail(e);
+    }
+    rc = batch_grid_blocks(bo, sv->device, &sv->blocks);
+    // every chunk table an iteration can pick, built now rather than in the
+    // middle of serving (one table of 65,536 polynomials takes milliseconds)
+    if (!rc) rc = warm_fit_tables(sv->device, o.variant, bo, (uint64_t)o.min_chunk);
+    if (!rc) rc = slrng_streams_create(o.variant, o.seed, o.n_streams, nullptr, &sv->streams);
+    // The basis states s_j M^i (i < n) of every resident stream, when they fit
+    // in kMaxBasisBytes: a request's start state is then a sum of basis states
+    // selected by x^pos mod p, computed by a whole wave at once, instead of n
+    // serial steps of one lane.
+    if (!rc) {
+      const uint64_t k = (uint64_t)variant_words(o.variant);
+      const uint64_t bytes = (uint64_t)o.n_streams * 64 * k * k * 8;
+      if (bytes <= kMaxBasisBytes) {
+        e = hipMalloc(&sv->basis, bytes);
+        if (e == hipSuccess) e = launch_basis(o.variant, streams_state_ptr(sv->streams), o.n_streams,
+                                              sv->basis, nullptr);
+        if (e != hipSuccess) rc = e == hipErrorOutOfMemory ? SLRNG_ENOMEM : hip_fail(e);
+      }
+    }
+    if (!rc) {
+      e = hipDeviceSynchronize();
+      if (e != hipSuccess) rc = hip_fail(e);
+    }
+    if (!rc) {
+      e = hipMalloc(&sv->arena_dev, o.budget_bytes);
       if (e != hipSuccess) rc = e == hipErrorOutOfMemory ? SLRNG_ENOMEM : hip_fail(e);
     }
-  }
-  if (!rc) {
-    e = hipDeviceSynchronize();
-    if (e != hipSuccess) rc = hip_fail(e);
-  }
-  if (!rc) {
-    e = hipMalloc(&sv->arena_dev, o.budget_bytes);
-    if (e != hipSuccess) rc = e == hipErrorOutOfMemory ? SLRNG_ENOMEM : hip_fail(e);
-  }
-  if (!rc) {
-    sv->arena.init(o.budget_bytes / kAlign * kAlign);
-    sv->head.assign(o.n_streams, 0);
-    sv->slots.resize(o.inflight);
-    for (auto &s : sv->slots) {
-      e = hipStreamCreateWithFlags(&s.st, hipStreamNonBlocking);
-      if (e == hipSuccess) e = hipEventCreate(&s.ev0);
-      if (e == hipSuccess) e = hipEventCreate(&s.evk);
-      if (e == hipSuccess) e = hipEventCreate(&s.ev1);
-      if (e != hipSuccess) {
-        rc = hip_fail(e);
-        break;
+    if (!rc) {
+      sv->arena.init(o.budget_bytes / kAlign * kAlign);
+      sv->head.assign(o.n_streams, 0);
+      sv->slots.resize(o.inflight);
+      for (auto &s : sv->slots) {
+        e = hipStreamCreateWithFlags(&s.st, hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipEventCreate(&s.ev0);
+        if (e == hipSuccess) e = hipEventCreate(&s.evk);
+        if (e == hipSuccess) e = hipEventCreate(&s.ev1);
+        if (e != hipSuccess) {
+          rc = hip_fail(e);
+          break;
+        }
+        // buffers for typical iterations now: pinned allocations take
+        // milliseconds, which the first iterations would otherwise wait for
+        rc = slot_reserve(s, kInitialPackBytes, kInitialReqs);
+        if (rc) break;
       }
-      // buffers for typical iterations now: pinned allocations take
-      // milliseconds, which the first iterations would otherwise wait for
-      rc = slot_reserve(s, kInitialPackBytes, kInitialReqs);
-      if (rc) break;
     }
-  }
-  if (!rc) {
-    e = hipEventCreate(&sv->ref);
-    if (e == hipSuccess) e = hipEventRecord(sv->ref, sv->slots[0].st);
-    if (e == hipSuccess) e = hipEventSynchronize(sv->ref);
-    if (e != hipSuccess) rc = hip_fail(e);
-  }
-  if (rc) {
-    sv->worker_done = true;
-    destroy_server(sv);
-    return rc;
-  }
-  sv->t0 = Clock::now();
-  sv->worker = std::thread(worker_main, sv);
-  sv->completer = std::thread(completer_main, sv);
-  *out = sv;
-  return SLRNG_OK;
+    if (!rc) {
+      e = hipEventCreate(&sv->ref);
+      if (e == hipSuccess) e = hipEventRecord(sv->ref, sv->slots[0].st);
+      if (e == hipSuccess) e = hipEventSynchronize(sv->ref);
+      if (e != hipSuccess) rc = hip_fail(e);
+    }
+    if (rc) {
+      sv->worker_done = true;
+      destroy_server(sv);
+      return rc;
+    }
+    sv->t0 = Clock::now();
+    sv->worker = std::thread(worker_main, sv);
+    sv->completer = std::thread(completer_main, sv);
+    *out = sv;
+    return SLRNG_OK;
+  });
 }
 
 extern "C" int slrng_server_destroy(slrng_server *sv) {
-  if (!sv) return SLRNG_EINVAL;
-  destroy_server(sv);
-  return SLRNG_OK;
+  return guarded([&]() -> int {
+    if (!sv) return SLRNG_EINVAL;
+    destroy_server(sv);
+    return SLRNG_OK;
+  });
 }
 
 extern "C" int slrng_server_submit(slrng_server *sv, uint32_t stream_id, uint64_t n, int kind,
                                    int flags, uint64_t *ticket) {
-  if (!sv || !ticket || (kind != SLRNG_U64 && kind != SLRNG_F64)) return SLRNG_EINVAL;
-  if (stream_id >= sv->o.n_streams || n == 0) return SLRNG_EINVAL;
-  if (n > sv->arena.size / 8) return SLRNG_ERANGE;
-  std::unique_lock<std::mutex> lk(sv->mu);
-  uint64_t off = 0;
-  for (;;) {
-    if (sv->stop) return SLRNG_EINVAL;
-    if (sv->arena.alloc(n * 8, &off)) break;
-    if (flags & SLRNG_SUBMIT_NONBLOCK) {
-      sv->rejected++;
-      return SLRNG_EAGAIN;
+  return guarded([&]() -> int {
+    if (!sv || !ticket || (kind != SLRNG_U64 && kind != SLRNG_F64)) return SLRNG_EINVAL;
+    if (stream_id >= sv->o.n_streams || n == 0) return SLRNG_EINVAL;
+    if (n > sv->arena.size / 8) return SLRNG_ERANGE;
+    std::unique_lock<std::mutex> lk(sv->mu);
+    uint64_t off = 0;
+    for (;;) {
+      if (sv->stop) return SLRNG_EINVAL;
+      if (sv->arena.alloc(n * 8, &off)) break;
+      if (flags & SLRNG_SUBMIT_NONBLOCK) {
+        sv->rejected++;
+        return SLRNG_EAGAIN;
+      }
+      sv->cv_space.wait(lk);
     }
-    sv->cv_space.wait(lk);
-  }
-  sv->peak_reserved = std::max(sv->peak_reserved, sv->arena.used);
-  Req q;
-  q.stream = stream_id;
-  q.kind = kind;
-  q.n = n;
-  q.pos = sv->head[stream_id];
-  sv->head[stream_id] += n;
-  q.off = off;
-  q.auto_release = (flags & SLRNG_SUBMIT_AUTORELEASE) != 0;
-  q.state = R_PENDING;
-  q.t_submit = Clock::now();
-  const uint64_t t = sv->next_ticket++;
-  sv->reqs.emplace(t, q);
-  sv->pending.push_back(t);
-  sv->pending_bytes += n * 8;
-  sv->submitted++;
-  *ticket = t;
-  sv->cv_work.notify_one();
-  return SLRNG_OK;
+    sv->peak_reserved = std::max(sv->peak_reserved, sv->arena.used);
+    Req q;
+    q.stream = stream_id;
+    q.kind = kind;
+    q.n = n;
+    q.pos = sv->head[stream_id];
+    sv->head[stream_id] += n;
+    q.off = off;
+    q.auto_release = (flags & SLRNG_SUBMIT_AUTORELEASE) != 0;
+    q.state = R_PENDING;
+    q.t_submit = Clock::now();
+    const uint64_t t = sv->next_ticket++;
+    sv->reqs.emplace(t, q);
+    sv->pending.push_back(t);
+    sv->pending_bytes += n * 8;
+    sv->submitted++;
+    *ticket = t;
+    sv->cv_work.notify_one();
+    return SLRNG_OK;
+  });
 }
 
 extern "C" int slrng_server_poll(slrng_server *sv, uint64_t ticket, void **dev_ptr, uint64_t *pos) {
-  if (!sv) return SLRNG_EINVAL;
-  std::lock_guard<std::mutex> g(sv->mu);
-  auto f = sv->reqs.find(ticket);
-  if (f == sv->reqs.end()) return SLRNG_EINVAL;
-  if (dev_ptr) *dev_ptr = sv->arena_dev + f->second.off;
-  if (pos) *pos = f->second.pos;
-  if (f->second.state == R_FAILED) return SLRNG_EHIP;
-  return f->second.state == R_DONE ? 1 : 0;
-}
-
-extern "C" int slrng_server_wait(slrng_server *sv, uint64_t ticket, void **dev_ptr, uint64_t *pos) {
-  if (!sv) return SLRNG_EINVAL;
-  std::unique_lock<std::mutex> lk(sv->mu);
-  for (;;) {
+  return guarded([&]() -> int {
+    if (!sv) return SLRNG_EINVAL;
+    std::lock_guard<std::mutex> g(sv->mu);
     auto f = sv->reqs.find(ticket);
     if (f == sv->reqs.end()) return SLRNG_EINVAL;
     if (dev_ptr) *dev_ptr = sv->arena_dev + f->second.off;
     if (pos) *pos = f->second.pos;
     if (f->second.state == R_FAILED) return SLRNG_EHIP;
-    if (f->second.state == R_DONE) return SLRNG_OK;
-    sv->cv_done.wait(lk);
-  }
+    return f->second.state == R_DONE ? 1 : 0;
+  });
+}
+
+extern "C" int slrng_server_wait(slrng_server *sv, uint64_t ticket, void **dev_ptr, uint64_t *pos) {
+  return guarded([&]() -> int {
+    if (!sv) return SLRNG_EINVAL;
+    std::unique_lock<std::mutex> lk(sv->mu);
+    for (;;) {
+      auto f = sv->reqs.find(ticket);
+      if (f == sv->reqs.end()) return SLRNG_EINVAL;
+      if (dev_ptr) *dev_ptr = sv->arena_dev + f->second.off;
+      if (pos) *pos = f->second.pos;
+      if (f->second.state == R_FAILED) return SLRNG_EHIP;
+      if (f->second.state == R_DONE) return SLRNG_OK;
+      sv->cv_done.wait(lk);
+    }
+  });
 }
 
 extern "C" int slrng_server_release(slrng_server *sv, uint64_t ticket) {
-  if (!sv) return SLRNG_EINVAL;
-  std::lock_guard<std::mutex> g(sv->mu);
-  auto f = sv->reqs.find(ticket);
-  if (f == sv->reqs.end() || f->second.auto_release) return SLRNG_EINVAL;
-  if (f->second.state != R_DONE && f->second.state != R_FAILED) return SLRNG_EAGAIN;
-  sv->arena.release(f->second.off, f->second.n * 8);
-  sv->reqs.erase(f);
-  sv->cv_space.notify_all();
-  return SLRNG_OK;
+  return guarded([&]() -> int {
+    if (!sv) return SLRNG_EINVAL;
+    std::lock_guard<std::mutex> g(sv->mu);
+    auto f = sv->reqs.find(ticket);
+    if (f == sv->reqs.end() || f->second.auto_release) return SLRNG_EINVAL;
+    if (f->second.state != R_DONE && f->second.state != R_FAILED) return SLRNG_EAGAIN;
+    sv->arena.release(f->second.off, f->second.n * 8);
+    sv->reqs.erase(f);
+    sv->cv_space.notify_all();
+    return SLRNG_OK;
+  });
 }
 
 extern "C" int slrng_server_drain(slrng_server *sv) {
-  if (!sv) return SLRNG_EINVAL;
-  std::unique_lock<std::mutex> lk(sv->mu);
-  sv->cv_done.wait(lk, [&] {
-    if (!sv->pending.empty() || !sv->inflight.empty()) return false;
-    for (auto &s : sv->slots)
-      if (s.busy) return false;
-    return true;
+  return guarded([&]() -> int {
+    if (!sv) return SLRNG_EINVAL;
+    std::unique_lock<std::mutex> lk(sv->mu);
+    sv->cv_done.wait(lk, [&] {
+      if (!sv->pending.empty() || !sv->inflight.empty()) return false;
+      for (auto &s : sv->slots)
+        if (s.busy) return false;
+      return true;
+    });
+    return sv->error ? sv->error : SLRNG_OK;
   });
-  return sv->error ? sv->error : SLRNG_OK;
 }
 
 extern "C" int slrng_server_get_stats(slrng_server *sv, slrng_server_stats *out) {
-  if (!sv || !out) return SLRNG_EINVAL;
-  std::vector<double> lat;
-  {
-    std::lock_guard<std::mutex> g(sv->mu);
-    memset(out, 0, sizeof(*out));
-    out->submitted = sv->submitted;
-    out->completed = sv->completed;
-    out->failed = sv->failed;
-    out->rejected = sv->rejected;
-    out->outputs = sv->outputs;
-    out->wall_s = secs(sv->t0, Clock::now());
-    // unions of the iterations' device intervals (iterations may overlap)
-    auto union_ms = [](std::vector<std::pair<double, double>> iv) {
-      std::sort(iv.begin(), iv.end());
-      double tot = 0, cs = 0, ce = -1;
-      for (auto &x : iv) {
-        if (x.first > ce) {
-          if (ce > cs) tot += ce - cs;
-          cs = x.first;
-          ce = x.second;
-        } else {
-          ce = std::max(ce, x.second);
+  return guarded([&]() -> int {
+    if (!sv || !out) return SLRNG_EINVAL;
+    std::vector<double> lat;
+    {
+      std::lock_guard<std::mutex> g(sv->mu);
+      memset(out, 0, sizeof(*out));
+      out->submitted = sv->submitted;
+      out->completed = sv->completed;
+      out->failed = sv->failed;
+      out->rejected = sv->rejected;
+      out->outputs = sv->outputs;
+      out->wall_s = secs(sv->t0, Clock::now());
+      // unions of the iterations' device intervals (iterations may overlap)
+      auto union_ms = [](std::vector<std::pair<double, double>> iv) {
+        std::sort(iv.begin(), iv.end());
+        double tot = 0, cs = 0, ce = -1;
+        for (auto &x : iv) {
+          if (x.first > ce) {
+            if (ce > cs) tot += ce - cs;
+            cs = x.first;
+            ce = x.second;
+          } else {
+            ce = std::max(ce, x.second);
+          }
         }
-      }
-      if (ce > cs) tot += ce - cs;
-      return tot;
-    };
-    out->busy_s = union_ms(sv->busy_ivals) * 1e-3;
-    out->kernel_s = union_ms(sv->kernel_ivals) * 1e-3;
-    out->iterations = sv->iterations;
-    out->max_inflight = sv->max_inflight;
-    out->peak_reserved_bytes = sv->peak_reserved;
-    out->reserved_bytes = sv->arena.used;
-    out->max_batch = sv->max_batch_seen;
-    out->mean_batch = sv->iterations ? (double)sv->batch_sum / sv->iterations : 0.0;
-    lat = sv->lat_us;
-  }
-  if (!lat.empty()) {
-    std::sort(lat.begin(), lat.end());
-    auto q = [&](double p) { return lat[std::min(lat.size() - 1, (size_t)(p * (lat.size() - 1) + 0.5))]; };
-    out->p50_us = q(0.50);
-    out->p99_us = q(0.99);
-    out->max_us = lat.back();
-  }
-  return SLRNG_OK;
+        if (ce > cs) tot += ce - cs;
+        return tot;
+      };
+      out->busy_s = union_ms(sv->busy_ivals) * 1e-3;
+      out->kernel_s = union_ms(sv->kernel_ivals) * 1e-3;
+      out->iterations = sv->iterations;
+      out->max_inflight = sv->max_inflight;
+      out->peak_reserved_bytes = sv->peak_reserved;
+      out->reserved_bytes = sv->arena.used;
+      out->max_batch = sv->max_batch_seen;
+      out->mean_batch = sv->iterations ? (double)sv->batch_sum / sv->iterations : 0.0;
+      lat = sv->lat_us;
+    }
+    if (!lat.empty()) {
+      std::sort(lat.begin(), lat.end());
+      auto q = [&](double p) { return lat[std::min(lat.size() - 1, (size_t)(p * (lat.size() - 1) + 0.5))]; };
+      out->p50_us = q(0.50);
+      out->p99_us = q(0.99);
+      out->max_us = lat.back();
+    }
+    return SLRNG_OK;
+  });
 }
 
 extern "C" int slrng_server_reset_stats(slrng_server *sv) {
-  if (!sv) return SLRNG_EINVAL;
-  std::lock_guard<std::mutex> g(sv->mu);
-  sv->t0 = Clock::now();
-  sv->lat_us.clear();
-  sv->submitted = sv->completed = sv->failed = sv->rejected = sv->outputs = 0;
-  sv->iterations = sv->max_inflight = sv->max_batch_seen = sv->batch_sum = 0;
-  sv->peak_reserved = sv->arena.used;
-  sv->busy_ivals.clear();
-  sv->kernel_ivals.clear();
-  return SLRNG_OK;
+  return guarded([&]() -> int {
+    if (!sv) return SLRNG_EINVAL;
+    std::lock_guard<std::mutex> g(sv->mu);
+    sv->t0 = Clock::now();
+    sv->lat_us.clear();
+    sv->submitted = sv->completed = sv->failed = sv->rejected = sv->outputs = 0;
+    sv->iterations = sv->max_inflight = sv->max_batch_seen = sv->batch_sum = 0;
+    sv->peak_reserved = sv->arena.used;
+    sv->busy_ivals.clear();
+    sv->kernel_ivals.clear();
+    return SLRNG_OK;
+  });
 }
 
 extern "C" int slrng_server_replay(slrng_server *sv, const double *t_arrival_s, const uint32_t *stream_ids,
                                    const uint64_t *n, const int32_t *kinds, size_t count) {
-  if (!sv || (count && (!t_arrival_s || !stream_ids || !n || !kinds))) return SLRNG_EINVAL;
-  const Clock::time_point start = Clock::now();
-  for (size_t i = 0; i < count; i++) {
-    const auto due = start + std::chrono::duration_cast<Clock::duration>(
-                                 std::chrono::duration<double>(t_arrival_s[i]));
-    // sleep until close to the arrival, then spin for the last stretch
-    while (true) {
-      const auto now = Clock::now();
-      if (now >= due) break;
-      if (due - now > std::chrono::microseconds(200))
-        std::this_thread::sleep_for(due - now - std::chrono::microseconds(100));
+  return guarded([&]() -> int {
+    if (!sv || (count && (!t_arrival_s || !stream_ids || !n || !kinds))) return SLRNG_EINVAL;
+    const Clock::time_point start = Clock::now();
+    for (size_t i = 0; i < count; i++) {
+      const auto due = start + std::chrono::duration_cast<Clock::duration>(
+                                   std::chrono::duration<double>(t_arrival_s[i]));
+      // sleep until close to the arrival, then spin for the last stretch
+      while (true) {
+        const auto now = Clock::now();
+        if (now >= due) break;
+        if (due - now > std::chrono::microseconds(200))
+          std::this_thread::sleep_for(due - now - std::chrono::microseconds(100));
+      }
+      uint64_t t = 0;
+      int rc = slrng_server_submit(sv, stream_ids[i], n[i], kinds[i], SLRNG_SUBMIT_AUTORELEASE, &t);
+      if (rc) return rc;
     }
-    uint64_t t = 0;
-    int rc = slrng_server_submit(sv, stream_ids[i], n[i], kinds[i], SLRNG_SUBMIT_AUTORELEASE, &t);
-    if (rc) return rc;
-  }
-  return slrng_server_drain(sv);
+    return slrng_server_drain(sv);
+  });
 }
