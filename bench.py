@@ -12,7 +12,8 @@ Prints one JSON line (rank 0).  `value` = outputs (uint64 + double) per
 second over the timed steps; `roofline` describes the generation kernel
 (HIP events around each launch; `traffic` from the committed HBM counters).
 The same line carries the other workloads, each run once after the sweep:
-jump-ahead at scale (2^20 streams), the 32-bit generators, the on-device
+the small case (1,024 streams), jump-ahead at scale (2^20 streams), the
+32-bit generators, the on-device
 linearity check, the batched-requests workload (one graph launch against one
 launch per request), the serving trace (continuous batching against the
 plain form) and the CPU oracle on a bounded sample (`cpu_baseline`).
@@ -71,27 +72,36 @@ def cpu_baseline(batch: int, N: int, seconds: float = 15.0) -> dict:
     """The oracle (plain serial C, threaded over streams only) on a bounded
     sample of the same workload: for each of the eight generators in turn,
     batches of `batch` streams of the seed-1 chain, N outputs each, as uint64
-    and as doubles, until `seconds` of host time are spent."""
+    and as doubles, until `seconds` of host time are spent, on all the host
+    threads available (at most 16); then the same on one thread for a third
+    of the time."""
     import oracle as O
     nth = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
     nth = max(1, min(nth, 16))
     chains = {name: O.stream_chain(O.GEN64[name], 1, batch) for name in SWEEP}
-    outs = 0
-    rounds = 0
-    t0 = time.perf_counter()
-    while True:
-        for name in SWEEP:
-            g = O.GEN64[name]
-            O.generate_many(g, chains[name], N, kind="u64", nthreads=nth)
-            O.generate_many(g, chains[name], N, kind="f64", nthreads=nth)
-            outs += 2 * batch * N
-        rounds += 1
-        if time.perf_counter() - t0 >= seconds:
-            break
-    dt = time.perf_counter() - t0
+
+    def run(threads: int, budget: float):
+        outs = rounds = 0
+        t0 = time.perf_counter()
+        while True:
+            for name in SWEEP:
+                g = O.GEN64[name]
+                O.generate_many(g, chains[name], N, kind="u64", nthreads=threads)
+                O.generate_many(g, chains[name], N, kind="f64", nthreads=threads)
+                outs += 2 * batch * N
+            rounds += 1
+            if time.perf_counter() - t0 >= budget:
+                break
+        return outs, rounds, time.perf_counter() - t0
+
+    outs, rounds, dt = run(nth, seconds)
+    outs1, rounds1, dt1 = run(1, seconds / 3)
     return {"value": outs / dt, "unit": "outputs/s", "cores": nth, "kind": "oracle",
             "sample": f"{rounds} round(s) of 8 generators x {batch} streams x {N} outputs x "
-                      f"(u64 + f64) from the seed-1 chains; {outs:.3g} outputs in {dt:.1f} s"}
+                      f"(u64 + f64) from the seed-1 chains; {outs:.3g} outputs in {dt:.1f} s",
+            "value_1thread": outs1 / dt1,
+            "sample_1thread": f"{rounds1} round(s) of the same on one thread; {outs1:.3g} outputs "
+                              f"in {dt1:.1f} s"}
 
 
 def batched_section(P, torch, stream, launches: int = 3) -> dict:
@@ -135,6 +145,34 @@ def batched_section(P, torch, stream, launches: int = 3) -> dict:
     del arena
     torch.cuda.empty_cache()
     return out
+
+
+def small_case_section(P, torch, stream, reps: int = 20) -> dict:
+    """The small case: xoshiro256**, 1,024 streams from seed 42 (stream i
+    jumped i times by 2^128), 4,096 uint64 outputs each (32 MiB).  Too small
+    to approach the HBM roof (about 4 us of writes at 8 TB/s): reported as
+    times, positioning included."""
+    name, seed, S, N = "xoshiro256**", 42, 1024, 4096
+    buf = torch.empty((S, N), dtype=torch.int64, device="cuda")
+    ev = lambda: torch.cuda.Event(enable_timing=True)  # noqa: E731
+    pos_ms = gen_ms = 0.0
+    with P.Streams(name, seed, S) as h:
+        for rep in range(reps + 1):
+            e = [ev() for _ in range(3)]
+            e[0].record(stream)
+            P.slrng_streams_seed(h.h, seed, stream)
+            e[1].record(stream)
+            P.slrng_generate(h.h, P.SLRNG_U64, N, buf.data_ptr(), N, stream)
+            e[2].record(stream)
+            torch.cuda.synchronize()
+            if rep:
+                pos_ms += e[0].elapsed_time(e[1]) / reps
+                gen_ms += e[1].elapsed_time(e[2]) / reps
+    del buf
+    torch.cuda.empty_cache()
+    return {"generator": name, "streams": S, "outputs_per_stream": N,
+            "position_us": round(pos_ms * 1e3, 2), "generate_us": round(gen_ms * 1e3, 2),
+            "generate_GBs": round(8 * S * N / (gen_ms * 1e-3) / 1e9, 1)}
 
 
 def positioning_section(P, torch, stream, reps: int = 5) -> dict:
@@ -392,6 +430,7 @@ def main():
         h.close()
     del buf_u, buf_f
     torch.cuda.empty_cache()
+    small = small_case_section(P, torch, stream)
     positioned = positioning_section(P, torch, stream)
     gen32 = gen32_section(P, torch, stream)
     lincomp = lincomp_section(P, torch, stream)
@@ -421,6 +460,7 @@ def main():
                      "traffic": profiled_traffic()},
         "write_ceiling_GBs": ceiling,
         "gen_GBs_per_generator": per_variant,
+        "small_case": small,
         "jump_ahead_at_scale": positioned,
         "generators_32bit": gen32,
         "linearity_check": lincomp,
