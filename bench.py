@@ -6,7 +6,9 @@ from a seed (SplitMix64 fill, stream i jumped i times by 2^(n/2)), generate
 65,536 uint64 outputs per stream (32 GiB, stream-major), re-position the same
 streams and generate the same outputs as [0,1) doubles (another 32 GiB).
 Step k uses seed (k mod 8) + 1, so 8 steps cover seeds 1..8.  Inputs are the
-seeds alone; all outputs stay in HBM.
+seeds alone; all outputs stay in HBM, in memory from the library's output
+allocator (slrng_output_alloc: physical pages spread over the HBM; the
+`placement` entry measures the same writes into compact memory beside it).
 
 Prints one JSON line (rank 0).  `value` = outputs (uint64 + double) per
 second over the timed steps; `roofline` describes the generation kernel
@@ -113,7 +115,7 @@ def batched_section(P, torch, stream, launches: int = 3) -> dict:
     import numpy as np
     from paper_1805_01407_amd import workloads as W
     w = W.batch_requests()
-    arena = torch.empty((w["arena_elems"],), dtype=torch.int64, device="cuda")
+    arena = P.output_empty((w["arena_elems"],), torch.int64)
     reqs = P.make_requests(w["variant"], w["kind"], w["seed"], w["start"], w["n"],
                            arena.data_ptr() + 8 * w["offset"])
     total = int(w["n"].sum())
@@ -144,6 +146,41 @@ def batched_section(P, torch, stream, launches: int = 3) -> dict:
                       "plan_ms": round(plan_ms, 1)}
     del arena
     torch.cuda.empty_cache()
+    return out
+
+
+def placement_section(P, torch, stream, S: int, N: int, reps: int = 3) -> dict:
+    """Store bandwidth against the physical placement of the output: the same
+    fill kernel and one generator (xoshiro256**, uint64) writing S x N words
+    into (a) the process's first large device allocation (torch.empty: one
+    compact physical range) and (b) memory from slrng_output_alloc (the same
+    virtual layout, physical pieces spread over the HBM).  Runs first, before
+    any other large allocation, so that (a) is compact."""
+    nbytes = 8 * S * N
+    out = {"bytes": nbytes}
+
+    def rate(ptr, fn):
+        fn(ptr)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            fn(ptr)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return round(nbytes * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9, 1)
+
+    with P.Streams("xoshiro256**", 1, S) as h:
+        for label, alloc in (("compact_first_allocation", lambda: torch.empty((S, N), dtype=torch.int64,
+                                                                               device="cuda")),
+                             ("output_alloc_spread", lambda: P.output_empty((S, N), torch.int64))):
+            buf = alloc()
+            out[label] = {
+                "fill_GBs": rate(buf.data_ptr(), lambda p: P.slrng_calib_write(p, nbytes, stream)),
+                "generate_GBs": rate(buf.data_ptr(),
+                                     lambda p: P.slrng_generate(h.h, P.SLRNG_U64, N, p, N, stream))}
+            del buf
+            torch.cuda.synchronize()
+            torch.cuda.empty_cache()
     return out
 
 
@@ -189,7 +226,7 @@ def positioning_section(P, torch, stream, reps: int = 5) -> dict:
     fp32 vector peak, an FMA counting as two).  The section also times the
     advance of every stream by its own random 128-bit distance."""
     name, seed, S, N = "xoshiro256++", 42, 1 << 20, 1024
-    buf = torch.empty((S, N), dtype=torch.int64, device="cuda")
+    buf = P.output_empty((S, N), torch.int64)
     ev = lambda: torch.cuda.Event(enable_timing=True)  # noqa: E731
     acc = {"position": 0.0, "long_jump": 0.0, "generate": 0.0, "advance_each": 0.0}
     # one random 128-bit distance per stream, for the per-stream advance
@@ -248,7 +285,7 @@ def gen32_section(P, torch, stream, rounds: int = 2) -> dict:
     upper 24 bits: 32 GiB per launch, the same bytes as a 64-bit sweep launch.
     HIP events around every launch; average write bandwidth per generator."""
     S, N = 65536, 131072
-    buf = torch.empty((S, N), dtype=torch.int32, device="cuda")
+    buf = P.output_empty((S, N), torch.int32)
     hs = {name: P.Streams(name, 1, S) for name in SWEEP32}
     per = {name: [] for name in SWEEP32}
     for r in range(rounds + 1):
@@ -364,9 +401,12 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     S, N = args.streams, args.n
-    buf_u = torch.empty((S, N), dtype=torch.int64, device=dev)
-    buf_f = torch.empty((S, N), dtype=torch.float64, device=dev)
     stream = torch.cuda.current_stream()
+    placement = placement_section(P, torch, stream, S, N)
+    # output memory from the library's allocator: virtually contiguous, its
+    # physical pages spread over the HBM (compact placement caps stores lower)
+    buf_u = P.output_empty((S, N), torch.int64)
+    buf_f = P.output_empty((S, N), torch.float64)
     hs = {name: P.Streams(name, 1, S) for name in SWEEP}
     torch.cuda.synchronize()
 
@@ -459,6 +499,7 @@ def main():
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": profiled_traffic()},
         "write_ceiling_GBs": ceiling,
+        "placement": placement,
         "gen_GBs_per_generator": per_variant,
         "small_case": small,
         "jump_ahead_at_scale": positioned,

@@ -207,6 +207,32 @@ int slrng_get_state(const slrng_streams *h, uint64_t *host_words, hipStream_t st
 int slrng_set_state(slrng_streams *h, const uint64_t *host_words, hipStream_t stream);
 int slrng_streams_destroy(slrng_streams *h);
 
+/* ---------------------------------------------------------------- output memory
+ *
+ * slrng_output_alloc: device memory for large outputs on the current device,
+ * virtually contiguous, with its physical backing spread over the HBM.  Not
+ * an operation of the generators: on MI355X the store bandwidth one buffer
+ * sees depends on how widely its physical pages are spread, and a large
+ * allocation that lands in one compact physical range caps streams of stores
+ * near 5.5 TB/s where the same bytes spread over about four times the span
+ * reach 6.5-6.9 TB/s.  From 1 GiB up the buffer is made of physical pieces of
+ * P = 256 MiB .. 1 GiB (a power of two near bytes / 64): gap x M pieces are
+ * created in order, every gap-th is kept and mapped back to back into one
+ * virtual range aligned to P, and the others are returned at once (gap = 4,
+ * lower when free memory is short: gap x M x P bytes are held only during the
+ * call).  Below 1 GiB it is a plain device allocation (256-byte aligned).
+ * The memory is uninitialised and usable like any device pointer (kernels,
+ * copies) on that device.  Synchronous.  EINVAL for bytes = 0 or a null
+ * dev_ptr, ENOMEM if the device cannot supply it, EHIP for other HIP errors.
+ * Thread-safe.
+ *
+ * slrng_output_free: frees memory from slrng_output_alloc.  It waits for the
+ * device to be idle first (unmapping memory that queued work still writes
+ * would fault).  NULL is a no-op; EINVAL for a pointer that
+ * slrng_output_alloc did not return (or already freed).  Thread-safe. */
+int slrng_output_alloc(uint64_t bytes, void **dev_ptr);
+int slrng_output_free(void *dev_ptr);
+
 /* ---------------------------------------------------------------- tuning
  *
  * Launch shape of slrng_generate per (variant, kind):

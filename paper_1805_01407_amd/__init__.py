@@ -17,6 +17,7 @@ from .binding import (  # noqa: F401
     slrng_streams_jump, slrng_streams_advance, slrng_streams_advance_each, slrng_generate, slrng_linear_complexity,
     slrng_get_state, slrng_set_state, slrng_streams_destroy,
     slrng_get_tuning, slrng_set_tuning, slrng_calib_write, slrng_calib_copy,
+    slrng_output_alloc, slrng_output_free, output_empty,
     SLRNG_U64, SLRNG_F64, SLRNG_U32, SLRNG_F32, SLRNG_JUMP, SLRNG_LONG_JUMP,
     SLRNG_BATCH_GRAPH, SLRNG_BATCH_PERSISTENT, SLRNG_BATCH_PLAIN, REQUEST_DTYPE, make_requests,
     slrng_batch_default_opts, slrng_batch_plan, slrng_batch_launch, slrng_batch_info,

@@ -144,6 +144,8 @@ def lib():
         "slrng_server_destroy": ([vp], i32),
         "slrng_calib_write": ([vp, u64, vp], i32),
         "slrng_calib_copy": ([vp, vp, u64, vp], i32),
+        "slrng_output_alloc": ([u64, ctypes.POINTER(vp)], i32),
+        "slrng_output_free": ([vp], i32),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -323,6 +325,55 @@ def slrng_calib_write(dev_out: int, nbytes: int, stream=None) -> None:
 
 def slrng_calib_copy(dev_dst: int, dev_src: int, nbytes: int, stream=None) -> None:
     _check(lib().slrng_calib_copy(dev_dst, dev_src, nbytes, _stream(stream)), "slrng_calib_copy")
+
+
+def slrng_output_alloc(nbytes: int) -> int:
+    """Device memory for large outputs (physical pages spread over the HBM
+    from 1 GiB up); returns the device address."""
+    p = ctypes.c_void_p()
+    _check(lib().slrng_output_alloc(nbytes, ctypes.byref(p)), "slrng_output_alloc")
+    return p.value
+
+
+def slrng_output_free(dev_ptr: int) -> None:
+    _check(lib().slrng_output_free(dev_ptr), "slrng_output_free")
+
+
+class _OutputMemory:
+    """One slrng_output_alloc block, exposed through the CUDA array interface
+    so that torch wraps it without a copy; freed when the last tensor on it
+    is gone."""
+
+    _TYPESTR = {"int64": "<i8", "float64": "<f8", "int32": "<i4", "float32": "<f4", "uint8": "|u1"}
+
+    def __init__(self, shape, dtype_name: str, itemsize: int):
+        n = 1
+        for s in shape:
+            n *= s
+        self.ptr = 0
+        self.ptr = slrng_output_alloc(max(n, 1) * itemsize)
+        self.__cuda_array_interface__ = {"shape": tuple(shape), "typestr": self._TYPESTR[dtype_name],
+                                         "data": (self.ptr, False), "version": 2, "strides": None}
+
+    def __del__(self):
+        if self.ptr and _lib is not None:
+            try:
+                _lib.slrng_output_free(self.ptr)
+            except Exception:  # interpreter shutdown
+                pass
+            self.ptr = 0
+
+
+def output_empty(shape, dtype=None):
+    """An uninitialised CUDA tensor on memory from slrng_output_alloc: the
+    layout of torch.empty(shape, dtype) (contiguous), with its physical pages
+    spread over the HBM for the store bandwidth of large outputs."""
+    import torch
+    dtype = torch.int64 if dtype is None else dtype
+    shape = tuple(int(s) for s in (shape if isinstance(shape, (tuple, list)) else (shape,)))
+    name = str(dtype).replace("torch.", "")
+    mem = _OutputMemory(shape, name, torch.empty((), dtype=dtype).element_size())
+    return torch.as_tensor(mem, device="cuda")
 
 
 _batch_defaults: dict = {}

@@ -59,6 +59,16 @@ def test_version_and_errors(P):
         [2, 2, 2, 4, 4, 4, 8, 8, 8, 16, 16, 16, 2, 16, 2, 2, 4, 4, 4]
 
 
+def test_output_memory_argument_errors(P):
+    # host-side checks only: no device memory is touched
+    L = P.lib()
+    p = ctypes.c_void_p(1234)
+    assert L.slrng_output_alloc(0, ctypes.byref(p)) == -1 and p.value is None  # EINVAL, *out cleared
+    assert L.slrng_output_alloc(1 << 20, None) == -1
+    assert L.slrng_output_free(None) == 0
+    assert L.slrng_output_free(ctypes.c_void_p(0x1000)) == -1  # not from slrng_output_alloc
+
+
 @pytest.mark.parametrize("name", list(O.GEN64))
 def test_charpoly_matches_oracle(P, name):
     assert P.slrng_charpoly(name) == O.charpoly(O.GEN64[name])

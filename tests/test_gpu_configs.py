@@ -1,9 +1,10 @@
 """GPU parity at the full sizes of the benchmark configurations, in the launch
 configuration bench.py times (default tuning), bit for bit against the oracle.
 
-* sweep: 65,536 streams x 65,536 outputs (32 GiB per kind) — xoshiro256**
-  compared in full (uint64 and doubles); xoroshiro1024** and xoroshiro128+ on
-  sampled rows plus every final state;
+* sweep: 65,536 streams x 65,536 outputs (32 GiB per kind, written into
+  memory from slrng_output_alloc as bench.py does) — xoshiro256** compared
+  in full (uint64 and doubles); xoroshiro1024** and xoroshiro128+ on sampled
+  rows plus every final state;
 * jump-ahead: 1,048,576 xoshiro256++ streams positioned by the jump chain,
   then long-jumped once: all states compared, then 1,024 outputs per stream
   (8 GiB) compared in full.
@@ -53,7 +54,7 @@ def test_sweep_full_size_xoshiro256ss_complete(P):
     g = O.GEN64[name]
     announce("sweep full", name, S, N)
     st0 = O.stream_chain(g, seed, S)
-    buf = torch.empty((S, N), dtype=torch.int64, device="cuda")
+    buf = P.output_empty((S, N), torch.int64)  # the memory bench.py writes into
     with P.Streams(name, seed, S) as h:
         assert np.array_equal(h.get_state(), st0)
         P.slrng_generate(h.h, P.SLRNG_U64, N, buf.data_ptr(), N, 0)
@@ -79,7 +80,7 @@ def test_sweep_full_size_sampled_rows(P, name):
     st0 = O.stream_chain(g, seed, S)
     rows = sorted({0, 1, 63, 64, 65, 1023, 1024, 4095, 32767, 65472, 65535} |
                   set(np.random.default_rng(0).integers(0, S, 8).tolist()))
-    buf = torch.empty((S, N), dtype=torch.int64, device="cuda")
+    buf = P.output_empty((S, N), torch.int64)
     with P.Streams(name, seed, S) as h:
         assert np.array_equal(h.get_state(), st0)
         for kind in (P.SLRNG_U64, P.SLRNG_F64):
