@@ -54,7 +54,7 @@ def tune_generate(variants, S=65536, N=65536, reps=5, quick=False, log=print) ->
     """64-bit generators: S x N outputs; 32-bit ones: S x 2N (the same bytes)."""
     import torch
     from . import binding as B
-    buf = torch.empty((S, N), dtype=torch.int64, device="cuda")
+    buf = B.output_empty((S, N), torch.int64)  # the memory large outputs live in
     out = {}
     waves = (4096, 8192) if quick else (2048, 4096, 8192, 16384)
     skews = (1, 4) if quick else (1, 4, 16)
@@ -90,7 +90,7 @@ def tune_batch(reps=5, quick=False, log=print) -> dict:
     from . import binding as B
     from . import workloads as W
     w = W.batch_requests()
-    arena = torch.empty((w["arena_elems"],), dtype=torch.int64, device="cuda")
+    arena = B.output_empty((w["arena_elems"],), torch.int64)
     reqs = B.make_requests(w["variant"], w["kind"], w["seed"], w["start"], w["n"],
                            arena.data_ptr() + 8 * w["offset"])
     total = int(w["n"].sum())

@@ -19,12 +19,17 @@ __device__ __forceinline__ void wave_sync() {
 }
 
 // Exact 53-bit double of the upper 53 bits: (x >> 11) * 2^-53 as
-// hi * 2^-21 + lo * 2^-53 with hi = x >> 43 (21 bits) and lo = bits 11..42;
-// both products are exact and so is their sum (53 significant bits).
+// hi * 2^-32 + lo * 2^-64 with hi = the upper word of x and lo = the lower
+// word with its low 11 bits cleared.  Both terms are exact (32-bit integers
+// scaled by powers of two) and their sum has at most 53 significant bits, so
+// the fused multiply-add rounds nothing; no 64-bit shift is needed.
 __device__ __forceinline__ u64 to_f64_bits(u64 x) {
-  const unsigned hi = (unsigned)(x >> 43);
-  const unsigned lo = (unsigned)(x >> 11);
-  const double d = __fma_rn((double)hi, 0x1p-21, (double)lo * 0x1p-53);
+  unsigned hi = (unsigned)(x >> 32);
+  // opaque to the optimiser, which would otherwise widen the conversion of
+  // hi to a 64-bit one (an extra f64 add); emits no instruction
+  asm("" : "+v"(hi));
+  const unsigned lo = (unsigned)x & 0xFFFFF800u;
+  const double d = __fma_rn((double)hi, 0x1p-32, (double)lo * 0x1p-64);
   return (u64)__double_as_longlong(d);
 }
 
