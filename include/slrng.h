@@ -220,7 +220,9 @@ int slrng_streams_destroy(slrng_streams *h);
  * created in order, every gap-th is kept and mapped back to back into one
  * virtual range aligned to P, and the others are returned at once (gap = 4,
  * lower when free memory is short: gap x M x P bytes are held only during the
- * call).  Below 1 GiB it is a plain device allocation (256-byte aligned).
+ * call).  Below 1 GiB, and on a device without the HIP virtual memory API
+ * or when the pieces cannot be mapped, it is a plain device allocation
+ * (256-byte aligned); placement changes speed only, never values.
  * The memory is uninitialised and usable like any device pointer (kernels,
  * copies) on that device.  Synchronous.  EINVAL for bytes = 0 or a null
  * dev_ptr, ENOMEM if the device cannot supply it, EHIP for other HIP errors.

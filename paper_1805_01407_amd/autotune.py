@@ -5,7 +5,10 @@ current torch stream) and keeps the fastest shape:
 
 * ``slrng_generate``, per variant and kind: LDS tile (16 or 32 outputs per lane
   per round), wave target (how finely short, wide requests are split into
-  jumped slots) and the number of staggered slot-boundary classes;
+  jumped slots) and the number of staggered slot-boundary classes, timed on
+  the 65,536 x 65,536 sweep; then the shortest slot (min_chunk), which only
+  matters when there are few streams, by the latency of a 1,024-stream
+  launch of 4,096 outputs per stream;
 * batched generation: LDS tile, persistent grid (waves per CU) and lane-chunk
   length per variant, on a seeded batched workload.
 
@@ -76,7 +79,19 @@ def tune_generate(variants, S=65536, N=65536, reps=5, quick=False, log=print) ->
                                 best = (ms, {"tile": tile, "target_waves": tw, "skew": sk,
                                              "min_chunk": 1024})
             gbs = 8 * S * N / (best[0] * 1e-3) / 1e9
-            log(f"generate {name} kind {kind}: {best[1]} {gbs:.0f} GB/s")
+            # shortest slot: latency of a small launch (the sweep's slots are
+            # far longer than any candidate, so its timing does not change)
+            cfg = best[1]
+            small_n = 2 * 4096 if w32 else 4096
+            with B.Streams(name, 1, 1024) as h:
+                lat = []
+                for mc in (256, 512, 1024):
+                    B.slrng_set_tuning(name, kind, cfg["tile"], cfg["target_waves"], mc, cfg["skew"])
+                    lat.append((_time_ms(lambda: B.slrng_generate(h.h, kind, small_n, buf.data_ptr(),
+                                                                  small_n), reps), mc))
+            cfg["min_chunk"] = min(lat)[1]
+            log(f"generate {name} kind {kind}: {best[1]} {gbs:.0f} GB/s; 1,024 streams: "
+                f"{min(lat)[0] * 1e3:.1f} us")
             out[f"{name}/{kind}"] = dict(best[1], GBs=round(gbs, 1))
             B.slrng_set_tuning(name, kind, **{k: best[1][k] for k in
                                               ("tile", "target_waves", "min_chunk", "skew")})

@@ -18,7 +18,9 @@
 //     gap x M x P bytes are held only during the call);
 //   * the kept pieces are mapped back to back into one reserved virtual range
 //     aligned to P, read-write for the current device.
-// Requests below 1 GiB are a plain device allocation.
+// Requests below 1 GiB are a plain device allocation, and so is any request
+// on a device without the virtual memory API or whose pieces cannot be mapped
+// (placement changes speed only, never values).
 #include <hip/hip_runtime_api.h>
 #include <stdint.h>
 
@@ -120,38 +122,57 @@ hipError_t map_pieces(int dev, uint64_t P, std::vector<hipMemGenericAllocationHa
   return hipSuccess;
 }
 
+// Spread placement for `bytes` on device `dev` (hipErrorNotSupported when
+// the device has no virtual memory API).
+hipError_t spread_pieces(int dev, uint64_t bytes, Block &b, void **out) {
+  int vmm = 0;
+  hipError_t e = hipDeviceGetAttribute(&vmm, hipDeviceAttributeVirtualMemoryManagementSupported, dev);
+  if (e != hipSuccess) return e;
+  if (!vmm) return hipErrorNotSupported;
+  const uint64_t P = piece_bytes(bytes);
+  const uint64_t M = (bytes + P - 1) / P;
+  size_t free_b = 0, total_b = 0;
+  e = hipMemGetInfo(&free_b, &total_b);
+  if (e != hipSuccess) return e;
+  const uint64_t usable = free_b > kFreeMargin ? free_b - kFreeMargin : 0;
+  int gap = (int)std::min<uint64_t>(kMaxGap, usable / (M * P));
+  if (gap < 1) gap = 1;
+  for (;; gap--) {
+    e = take_pieces(dev, P, M, gap, b.pieces);
+    if (e == hipSuccess || gap == 1) break;
+  }
+  if (e != hipSuccess) return e;
+  e = map_pieces(dev, P, b.pieces, out);
+  if (e != hipSuccess) {
+    release_all(b.pieces);
+    return e;
+  }
+  b.spread = true;
+  b.reserved = M * P;
+  return hipSuccess;
+}
+
 }  // namespace
 
 hipError_t spread_alloc(uint64_t bytes, void **out) {
   *out = nullptr;
   Block b;
-  if (bytes < kSpreadMin) {
-    hipError_t e = hipMalloc(out, bytes);
-    if (e != hipSuccess) return e;
-  } else {
+  hipError_t e = hipErrorNotSupported;
+  if (bytes >= kSpreadMin) {
     int dev = 0;
-    hipError_t e = hipGetDevice(&dev);
+    e = hipGetDevice(&dev);
     if (e != hipSuccess) return e;
-    const uint64_t P = piece_bytes(bytes);
-    const uint64_t M = (bytes + P - 1) / P;
-    size_t free_b = 0, total_b = 0;
-    e = hipMemGetInfo(&free_b, &total_b);
-    if (e != hipSuccess) return e;
-    const uint64_t usable = free_b > kFreeMargin ? free_b - kFreeMargin : 0;
-    int gap = (int)std::min<uint64_t>(kMaxGap, usable / (M * P));
-    if (gap < 1) gap = 1;
-    for (;; gap--) {
-      e = take_pieces(dev, P, M, gap, b.pieces);
-      if (e == hipSuccess || gap == 1) break;
+    e = spread_pieces(dev, bytes, b, out);
+    if (e == hipErrorOutOfMemory) return e;
+    if (e != hipSuccess) {  // no virtual memory API, or a mapping failed
+      (void)hipGetLastError();
+      b = Block();
+      *out = nullptr;
     }
+  }
+  if (e != hipSuccess) {
+    e = hipMalloc(out, bytes);
     if (e != hipSuccess) return e;
-    e = map_pieces(dev, P, b.pieces, out);
-    if (e != hipSuccess) {
-      release_all(b.pieces);
-      return e;
-    }
-    b.spread = true;
-    b.reserved = M * P;
   }
   std::lock_guard<std::mutex> g(g_mu);
   g_blocks.emplace(*out, std::move(b));
