@@ -15,10 +15,11 @@ second over the timed steps; `roofline` describes the generation kernel
 (HIP events around each launch; `traffic` from the committed HBM counters).
 The same line carries the other workloads, each run once after the sweep:
 the small case (1,024 streams), jump-ahead at scale (2^20 streams), the
-32-bit generators, the on-device
-linearity check, the batched-requests workload (one graph launch against one
-launch per request), the serving trace (continuous batching against the
-plain form) and the CPU oracle on a bounded sample (`cpu_baseline`).
+32-bit generators, the on-device linearity check, the batched-requests
+workload (one graph launch against one launch per request), the serving
+trace (continuous batching against the plain form) and the CPU oracle on a
+bounded sample (`cpu_baseline`; its `per_config` entry times the oracle on
+samples of the other workloads, on one thread and on all).
 """
 from __future__ import annotations
 
@@ -104,6 +105,76 @@ def cpu_baseline(batch: int, N: int, seconds: float = 15.0) -> dict:
             "value_1thread": outs1 / dt1,
             "sample_1thread": f"{rounds1} round(s) of the same on one thread; {outs1:.3g} outputs "
                               f"in {dt1:.1f} s"}
+
+
+def cpu_per_config(budget: float = 3.0) -> dict:
+    """The oracle on the other configurations, each on a bounded sample, on
+    one host thread and on all of them (at most 16): the small case in full;
+    jump-ahead at scale on the first 2^14 of its 2^20 streams (the stream
+    chain is serial by definition; the long jumps and the outputs are
+    threaded over streams); the batched requests in list order until
+    `budget` seconds of host time, threaded over requests."""
+    import numpy as np
+    from concurrent.futures import ThreadPoolExecutor
+
+    import oracle as O
+    from paper_1805_01407_amd import workloads as W
+    from paper_1805_01407_amd.binding import VARIANT_IDS
+    nth = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    nth = max(1, min(nth, 16))
+    out = {"cores": nth}
+
+    g = O.GEN64["xoshiro256**"]
+    t0 = time.perf_counter()
+    st = O.stream_chain(g, 42, 1024)
+    t_chain = time.perf_counter() - t0
+    small = {"streams": 1024, "outputs_per_stream": 4096, "position_ms": round(t_chain * 1e3, 2)}
+    for label, th in (("1thread", 1), ("all", nth)):
+        t0 = time.perf_counter()
+        O.generate_many(g, st, 4096, kind="u64", nthreads=th)
+        small[f"generate_ms_{label}"] = round((time.perf_counter() - t0) * 1e3, 2)
+    out["small_case"] = small
+
+    g = O.GEN64["xoshiro256++"]
+    S = 1 << 14
+    t0 = time.perf_counter()
+    chain = O.stream_chain(g, 42, S)
+    t_chain = time.perf_counter() - t0
+    jump = {"streams_sampled": S, "chain_streams_per_s": S / t_chain}
+    J = O.jump_distance(g, "long")
+    for label, th in (("1thread", 1), ("all", nth)):
+        t0 = time.perf_counter()
+        lj = O.jump_many(g, chain, J, nthreads=th)
+        jump[f"long_jumps_per_s_{label}"] = S / (time.perf_counter() - t0)
+        t0 = time.perf_counter()
+        O.generate_many(g, lj, 1024, kind="u64", nthreads=th)
+        jump[f"outputs_per_s_{label}"] = S * 1024 / (time.perf_counter() - t0)
+    out["jump_ahead_at_scale"] = jump
+
+    w = W.batch_requests()
+    gens = {v: O.GEN64[name] for name, v in VARIANT_IDS.items() if name in O.GEN64}
+
+    def one(r):
+        gr = gens[int(w["variant"][r])]
+        x = O.seed_state(gr, int(w["seed"][r]))
+        O.generate_many(gr, x.reshape(1, -1), int(w["n"][r]), kind="f64" if w["kind"][r] else "u64",
+                        nthreads=1)
+        return int(w["n"][r])
+
+    batched = {}
+    for label, th in (("1thread", 1), ("all", nth)):
+        done = r = 0
+        t0 = time.perf_counter()
+        with ThreadPoolExecutor(max_workers=th) as ex:
+            while time.perf_counter() - t0 < budget and r < len(w["n"]):
+                step = th * 4
+                done += sum(ex.map(one, range(r, min(r + step, len(w["n"])))))
+                r += step
+        dt = time.perf_counter() - t0
+        batched[f"outputs_per_s_{label}"] = done / dt
+        batched[f"requests_{label}"] = min(r, len(w["n"]))
+    out["batched_requests"] = batched
+    return out
 
 
 def batched_section(P, torch, stream, launches: int = 3) -> dict:
@@ -478,6 +549,8 @@ def main():
     served = None if args.serve_seconds <= 0 else serving_section(P, args.serve_seconds)
 
     cpu = None if args.no_cpu else cpu_baseline(args.cpu_streams, N, args.cpu_seconds)
+    if cpu is not None:
+        cpu["per_config"] = cpu_per_config()
 
     out = {
         "metric": "64-bit outputs/s (uint64 + [0,1) doubles), full family sweep",

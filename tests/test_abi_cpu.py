@@ -225,6 +225,21 @@ def test_bench_refuses_more_than_one_gpu():
     assert r.returncode == 2 and "one GPU" in r.stderr
 
 
+def test_bench_oracle_baselines_per_config():
+    # the host-only part of bench.py: the oracle timed on samples of the
+    # small case, jump-ahead and batched workloads
+    import sys
+    sys.path.insert(0, ROOT)
+    import bench
+    r = bench.cpu_per_config(budget=0.2)
+    assert r["cores"] >= 1
+    assert r["small_case"]["generate_ms_1thread"] > 0 and r["small_case"]["generate_ms_all"] > 0
+    j = r["jump_ahead_at_scale"]
+    assert j["chain_streams_per_s"] > 0 and j["long_jumps_per_s_all"] > 0 and j["outputs_per_s_all"] > 0
+    b = r["batched_requests"]
+    assert b["requests_1thread"] >= 1 and b["outputs_per_s_all"] > 0
+
+
 def test_plain_c_program_uses_the_abi(tmp_path):
     """A C program compiled against include/slrng.h and linked with
     libslrng.so (no Python in between) gets the same polynomials as the
