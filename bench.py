@@ -385,10 +385,13 @@ def gen32_section(P, torch, stream, rounds: int = 2) -> dict:
 
 
 def lincomp_section(P, torch, stream, reps: int = 3) -> dict:
-    """On-device linearity check: Berlekamp-Massey on bit 0 of 2n outputs of
+    """On-device linearity checks: Berlekamp-Massey on bit 0 of 2n outputs of
     each of 65,536 xoshiro256+ streams (complexity n = 256 expected, table
-    tab:plusdeg).  Reports the time per check and the streams checked per
-    second."""
+    tab:plusdeg), with the time per check and the streams checked per second;
+    then the maximum-dimension equidistribution test of Section
+    "Equidistribution" (the rank of an n x n matrix over Z/2Z, one
+    workgroup) for every word of xoroshiro1024 (n = 1,024) and of
+    xoshiro256, with the time per word."""
     name, S, nbits = "xoshiro256+", 65536, 512
     with P.Streams(name, 1, S) as h:
         h.linear_complexity(0, nbits, stream)
@@ -401,8 +404,23 @@ def lincomp_section(P, torch, stream, reps: int = 3) -> dict:
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1) / reps
         ok = bool((lc == 256).all().item())
-    return {"generator": name, "streams": S, "bit": 0, "nbits": nbits, "ms": round(ms, 3),
-            "streams_per_s": S / (ms * 1e-3), "all_equal_n": ok}
+    out = {"generator": name, "streams": S, "bit": 0, "nbits": nbits, "ms": round(ms, 3),
+           "streams_per_s": S / (ms * 1e-3), "all_equal_n": ok}
+    ed = {}
+    for gen, k, n in (("xoroshiro1024+", 16, 1024), ("xoshiro256+", 4, 256)):
+        ranks = torch.zeros(k, dtype=torch.int32, device="cuda")
+        P.slrng_equidistribution_rank(gen, 0, k, ranks.data_ptr(), stream)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for word in range(k):
+            P.slrng_equidistribution_rank(gen, word, k, ranks.data_ptr() + 4 * word, stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ed[gen] = {"n": n, "ms_per_word": round(e0.elapsed_time(e1) / k, 3),
+                   "all_words_full_rank": bool((ranks == n).all().item())}
+    out["equidistribution_rank"] = ed
+    return out
 
 
 def serving_section(P, seconds: float) -> dict:

@@ -201,6 +201,28 @@ int slrng_streams_advance_each(slrng_streams *h, const uint64_t *dev_steps, hipS
  * device memory, 4-byte aligned, S uint32.  Asynchronous.  EINVAL otherwise. */
 int slrng_linear_complexity(const slrng_streams *h, int bit, uint32_t nbits, uint32_t *dev_lc,
                             hipStream_t stream);
+
+/* slrng_equidistribution_rank: the test of Section "Equidistribution" for
+ * one word of a linear engine, on the device.  For the engine of `variant`
+ * (the scrambler plays no part; n = k w state bits), *dev_rank = the rank
+ * over Z/2Z of the n x (dims w) matrix whose row i holds word `word` of
+ * e_i M^0, e_i M^1, ..., e_i M^(dims-1), with e_i the state whose only set
+ * bit is bit i (logical word order; the columns of M^t that belong to that
+ * word, juxtaposed).  With dims = k the word is equidistributed in the
+ * maximum dimension exactly when the rank is n (the matrix is invertible);
+ * for dims < k, d-dimensionally equidistributed exactly when it is dims w.
+ * word in [0, k), dims in [1, k]; dev_rank: device memory, 4-byte aligned,
+ * one uint32.  One workgroup; asynchronous.  EINVAL otherwise.
+ *
+ * slrng_gf2_rank: the Gaussian elimination over Z/2Z behind it, on a
+ * caller's matrix: nrows and ncols in [1, 1024]; dev_rows: device memory,
+ * 8-byte aligned, row r in words r * ceil(ncols/64) .. + ceil(ncols/64) - 1,
+ * bit b of word q = column 64 q + b (bits past ncols are ignored);
+ * *dev_rank = the rank.  Asynchronous.  EINVAL otherwise. */
+int slrng_equidistribution_rank(int variant, int word, int dims, uint32_t *dev_rank,
+                                hipStream_t stream);
+int slrng_gf2_rank(const uint64_t *dev_rows, uint32_t nrows, uint32_t ncols, uint32_t *dev_rank,
+                   hipStream_t stream);
 int slrng_generate(slrng_streams *h, int kind, uint64_t n, void *dev_out, uint64_t ld,
                    hipStream_t stream);
 int slrng_get_state(const slrng_streams *h, uint64_t *host_words, hipStream_t stream);

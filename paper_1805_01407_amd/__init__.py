@@ -15,6 +15,7 @@ from .binding import (  # noqa: F401
     slrng_streams_create, slrng_streams_create_from_states, slrng_streams_count,
     slrng_streams_variant, slrng_streams_seed,
     slrng_streams_jump, slrng_streams_advance, slrng_streams_advance_each, slrng_generate, slrng_linear_complexity,
+    slrng_equidistribution_rank, slrng_gf2_rank, equidistribution_rank, gf2_rank,
     slrng_get_state, slrng_set_state, slrng_streams_destroy,
     slrng_get_tuning, slrng_set_tuning, slrng_calib_write, slrng_calib_copy,
     slrng_output_alloc, slrng_output_free, output_empty,

@@ -117,6 +117,8 @@ def lib():
         "slrng_streams_advance": ([vp, u64, u64, vp], i32),
         "slrng_streams_advance_each": ([vp, vp, vp], i32),
         "slrng_linear_complexity": ([vp, i32, ctypes.c_uint32, vp, vp], i32),
+        "slrng_equidistribution_rank": ([i32, i32, i32, vp, vp], i32),
+        "slrng_gf2_rank": ([vp, ctypes.c_uint32, ctypes.c_uint32, vp, vp], i32),
         "slrng_generate": ([vp, i32, u64, vp, u64, vp], i32),
         "slrng_get_state": ([vp, u64p, vp], i32),
         "slrng_set_state": ([vp, u64p, vp], i32),
@@ -282,6 +284,43 @@ def slrng_linear_complexity(h: int, bit: int, nbits: int, dev_lc: int, stream=No
     """dev_lc: device address of S uint32 results."""
     _check(lib().slrng_linear_complexity(h, bit, nbits, dev_lc, _stream(stream)),
            "slrng_linear_complexity")
+
+
+def slrng_equidistribution_rank(variant, word: int, dims: int, dev_rank: int, stream=None) -> None:
+    """dev_rank: device address of one uint32 result."""
+    _check(lib().slrng_equidistribution_rank(_variant(variant), word, dims, dev_rank, _stream(stream)),
+           "slrng_equidistribution_rank")
+
+
+def slrng_gf2_rank(dev_rows: int, nrows: int, ncols: int, dev_rank: int, stream=None) -> None:
+    _check(lib().slrng_gf2_rank(dev_rows, nrows, ncols, dev_rank, _stream(stream)), "slrng_gf2_rank")
+
+
+def equidistribution_rank(variant, word: int, dims: int | None = None) -> int:
+    """The rank of slrng_equidistribution_rank as a Python int (dims defaults
+    to k, the maximum dimension); synchronises the current stream."""
+    import torch
+    if dims is None:
+        dims = slrng_state_words(variant)
+    out = torch.zeros(1, dtype=torch.int32, device="cuda")
+    slrng_equidistribution_rank(variant, word, dims, out.data_ptr())
+    return int(out.item())
+
+
+def gf2_rank(bits) -> int:
+    """Rank over Z/2Z of a 0/1 matrix (nrows x ncols, both <= 1024), packed
+    into the row layout of slrng_gf2_rank; synchronises the current stream."""
+    import torch
+    a = np.asarray(bits, dtype=np.uint8) & 1
+    nrows, ncols = a.shape
+    nw = (ncols + 63) // 64
+    padded = np.zeros((nrows, nw * 64), dtype=np.uint8)
+    padded[:, :ncols] = a
+    words = np.packbits(padded, axis=1, bitorder="little").view("<u8").reshape(nrows, nw)
+    dev = torch.from_numpy(np.ascontiguousarray(words).view(np.int64)).cuda()
+    out = torch.zeros(1, dtype=torch.int32, device="cuda")
+    slrng_gf2_rank(dev.data_ptr(), nrows, ncols, out.data_ptr())
+    return int(out.item())
 
 
 def slrng_generate(h: int, kind: int, n: int, dev_out: int, ld: int, stream=None) -> None:

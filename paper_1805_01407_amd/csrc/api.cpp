@@ -543,6 +543,28 @@ extern "C" int slrng_linear_complexity(const slrng_streams *h, int bit, uint32_t
   });
 }
 
+extern "C" int slrng_equidistribution_rank(int variant, int word, int dims, uint32_t *dev_rank,
+                                           hipStream_t stream) {
+  return guarded([&]() -> int {
+    if (!valid_variant(variant) || !dev_rank || ((uintptr_t)dev_rank & 3)) return SLRNG_EINVAL;
+    const int k = variant_words(variant);
+    if (word < 0 || word >= k || dims < 1 || dims > k) return SLRNG_EINVAL;
+    hipError_t e = launch_equidist_rank(variant, word, dims, dev_rank, stream);
+    return e == hipSuccess ? SLRNG_OK : hip_fail(e);
+  });
+}
+
+extern "C" int slrng_gf2_rank(const uint64_t *dev_rows, uint32_t nrows, uint32_t ncols,
+                              uint32_t *dev_rank, hipStream_t stream) {
+  return guarded([&]() -> int {
+    if (!dev_rows || ((uintptr_t)dev_rows & 7) || !dev_rank || ((uintptr_t)dev_rank & 3))
+      return SLRNG_EINVAL;
+    if (nrows < 1 || nrows > 1024 || ncols < 1 || ncols > 1024) return SLRNG_EINVAL;
+    hipError_t e = launch_gf2_rank(dev_rows, nrows, ncols, dev_rank, stream);
+    return e == hipSuccess ? SLRNG_OK : hip_fail(e);
+  });
+}
+
 extern "C" int slrng_generate(slrng_streams *h, int kind, uint64_t n, void *dev_out, uint64_t ld,
                               hipStream_t stream) {
   return guarded([&]() -> int {

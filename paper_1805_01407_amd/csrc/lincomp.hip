@@ -127,6 +127,122 @@ __global__ __launch_bounds__(kWave) void k_lincomp(const u64 *__restrict__ state
   if (live) out[i] = L;
 }
 
+// ---------------------------------------------------------------- rank over Z/2Z
+//
+// Gaussian elimination of an nrows x ncols bit matrix (both <= 1024) held in
+// LDS by one workgroup of 1024 threads, one row per thread.  Storage is
+// word-major, rows[q * nrows + r] = columns 64q .. 64q+63 of row r (bit b =
+// column 64q + b), so the threads of a wave touch consecutive words.  For each
+// column: the lowest unused row with that bit set is the pivot (one ballot per
+// wave, an LDS atomic minimum across waves); every other unused row with the
+// bit set adds the pivot row.  The rank is the number of pivots.  Two
+// barriers per column; the pivot slot alternates between two LDS words so
+// that clearing the next one needs no third.
+__device__ unsigned eliminate(u64 *rows, unsigned nrows, unsigned ncols, unsigned *piv) {
+  const unsigned tid = threadIdx.x;
+  const unsigned lane = tid % kWave;
+  const unsigned nwords = (ncols + 63) / 64;
+  bool used = tid >= nrows;  // threads past the last row never take part
+  unsigned rank = 0;
+  if (tid == 0) {
+    piv[0] = nrows;
+    piv[1] = nrows;
+  }
+  __syncthreads();
+  for (unsigned c = 0; c < ncols; c++) {
+    const unsigned q = c / 64, b = c % 64;
+    const bool cand = !used && ((rows[q * nrows + tid] >> b) & 1);
+    const u64 mask = __ballot(cand);
+    if (mask && lane == 0) atomicMin(&piv[c & 1], tid + (unsigned)__builtin_ctzll(mask));
+    if (tid == 0) piv[(c + 1) & 1] = nrows;
+    __syncthreads();
+    const unsigned p = piv[c & 1];
+    if (p < nrows) {
+      rank++;
+      if (tid == p) used = true;
+      else if (cand) {
+        for (unsigned w = q; w < nwords; w++) rows[w * nrows + tid] ^= rows[w * nrows + p];
+      }
+    }
+    __syncthreads();
+  }
+  return rank;
+}
+
+constexpr unsigned kRankMax = 1024;  // rows and columns
+
+__global__ __launch_bounds__(kRankMax) void k_gf2_rank(const u64 *__restrict__ in, unsigned nrows,
+                                                       unsigned ncols, unsigned *__restrict__ out) {
+  __shared__ u64 rows[kRankMax * (kRankMax / 64)];
+  __shared__ unsigned piv[2];
+  const unsigned tid = threadIdx.x;
+  const unsigned nwords = (ncols + 63) / 64;
+  if (tid < nrows)
+    for (unsigned w = 0; w < nwords; w++) rows[w * nrows + tid] = in[(u64)tid * nwords + w];
+  // columns past ncols in the last word are ignored by eliminate()
+  const unsigned r = eliminate(rows, nrows, ncols, piv);
+  if (tid == 0) *out = r;
+}
+
+// Row i of the equidistribution matrix: word `word` of e_i M^t for t < dims
+// (e_i = the state with logical bit i set: word i / w, bit i % w), word t at
+// columns t w .. t w + w - 1.
+template <int V>
+__device__ void equidist_row64(u64 *rows, unsigned n, int word, int dims) {
+  constexpr int K = Params<V>::k;
+  const unsigned i = threadIdx.x;
+  u64 s[K];
+#pragma unroll
+  for (int w = 0; w < K; w++) s[w] = (unsigned)w == i / 64 ? (1ull << (i % 64)) : 0ull;
+  for (int t = 0; t < dims; t++) {
+    u64 x = 0;
+#pragma unroll
+    for (int w = 0; w < K; w++)
+      if (w == word) x = s[w];
+    rows[(unsigned)t * n + i] = x;
+    step<V, 0>(s);
+    if constexpr (K == 16) rotate_to_logical<V>(s, 1);  // back to logical order
+  }
+}
+
+template <int V>
+__device__ void equidist_row32(u64 *rows, unsigned n, int word, int dims) {
+  constexpr int K = Params32<V>::k;
+  const unsigned i = threadIdx.x;
+  u32 s[K];
+#pragma unroll
+  for (int w = 0; w < K; w++) s[w] = (unsigned)w == i / 32 ? (1u << (i % 32)) : 0u;
+  const unsigned nwords = ((unsigned)dims * 32 + 63) / 64;
+  for (unsigned q = 0; q < nwords; q++) rows[q * n + i] = 0;
+  for (int t = 0; t < dims; t++) {
+    u32 x = 0;
+#pragma unroll
+    for (int w = 0; w < K; w++)
+      if (w == word) x = s[w];
+    rows[(unsigned)(t / 2) * n + i] |= (u64)x << (32 * (t % 2));
+    step32<V>(s);
+  }
+}
+
+template <int V, bool W32>
+constexpr unsigned state_bits() {
+  if constexpr (W32) return 32u * Params32<V>::k;
+  else return 64u * Params<V>::k;
+}
+
+template <int V, bool W32>
+__global__ __launch_bounds__(kRankMax) void k_equidist_rank(int word, int dims, unsigned *__restrict__ out) {
+  __shared__ u64 rows[kRankMax * (kRankMax / 64)];
+  __shared__ unsigned piv[2];
+  constexpr unsigned n = state_bits<V, W32>();
+  if (threadIdx.x < n) {
+    if constexpr (W32) equidist_row32<V>(rows, n, word, dims);
+    else equidist_row64<V>(rows, n, word, dims);
+  }
+  const unsigned r = eliminate(rows, n, (unsigned)dims * (W32 ? 32u : 64u), piv);
+  if (threadIdx.x == 0) *out = r;
+}
+
 #define SL_DISPATCH_ALL(v, EXPR64, EXPR32) \
   switch (v) {                             \
     case 0: return EXPR64(0);              \
@@ -168,6 +284,26 @@ hipError_t launch_lincomp(int variant, const uint64_t *state, uint64_t S, int bi
   SL_DISPATCH_ALL(variant, SL_LC64, SL_LC32)
 #undef SL_LC64
 #undef SL_LC32
+}
+
+hipError_t launch_gf2_rank(const uint64_t *rows, unsigned nrows, unsigned ncols, unsigned *out,
+                           hipStream_t st) {
+  hipLaunchKernelGGL(k_gf2_rank, dim3(1), dim3(kRankMax), 0, st, rows, nrows, ncols, out);
+  return hipGetLastError();
+}
+
+template <int V, bool W32>
+static hipError_t equidist_v(int word, int dims, unsigned *out, hipStream_t st) {
+  hipLaunchKernelGGL((k_equidist_rank<V, W32>), dim3(1), dim3(kRankMax), 0, st, word, dims, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_equidist_rank(int variant, int word, int dims, unsigned *out, hipStream_t st) {
+#define SL_ED64(V) equidist_v<V, false>(word, dims, out, st)
+#define SL_ED32(V) equidist_v<V, true>(word, dims, out, st)
+  SL_DISPATCH_ALL(variant, SL_ED64, SL_ED32)
+#undef SL_ED64
+#undef SL_ED32
 }
 
 }  // namespace slrng

@@ -17,4 +17,15 @@ inline unsigned lincomp_words(unsigned nbits) { return nbits / 32 + 4; }
 hipError_t launch_lincomp(int variant, const uint64_t *state, uint64_t S, int bit, unsigned nbits,
                           unsigned *out, hipStream_t st);
 
+// Rank over Z/2Z of an nrows x ncols bit matrix (both in [1, 1024]); row r
+// at rows[r * ceil(ncols / 64) + q], bit b = column 64 q + b.  One
+// workgroup; *out on the device.
+hipError_t launch_gf2_rank(const uint64_t *rows, unsigned nrows, unsigned ncols, unsigned *out,
+                           hipStream_t st);
+
+// Rank of the equidistribution matrix of one engine word: rows e_i (i < n),
+// columns word `word` of e_i M^t for t < dims (the engine of `variant`,
+// logical word order; word < k, 1 <= dims <= k).
+hipError_t launch_equidist_rank(int variant, int word, int dims, unsigned *out, hipStream_t st);
+
 }  // namespace slrng

@@ -59,6 +59,22 @@ def test_version_and_errors(P):
         [2, 2, 2, 4, 4, 4, 8, 8, 8, 16, 16, 16, 2, 16, 2, 2, 4, 4, 4]
 
 
+def test_rank_argument_errors(P):
+    # host-side checks only: every call below is rejected before any launch
+    L = P.lib()
+    fake = ctypes.c_void_p(0x1000)  # never dereferenced
+    bad = [(99, 0, 1), (-1, 0, 1), (0, -1, 1), (0, 2, 1), (0, 0, 0), (0, 0, 3),  # xoroshiro128: k = 2
+           (9, 16, 1), (9, 0, 17), (14, 2, 1), (16, 0, 5)]                     # k = 16, 2, 4
+    for v, word, dims in bad:
+        assert L.slrng_equidistribution_rank(v, word, dims, fake, None) == -1, (v, word, dims)
+    assert L.slrng_equidistribution_rank(0, 0, 1, None, None) == -1
+    assert L.slrng_equidistribution_rank(0, 0, 1, ctypes.c_void_p(0x1002), None) == -1  # misaligned
+    for nrows, ncols in ((0, 1), (1, 0), (1025, 1), (1, 1025)):
+        assert L.slrng_gf2_rank(fake, nrows, ncols, fake, None) == -1
+    assert L.slrng_gf2_rank(None, 1, 1, fake, None) == -1
+    assert L.slrng_gf2_rank(ctypes.c_void_p(0x1004), 1, 1, fake, None) == -1  # rows misaligned
+
+
 def test_output_memory_argument_errors(P):
     # host-side checks only: no device memory is touched
     L = P.lib()
