@@ -37,7 +37,6 @@
 #include "batch.hpp"
 #include "batch_plan.hpp"
 #include "kernels.hpp"
-#include "memory.hpp"
 
 using namespace slrng;
 
@@ -453,7 +452,7 @@ static void destroy_server(slrng_server *sv) {
     free_slot(s);
   }
   if (sv->ref) (void)hipEventDestroy(sv->ref);
-  if (sv->arena_dev) (void)spread_free(sv->arena_dev);
+  if (sv->arena_dev) (void)hipFree(sv->arena_dev);
   if (sv->basis) (void)hipFree(sv->basis);
   if (sv->streams) slrng_streams_destroy(sv->streams);
   delete sv;
@@ -512,8 +511,10 @@ extern "C" int slrng_server_create(const slrng_server_opts *opts, slrng_server *
       if (e != hipSuccess) rc = hip_fail(e);
     }
     if (!rc) {
-      // physical pieces spread over the HBM for the arena's store bandwidth
-      e = spread_alloc(o.budget_bytes, reinterpret_cast<void **>(&sv->arena_dev));
+      // a plain allocation: served iterations are latency-bound, and spreading
+      // the arena's physical pages (slrng_output_alloc) measured no faster
+      // while holding four times the budget during creation
+      e = hipMalloc(&sv->arena_dev, o.budget_bytes);
       if (e != hipSuccess) rc = e == hipErrorOutOfMemory ? SLRNG_ENOMEM : hip_fail(e);
     }
     if (!rc) {
