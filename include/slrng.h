@@ -269,14 +269,19 @@ int slrng_output_free(void *dev_ptr);
  *                chunks at different offsets, which spreads concurrent stores
  *                over the memory channels when the row stride is a power of
  *                two); 1 = no stagger;
- *  min_chunk     no chunk shorter than this many outputs.
+ *  min_chunk     no chunk shorter than this many outputs;
+ *  store         0: plain (write-back) output stores; 1: nontemporal ones
+ *                (on the 16-byte aligned path).  Which is faster depends on
+ *                the physical placement of the output (compact memory:
+ *                plain; slrng_output_alloc memory: nontemporal, as measured
+ *                on MI355X).
  * The launch shape never changes the values produced.  Values outside the
  * accepted range give EINVAL. */
 typedef struct slrng_tuning {
   int32_t tile;
   int32_t target_waves;
   int32_t skew;
-  int32_t reserved; /* 0 */
+  int32_t store;    /* output stores: 0 plain (write-back), 1 nontemporal */
   uint64_t min_chunk;
 } slrng_tuning;
 

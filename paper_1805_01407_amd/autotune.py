@@ -6,7 +6,8 @@ current torch stream) and keeps the fastest shape:
 * ``slrng_generate``, per variant and kind: LDS tile (16 or 32 outputs per lane
   per round), wave target (how finely short, wide requests are split into
   jumped slots) and the number of staggered slot-boundary classes, timed on
-  the 65,536 x 65,536 sweep; then the shortest slot (min_chunk), which only
+  the 65,536 x 65,536 sweep in memory from slrng_output_alloc, with plain or
+  nontemporal output stores; then the shortest slot (min_chunk), which only
   matters when there are few streams, by the latency of a 1,024-stream
   launch of 4,096 outputs per stream;
 * batched generation: LDS tile, persistent grid (waves per CU) and lane-chunk
@@ -72,12 +73,13 @@ def tune_generate(variants, S=65536, N=65536, reps=5, quick=False, log=print) ->
                 for tile in tiles:
                     for tw in waves:
                         for sk in skews:
-                            B.slrng_set_tuning(name, kind, tile, tw, 1024, sk)
-                            ms = _time_ms(lambda: B.slrng_generate(h.h, kind, n_out, buf.data_ptr(),
-                                                                   n_out), reps)
-                            if best is None or ms < best[0]:
-                                best = (ms, {"tile": tile, "target_waves": tw, "skew": sk,
-                                             "min_chunk": 1024})
+                            for store in (0, 1):
+                                B.slrng_set_tuning(name, kind, tile, tw, 1024, sk, store)
+                                ms = _time_ms(lambda: B.slrng_generate(h.h, kind, n_out, buf.data_ptr(),
+                                                                       n_out), reps)
+                                if best is None or ms < best[0]:
+                                    best = (ms, {"tile": tile, "target_waves": tw, "skew": sk,
+                                                 "min_chunk": 1024, "store": store})
             gbs = 8 * S * N / (best[0] * 1e-3) / 1e9
             # shortest slot: latency of a small launch (the sweep's slots are
             # far longer than any candidate, so its timing does not change)
@@ -86,7 +88,8 @@ def tune_generate(variants, S=65536, N=65536, reps=5, quick=False, log=print) ->
             with B.Streams(name, 1, 1024) as h:
                 lat = []
                 for mc in (256, 512, 1024):
-                    B.slrng_set_tuning(name, kind, cfg["tile"], cfg["target_waves"], mc, cfg["skew"])
+                    B.slrng_set_tuning(name, kind, cfg["tile"], cfg["target_waves"], mc, cfg["skew"],
+                                       cfg["store"])
                     lat.append((_time_ms(lambda: B.slrng_generate(h.h, kind, small_n, buf.data_ptr(),
                                                                   small_n), reps), mc))
             cfg["min_chunk"] = min(lat)[1]
@@ -94,7 +97,7 @@ def tune_generate(variants, S=65536, N=65536, reps=5, quick=False, log=print) ->
                 f"{min(lat)[0] * 1e3:.1f} us")
             out[f"{name}/{kind}"] = dict(best[1], GBs=round(gbs, 1))
             B.slrng_set_tuning(name, kind, **{k: best[1][k] for k in
-                                              ("tile", "target_waves", "min_chunk", "skew")})
+                                              ("tile", "target_waves", "min_chunk", "skew", "store")})
     del buf
     torch.cuda.empty_cache()
     return out
@@ -153,7 +156,7 @@ def apply(path: str = DEFAULT_PATH) -> bool:
     for key, cfg in t.get("generate", {}).items():
         name, kind = key.rsplit("/", 1)
         B.slrng_set_tuning(name, int(kind), cfg["tile"], cfg["target_waves"], cfg["min_chunk"],
-                           cfg["skew"])
+                           cfg["skew"], cfg.get("store", 0))
     if "batch" in t:
         B.set_batch_defaults(t["batch"])
     return True

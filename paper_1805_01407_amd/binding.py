@@ -44,7 +44,7 @@ class SlrngError(RuntimeError):
 
 class _Tuning(ctypes.Structure):
     _fields_ = [("tile", ctypes.c_int32), ("target_waves", ctypes.c_int32),
-                ("skew", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("skew", ctypes.c_int32), ("store", ctypes.c_int32),
                 ("min_chunk", ctypes.c_uint64)]
 
 
@@ -349,12 +349,12 @@ def slrng_get_tuning(variant, kind: int = SLRNG_U64) -> dict:
     t = _Tuning()
     _check(lib().slrng_get_tuning(_variant(variant), kind, ctypes.byref(t)), "slrng_get_tuning")
     return {"tile": t.tile, "target_waves": t.target_waves, "skew": t.skew,
-            "min_chunk": t.min_chunk}
+            "min_chunk": t.min_chunk, "store": t.store}
 
 
 def slrng_set_tuning(variant, kind: int, tile: int, target_waves: int, min_chunk: int,
-                     skew: int = 1) -> None:
-    t = _Tuning(tile, target_waves, skew, 0, min_chunk)
+                     skew: int = 1, store: int = 0) -> None:
+    t = _Tuning(tile, target_waves, skew, store, min_chunk)
     _check(lib().slrng_set_tuning(_variant(variant), kind, ctypes.byref(t)), "slrng_set_tuning")
 
 

@@ -599,9 +599,10 @@ extern "C" int slrng_generate(slrng_streams *h, int kind, uint64_t n, void *dev_
     a.out = dev_out;
     a.ld = ld;
     a.slot_polys = sp;
-    GenConfig cfg{t.tile};
-    hipError_t e = is_variant32(h->variant) ? launch_generate32(h->variant, kind_index(kind), a, stream)
-                                            : launch_generate(h->variant, kind, a, cfg, stream);
+    GenConfig cfg{t.tile, t.store == 1};
+    hipError_t e = is_variant32(h->variant)
+                       ? launch_generate32(h->variant, kind_index(kind), a, cfg.nt, stream)
+                       : launch_generate(h->variant, kind, a, cfg, stream);
     if (e != hipSuccess) return hip_fail(e);
     if (nslots > 1) h->cur = 1 - h->cur;
     return SLRNG_OK;
@@ -624,7 +625,7 @@ extern "C" int slrng_set_tuning(int variant, int kind, const slrng_tuning *t) {
     // the 32-bit kernels stage tiles of 64 outputs; the 64-bit ones 16 or 32
     const bool tile_ok = is_variant32(variant) ? t->tile == 64 : (t->tile == 16 || t->tile == 32);
     if (!tile_ok || t->target_waves < 1 || t->target_waves > (1 << 20) ||
-        t->min_chunk < 1 || t->min_chunk > (1ull << 40) || t->reserved != 0)
+        t->min_chunk < 1 || t->min_chunk > (1ull << 40) || (t->store != 0 && t->store != 1))
       return SLRNG_EINVAL;
     if (t->skew != 1 && t->skew != 2 && t->skew != 4 && t->skew != 8 && t->skew != 16)
       return SLRNG_EINVAL;

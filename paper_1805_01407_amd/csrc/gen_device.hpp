@@ -165,11 +165,25 @@ __device__ __forceinline__ int gen_tile_partial(u64 (&s)[Params<V>::k], u64 *row
   return m % BLK;
 }
 
-// Output stores are plain (write-back) stores: measured faster than
-// nontemporal ones for the tiled stream-major pattern on gfx950.
+// Output stores of the generation kernels: plain (write-back) or
+// nontemporal (the nt cache policy), chosen per launch.  Which is faster
+// depends on where the output's physical pages lie: in one compact range plain
+// stores measured faster, in memory whose pages are spread over the HBM
+// nontemporal ones did; the autotuner measures both per generator and kind.
 template <typename VT>
 __device__ __forceinline__ void out_store(VT *p, VT v) {
   *p = v;
+}
+
+template <typename VT>
+__device__ __forceinline__ void out_store_nt(VT *p, VT v) {
+  __builtin_nontemporal_store(v, p);
+}
+
+template <bool NT, typename VT>
+__device__ __forceinline__ void out_store_as(VT *p, VT v) {
+  if constexpr (NT) out_store_nt(p, v);
+  else out_store(p, v);
 }
 
 // Store with the device-scope cache policy (sc1): the line is written through
@@ -195,7 +209,7 @@ __device__ __forceinline__ void out_store_wt(VT *p, VT v) {
 // Store a staged tile: rows 0..rows_live of the wave, m outputs each, to
 // base + r*ld + c.  A16: every row start is 16-byte aligned (dwordx4 path).
 // A full tile (all 64 rows, T outputs) takes the unpredicated path.
-template <int T, bool A16>
+template <int T, bool A16, bool NT>
 __device__ __forceinline__ void store_tile(const u64 *lds, int lane, u64 *base, u64 ld,
                                            int rows_live, int m) {
   constexpr int S = TileGeom<T>::kStride;
@@ -217,7 +231,7 @@ __device__ __forceinline__ void store_tile(const u64 *lds, int lane, u64 *base, 
       for (int q = 0; q < T / 2; q++) v[q] = src[q * RPI * S / 2];
       __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-      for (int q = 0; q < T / 2; q++) out_store(reinterpret_cast<u64x2 *>(dst + q * step), v[q]);
+      for (int q = 0; q < T / 2; q++) out_store_as<NT>(reinterpret_cast<u64x2 *>(dst + q * step), v[q]);
       return;
     }
 #pragma unroll
@@ -225,8 +239,8 @@ __device__ __forceinline__ void store_tile(const u64 *lds, int lane, u64 *base, 
       const int r = q * RPI + r0;
       if (r < rows_live && c < m) {
         const u64x2 v = src[q * RPI * S / 2];
-        if (c + 1 < m) out_store(reinterpret_cast<u64x2 *>(dst + q * step), v);
-        else out_store(dst + q * step, v.x);
+        if (c + 1 < m) out_store_as<NT>(reinterpret_cast<u64x2 *>(dst + q * step), v);
+        else out_store_as<NT>(dst + q * step, v.x);
       }
     }
   } else {
@@ -239,7 +253,7 @@ __device__ __forceinline__ void store_tile(const u64 *lds, int lane, u64 *base, 
 #pragma unroll
     for (int q = 0; q < T; q++) {
       const int r = q * RPI + r0;
-      if (r < rows_live && c < m) out_store(dst + q * step, lds[r * S + c]);
+      if (r < rows_live && c < m) out_store_as<NT>(dst + q * step, lds[r * S + c]);
     }
   }
 }

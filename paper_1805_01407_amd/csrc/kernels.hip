@@ -25,7 +25,7 @@
 
 namespace slrng {
 
-template <int V, int KIND, int T, bool A16>
+template <int V, int KIND, int T, bool A16, bool NT>
 __global__ __launch_bounds__(kBlock) void k_generate(GenArgs a) {
   constexpr int K = Params<V>::k;
   __shared__ __attribute__((aligned(16))) u64 lds_all[(kBlock / kWave) * TileGeom<T>::kWaveLds];
@@ -64,7 +64,7 @@ __global__ __launch_bounds__(kBlock) void k_generate(GenArgs a) {
     if (m == T) gen_tile_full<V, KIND, T>(s, myrow);
     else ph = gen_tile_partial<V, KIND, T>(s, myrow, m);
     wave_sync();
-    store_tile<T, A16>(lds, lane, base + t0, a.ld, rows_live, m);
+    store_tile<T, A16, NT>(lds, lane, base + t0, a.ld, rows_live, m);
     wave_sync();
   }
   if constexpr (K == 16) rotate_to_logical<V>(s, ph);
@@ -167,21 +167,24 @@ __global__ __launch_bounds__(kBlock) void k_copy(u64x2 *dst, const u64x2 *src, u
 // ---------------------------------------------------------------- launchers
 
 template <int V, int KIND, int T>
-static hipError_t gen_t(const GenArgs &a, hipStream_t st) {
+static hipError_t gen_t(const GenArgs &a, bool nt, hipStream_t st) {
   const u64 waves = (a.S + kWave - 1) / kWave;
   dim3 grid((unsigned)((waves + (kBlock / kWave) - 1) / (kBlock / kWave)), (unsigned)a.nslots);
   // slot starts are multiples of C/D (even), so rows start 16-byte aligned
   // when the buffer and the row stride are
   const bool a16 = ((uintptr_t)a.out % 16 == 0) && (a.ld % 2 == 0) && ((a.C / a.D) % 2 == 0);
-  if (a16) hipLaunchKernelGGL((k_generate<V, KIND, T, true>), grid, dim3(kBlock), 0, st, a);
-  else hipLaunchKernelGGL((k_generate<V, KIND, T, false>), grid, dim3(kBlock), 0, st, a);
+  // nontemporal stores on the 16-byte path only (the 8-byte path is the
+  // rare misaligned case)
+  if (a16 && nt) hipLaunchKernelGGL((k_generate<V, KIND, T, true, true>), grid, dim3(kBlock), 0, st, a);
+  else if (a16) hipLaunchKernelGGL((k_generate<V, KIND, T, true, false>), grid, dim3(kBlock), 0, st, a);
+  else hipLaunchKernelGGL((k_generate<V, KIND, T, false, false>), grid, dim3(kBlock), 0, st, a);
   return hipGetLastError();
 }
 
 template <int V>
 static hipError_t gen_v(int kind, const GenArgs &a, const GenConfig &cfg, hipStream_t st) {
-  if (cfg.tile == 32) return kind ? gen_t<V, 1, 32>(a, st) : gen_t<V, 0, 32>(a, st);
-  return kind ? gen_t<V, 1, 16>(a, st) : gen_t<V, 0, 16>(a, st);
+  if (cfg.tile == 32) return kind ? gen_t<V, 1, 32>(a, cfg.nt, st) : gen_t<V, 0, 32>(a, cfg.nt, st);
+  return kind ? gen_t<V, 1, 16>(a, cfg.nt, st) : gen_t<V, 0, 16>(a, cfg.nt, st);
 }
 
 #define SL_DISPATCH(v, EXPR_T)      \

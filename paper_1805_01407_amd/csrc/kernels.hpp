@@ -44,6 +44,7 @@ struct GenArgs {
 
 struct GenConfig {
   int tile;  // outputs per lane staged through LDS per round: 16 or 32
+  bool nt;   // nontemporal output stores (else plain write-back stores)
 };
 
 // All return hipError_t of the launch.

@@ -118,7 +118,7 @@ __device__ __forceinline__ void gen_tile32_partial(u32 (&s)[Params32<V>::k], u32
 // Store a staged tile: rows 0..rows_live of the wave, m outputs each, to
 // base + r*ld + c.  A16: every row start is 16-byte aligned (4 outputs per
 // lane and store, 16 lanes per row); else one output per lane and store.
-template <bool A16>
+template <bool A16, bool NT>
 __device__ __forceinline__ void store_tile32(const u32 *lds, int lane, u32 *base, u64 ld,
                                              int rows_live, int m) {
   if constexpr (A16) {
@@ -135,7 +135,7 @@ __device__ __forceinline__ void store_tile32(const u32 *lds, int lane, u32 *base
       for (int q = 0; q < kT32 / 4; q++) v[q] = src[q * RPI * kStride32 / 4];
       __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-      for (int q = 0; q < kT32 / 4; q++) out_store(reinterpret_cast<u32x4 *>(dst + q * step), v[q]);
+      for (int q = 0; q < kT32 / 4; q++) out_store_as<NT>(reinterpret_cast<u32x4 *>(dst + q * step), v[q]);
       return;
     }
 #pragma unroll
@@ -145,7 +145,7 @@ __device__ __forceinline__ void store_tile32(const u32 *lds, int lane, u32 *base
         const u32x4 v = src[q * RPI * kStride32 / 4];
         u32 *d = dst + q * step;
         if (c + 3 < m) {
-          out_store(reinterpret_cast<u32x4 *>(d), v);
+          out_store_as<NT>(reinterpret_cast<u32x4 *>(d), v);
         } else {
           d[0] = v.x;
           if (c + 1 < m) d[1] = v.y;
@@ -163,7 +163,7 @@ __device__ __forceinline__ void store_tile32(const u32 *lds, int lane, u32 *base
 // ---------------------------------------------------------------- kernels
 
 // Generation (see GenArgs for the slot and skew plan; outputs are 32-bit).
-template <int V, int KIND, bool A16>
+template <int V, int KIND, bool A16, bool NT>
 __global__ __launch_bounds__(kBlock) void k_generate32(GenArgs a) {
   constexpr int K = Params32<V>::k;
   __shared__ __attribute__((aligned(16))) u32 lds_all[(kBlock / kWave) * kWaveLds32];
@@ -200,7 +200,7 @@ __global__ __launch_bounds__(kBlock) void k_generate32(GenArgs a) {
     if (m == kT32) gen_tile32_full<V, KIND>(s, myrow);
     else gen_tile32_partial<V, KIND>(s, myrow, m);
     wave_sync();
-    store_tile32<A16>(lds, lane, base + t0, a.ld, rows_live, m);
+    store_tile32<A16, NT>(lds, lane, base + t0, a.ld, rows_live, m);
     wave_sync();
   }
   if (t_end == a.n && live) {
@@ -297,25 +297,27 @@ __global__ __launch_bounds__(kBlock) void k_advance_each32(u64 *__restrict__ sta
     default: return hipErrorInvalidValue; \
   }
 
+template <int V, int KIND>
+static hipError_t gen32_k(const GenArgs &a, bool nt, dim3 grid, bool a16, hipStream_t st) {
+  // nontemporal stores on the 16-byte path only
+  if (a16 && nt) hipLaunchKernelGGL((k_generate32<V, KIND, true, true>), grid, dim3(kBlock), 0, st, a);
+  else if (a16) hipLaunchKernelGGL((k_generate32<V, KIND, true, false>), grid, dim3(kBlock), 0, st, a);
+  else hipLaunchKernelGGL((k_generate32<V, KIND, false, false>), grid, dim3(kBlock), 0, st, a);
+  return hipGetLastError();
+}
+
 template <int V>
-static hipError_t gen32_v(int kind, const GenArgs &a, hipStream_t st) {
+static hipError_t gen32_v(int kind, const GenArgs &a, bool nt, hipStream_t st) {
   const u64 waves = (a.S + kWave - 1) / kWave;
   dim3 grid((unsigned)((waves + (kBlock / kWave) - 1) / (kBlock / kWave)), (unsigned)a.nslots);
   // slot starts are multiples of C/D, a multiple of the tile, so rows start
   // 16-byte aligned when the buffer is and the row stride is a multiple of 4
   const bool a16 = ((uintptr_t)a.out % 16 == 0) && (a.ld % 4 == 0) && ((a.C / a.D) % 4 == 0);
-  if (kind) {
-    if (a16) hipLaunchKernelGGL((k_generate32<V, 1, true>), grid, dim3(kBlock), 0, st, a);
-    else hipLaunchKernelGGL((k_generate32<V, 1, false>), grid, dim3(kBlock), 0, st, a);
-  } else {
-    if (a16) hipLaunchKernelGGL((k_generate32<V, 0, true>), grid, dim3(kBlock), 0, st, a);
-    else hipLaunchKernelGGL((k_generate32<V, 0, false>), grid, dim3(kBlock), 0, st, a);
-  }
-  return hipGetLastError();
+  return kind ? gen32_k<V, 1>(a, nt, grid, a16, st) : gen32_k<V, 0>(a, nt, grid, a16, st);
 }
 
-hipError_t launch_generate32(int variant, int kind, const GenArgs &a, hipStream_t st) {
-#define SL_GEN32(V) gen32_v<V>(kind, a, st)
+hipError_t launch_generate32(int variant, int kind, const GenArgs &a, bool nt, hipStream_t st) {
+#define SL_GEN32(V) gen32_v<V>(kind, a, nt, st)
   SL_DISPATCH32(variant, SL_GEN32)
 #undef SL_GEN32
 }

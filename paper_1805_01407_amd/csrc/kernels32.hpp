@@ -9,7 +9,7 @@
 
 namespace slrng {
 
-hipError_t launch_generate32(int variant, int kind, const GenArgs &a, hipStream_t st);
+hipError_t launch_generate32(int variant, int kind, const GenArgs &a, bool nt, hipStream_t st);
 hipError_t launch_position32(int variant, uint64_t seed, uint64_t S, const uint64_t *tab0,
                              const uint64_t *up, int levels, uint64_t *state_out, hipStream_t st);
 hipError_t launch_jump32(int variant, uint64_t *state, uint64_t S, const UPoly &r, hipStream_t st);

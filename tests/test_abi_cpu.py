@@ -128,7 +128,12 @@ def test_tuning_validation(P):
         P.slrng_set_tuning("xoshiro256**", 2, 16, 1024, 1024)
     with pytest.raises(P.SlrngError):
         P.slrng_set_tuning("xoshiro256**", 0, 16, 1024, 1024, skew=3)
-    P.slrng_set_tuning("xoshiro256**", 0, t["tile"], t["target_waves"], t["min_chunk"], t["skew"])
+    with pytest.raises(P.SlrngError):
+        P.slrng_set_tuning("xoshiro256**", 0, 16, 1024, 1024, store=2)
+    P.slrng_set_tuning("xoshiro256**", 0, t["tile"], t["target_waves"], t["min_chunk"], t["skew"], 1)
+    assert P.slrng_get_tuning("xoshiro256**")["store"] == 1
+    P.slrng_set_tuning("xoshiro256**", 0, t["tile"], t["target_waves"], t["min_chunk"], t["skew"],
+                       t["store"])
 
 
 def test_invalid_arguments_return_einval(P):
@@ -228,7 +233,7 @@ def test_32bit_argument_errors_before_any_device_call(P):
     with pytest.raises(P.SlrngError):
         P.slrng_get_tuning("xoshiro256+", P.SLRNG_U32)
     P.slrng_set_tuning("xoshiro128+", P.SLRNG_U32, t["tile"], t["target_waves"], t["min_chunk"],
-                       t["skew"])
+                       t["skew"], t["store"])
 
 
 def test_bench_refuses_more_than_one_gpu():

@@ -96,17 +96,17 @@ def test_generate32_split_streams(P, name):
     S, N = 70, 40000
     chain = O.stream_chain(g, 3, S)
     exp, fin = oracle_outputs(g, chain, N)
-    for skew in (1, 4):
-        announce("gen32 split", name, skew)
+    for skew, store in ((1, 0), (4, 1), (1, 1)):
+        announce("gen32 split", name, skew, store)
         old = P.slrng_get_tuning(name, P.SLRNG_U32)
-        P.slrng_set_tuning(name, P.SLRNG_U32, 64, 4096, 1024, skew)
+        P.slrng_set_tuning(name, P.SLRNG_U32, 64, 4096, 1024, skew, store)
         try:
             with P.Streams(name, 3, S) as h:
                 out = as_u32(h.generate(N))
                 assert np.array_equal(h.get_state(), fin)
         finally:
             P.slrng_set_tuning(name, P.SLRNG_U32, old["tile"], old["target_waves"],
-                               old["min_chunk"], old["skew"])
+                               old["min_chunk"], old["skew"], old["store"])
         assert np.array_equal(out, exp)
 
 

@@ -109,16 +109,18 @@ def test_zero_length_is_noop(P):
 @pytest.mark.parametrize("name", ["xoshiro256**", "xoroshiro1024**", "xoroshiro128++", "xoshiro512+"])
 def test_chunk_split_matches_unsplit(P, name):
     """Force the stream-splitting path (slots jumped ahead, with and without
-    staggered boundaries): the values never depend on the launch shape."""
+    staggered boundaries) with plain and nontemporal stores: the values never
+    depend on the launch shape."""
     t = P.slrng_get_tuning(name)
     try:
-        for tile, skew in ((16, 1), (32, 1), (16, 4), (32, 16)):
-            P.slrng_set_tuning(name, 0, tile, 1 << 16, 64, skew)
+        for tile, skew, store in ((16, 1, 0), (32, 1, 1), (16, 4, 1), (32, 16, 0), (32, 16, 1)):
+            P.slrng_set_tuning(name, 0, tile, 1 << 16, 64, skew, store)
             check_generate(P, name, 21, 300, 3001)
             check_generate(P, name, 22, 3, 100)
             check_generate(P, name, 23, 64, 1)
     finally:
-        P.slrng_set_tuning(name, 0, t["tile"], t["target_waves"], t["min_chunk"], t["skew"])
+        P.slrng_set_tuning(name, 0, t["tile"], t["target_waves"], t["min_chunk"], t["skew"],
+                           t["store"])
 
 
 def test_split_calls_equal_one_call(P):
