@@ -268,7 +268,8 @@ int slrng_output_free(void *dev_ptr);
  *                (groups of 64 streams in different classes start their
  *                chunks at different offsets, which spreads concurrent stores
  *                over the memory channels when the row stride is a power of
- *                two); 1 = no stagger;
+ *                two); 1 = no stagger; applied only to chunks of at least
+ *                8 x tile x skew outputs;
  *  min_chunk     no chunk shorter than this many outputs;
  *  store         0: plain (write-back) output stores; 1: nontemporal ones
  *                (on the 16-byte aligned path).  Which is faster depends on

@@ -17,7 +17,7 @@ The result is a JSON file keyed by GPU architecture; the binding applies it
 when it loads the library (``apply``).  The launch shape never changes any
 output value, only speed.
 
-    python -m paper_1805_01407_amd.autotune [--out FILE] [--quick]
+    python -m paper_1805_01407_amd.autotune [--out FILE] [--quick] [--only generate|batch|min_chunk]
 """
 from __future__ import annotations
 
@@ -81,26 +81,47 @@ def tune_generate(variants, S=65536, N=65536, reps=5, quick=False, log=print) ->
                                     best = (ms, {"tile": tile, "target_waves": tw, "skew": sk,
                                                  "min_chunk": 1024, "store": store})
             gbs = 8 * S * N / (best[0] * 1e-3) / 1e9
-            # shortest slot: latency of a small launch (the sweep's slots are
-            # far longer than any candidate, so its timing does not change)
             cfg = best[1]
-            small_n = 2 * 4096 if w32 else 4096
-            with B.Streams(name, 1, 1024) as h:
-                lat = []
-                for mc in (256, 512, 1024):
-                    B.slrng_set_tuning(name, kind, cfg["tile"], cfg["target_waves"], mc, cfg["skew"],
-                                       cfg["store"])
-                    lat.append((_time_ms(lambda: B.slrng_generate(h.h, kind, small_n, buf.data_ptr(),
-                                                                  small_n), reps), mc))
-            cfg["min_chunk"] = min(lat)[1]
-            log(f"generate {name} kind {kind}: {best[1]} {gbs:.0f} GB/s; 1,024 streams: "
-                f"{min(lat)[0] * 1e3:.1f} us")
-            out[f"{name}/{kind}"] = dict(best[1], GBs=round(gbs, 1))
-            B.slrng_set_tuning(name, kind, **{k: best[1][k] for k in
+            cfg["min_chunk"], lat_us = _best_min_chunk(name, kind, cfg, reps)
+            log(f"generate {name} kind {kind}: {cfg} {gbs:.0f} GB/s; 1,024 streams: {lat_us:.1f} us")
+            out[f"{name}/{kind}"] = dict(cfg, GBs=round(gbs, 1))
+            B.slrng_set_tuning(name, kind, **{k: cfg[k] for k in
                                               ("tile", "target_waves", "min_chunk", "skew", "store")})
     del buf
     torch.cuda.empty_cache()
     return out
+
+
+def _best_min_chunk(name, kind, cfg, reps=9):
+    """Shortest slot for a launch shape: the latency of 1,024 streams x 4,096
+    outputs (8,192 for 32-bit generators) in ordinary device memory, where
+    outputs of that size live (the sweep's slots are far longer than any
+    candidate, so its timing does not change).  Returns (min_chunk, us)."""
+    import torch
+    from . import binding as B
+    small_n = 2 * 4096 if name in B.VARIANTS32 else 4096
+    buf = torch.empty((1024, small_n), dtype=torch.int64, device="cuda")
+    lat = []
+    with B.Streams(name, 1, 1024) as h:
+        for mc in (256, 512, 1024):
+            B.slrng_set_tuning(name, kind, cfg["tile"], cfg["target_waves"], mc, cfg["skew"],
+                               cfg.get("store", 0))
+            lat.append((_time_ms(lambda: B.slrng_generate(h.h, kind, small_n, buf.data_ptr(), small_n),
+                                 reps), mc))
+    ms, mc = min(lat)
+    return mc, ms * 1e3
+
+
+def tune_min_chunk(data: dict, log=print) -> dict:
+    """Re-tune min_chunk alone for every saved (generator, kind) entry."""
+    from . import binding as B
+    for key, cfg in data.items():
+        name, kind = key.rsplit("/", 1)
+        cfg["min_chunk"], lat_us = _best_min_chunk(name, int(kind), cfg)
+        B.slrng_set_tuning(name, int(kind), cfg["tile"], cfg["target_waves"], cfg["min_chunk"],
+                           cfg["skew"], cfg.get("store", 0))
+        log(f"min_chunk {key}: {cfg['min_chunk']} ({lat_us:.1f} us)")
+    return data
 
 
 def tune_batch(reps=5, quick=False, log=print) -> dict:
@@ -166,7 +187,7 @@ def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--out", default=DEFAULT_PATH)
     ap.add_argument("--quick", action="store_true")
-    ap.add_argument("--only", choices=["generate", "batch"], default=None)
+    ap.add_argument("--only", choices=["generate", "batch", "min_chunk"], default=None)
     args = ap.parse_args(argv)
     sys.path.insert(0, os.path.dirname(HERE))
     from . import binding as B
@@ -179,6 +200,8 @@ def main(argv=None):
     entry = data.get(arch, {})
     if args.only in (None, "generate"):
         entry["generate"] = tune_generate(B.VARIANTS + B.VARIANTS32, quick=args.quick)
+    if args.only == "min_chunk":
+        entry["generate"] = tune_min_chunk(entry.get("generate", {}))
     if args.only in (None, "batch"):
         entry["batch"] = tune_batch(quick=args.quick)
     data[arch] = entry

@@ -260,10 +260,14 @@ void plan_slots(uint64_t S, uint64_t n, const slrng_tuning &t, uint64_t &C, uint
   uint64_t want = 1;
   if (waves < (uint64_t)t.target_waves) want = ((uint64_t)t.target_waves + waves - 1) / waves;
   if (want > (uint64_t)kMaxChunks) want = kMaxChunks;
-  D = (uint64_t)t.skew;
-  const uint64_t unit = (uint64_t)t.tile * D;
   C = (n + want - 1) / want;
   if (C < t.min_chunk) C = t.min_chunk;
+  // staggered boundaries pay only for long slots (the shift C/D spans at
+  // least 8 tiles); short, latency-bound slots go without, so that their
+  // length is not rounded up to a multiple of tile x D
+  D = (uint64_t)t.skew;
+  if (D > 1 && C < D * (uint64_t)t.tile * 8) D = 1;
+  const uint64_t unit = (uint64_t)t.tile * D;
   C = (C + unit - 1) / unit * unit;
   uint64_t nchunks = (n + C - 1) / C;
   if (nchunks == 0) nchunks = 1;
