@@ -9,8 +9,8 @@
 //    are contiguous.  Each wave stages a tile of T outputs per lane in LDS
 //    (row = lane) and then reads it back column-wise so that each
 //    global_store_dwordx4 writes whole 128/256-byte runs of a few rows:
-//    fully coalesced, plain write-back stores (nontemporal and write-through
-//    stores measured slower for this stream-major pattern);
+//    fully coalesced; plain or nontemporal stores as the launch shape says
+//    (write-through stores measured slower for this stream-major pattern);
 //  * waves never wait on each other: every wave owns its LDS rows and the
 //    LDS exchange inside a wave is ordered by the in-order LDS queue plus
 //    a wavefront-scope fence (no workgroup barrier);
