@@ -171,6 +171,44 @@ def test_set_get_state_roundtrip(P):
         assert (s.get_state() == fin).all()
 
 
+# outputs at the edges of the float conversions: the low bits that are
+# dropped, the 2^11 (2^8) threshold, each word of the upper part, all ones
+EDGE64 = [0, 1, 0x7FF, 0x800, 0xFFF, 0xFFFFF7FF, 0xFFFFF800, 0xFFFFFFFF, 1 << 32, (1 << 32) | 0x7FF,
+          (1 << 32) + 0x800, 0x7FFFFFFFFFFFFFFF, 1 << 63, (1 << 63) | 0x7FF, (1 << 64) - 0x800,
+          (1 << 64) - 0x801, (1 << 64) - 1, 0x0123456789ABCDEF, 0xFEDCBA9876543210, 0x00000000FFFFF800]
+EDGE32 = [0, 1, 0x7F, 0x80, 0xFF, 0x100, 0x1FF, 0xFFFFFF, 0x1000000, 0x7FFFFFFF, 0x80000000,
+          0xFFFFFF00, 0xFFFFFFFE, 0xFFFFFFFF, 0x12345678]
+
+
+def test_float_conversion_at_edge_values(P):
+    """Streams whose first output is a chosen value: xoroshiro128+ emits
+    s0 + s1 and xoshiro128+ emits s0 + s3, so the states (x, 0) and
+    (x, 0, 0, 0) give x (and (1, 2^64 - 1), (1, 0, 0, 2^32 - 1) give 0, the
+    zero state being excluded).  The doubles must be (x >> 11) 2^-53 and the
+    floats (x >> 8) 2^-24, bit for bit."""
+    import torch
+    announce("float conversion edges")
+    st = np.array([[x, 0] if x else [1, (1 << 64) - 1] for x in EDGE64], dtype=np.uint64)
+    with P.Streams("xoroshiro128+", states=st.reshape(-1)) as s:
+        u = to_u64(s.generate(1, P.SLRNG_U64))[:, 0]
+        s.set_state(st)
+        d = s.generate(1, P.SLRNG_F64).cpu().numpy()[:, 0]
+    x = np.array(EDGE64, dtype=np.uint64)
+    assert (u == x).all()
+    exp = (x >> np.uint64(11)).astype(np.float64) * 2.0**-53
+    assert (d.view(np.uint64) == exp.view(np.uint64)).all()
+    assert (d < 1.0).all() and d[EDGE64.index((1 << 64) - 1)] == 1.0 - 2.0**-53
+    st32 = np.array([[x, 0, 0, 0] if x else [1, 0, 0, (1 << 32) - 1] for x in EDGE32], dtype=np.uint64)
+    with P.Streams("xoshiro128+", states=st32.reshape(-1)) as s:
+        w = s.generate(1, P.SLRNG_U32).cpu().numpy().view(np.uint32)[:, 0]
+        s.set_state(st32)
+        f = s.generate(1, P.SLRNG_F32).cpu().numpy()[:, 0]
+    x32 = np.array(EDGE32, dtype=np.uint64)
+    assert (w == x32.astype(np.uint32)).all()
+    assert (f.view(np.uint32) == O.to_float32(x32).view(np.uint32)).all()
+    torch.cuda.synchronize()
+
+
 def test_positioning_levels_beyond_1024(P):
     """Streams past 1024 use the second (wave-uniform) positioning level."""
     name = "xoshiro256++"
