@@ -411,6 +411,9 @@ def output_empty(shape, dtype=None):
     dtype = torch.int64 if dtype is None else dtype
     shape = tuple(int(s) for s in (shape if isinstance(shape, (tuple, list)) else (shape,)))
     name = str(dtype).replace("torch.", "")
+    if name not in _OutputMemory._TYPESTR:
+        raise ValueError(f"output_empty: unsupported dtype {dtype} "
+                         f"(one of {', '.join(sorted(_OutputMemory._TYPESTR))})")
     mem = _OutputMemory(shape, name, torch.empty((), dtype=dtype).element_size())
     return torch.as_tensor(mem, device="cuda")
 

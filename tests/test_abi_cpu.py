@@ -77,6 +77,9 @@ def test_rank_argument_errors(P):
 
 def test_output_memory_argument_errors(P):
     # host-side checks only: no device memory is touched
+    import torch
+    with pytest.raises(ValueError, match="unsupported dtype"):
+        P.output_empty((4, 4), torch.bfloat16)
     L = P.lib()
     p = ctypes.c_void_p(1234)
     assert L.slrng_output_alloc(0, ctypes.byref(p)) == -1 and p.value is None  # EINVAL, *out cleared
