@@ -38,7 +38,8 @@
  *  - Functions taking a hipStream_t are asynchronous and ordered on that
  *    stream (0 = the null stream); the caller orders calls on one handle.
  *  - Device buffers are caller-owned unless stated; handles own their state
- *    memory.  Handles are not thread-safe.
+ *    memory.  Handles are not thread-safe.  Large outputs write fastest into
+ *    memory from slrng_output_alloc (physical pages spread over the HBM).
  */
 #ifndef SLRNG_H
 #define SLRNG_H
