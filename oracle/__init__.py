@@ -12,7 +12,20 @@ Polynomials over Z/2Z are Python integers: bit i is the coefficient of x^i.
 States are numpy uint64 arrays in the logical order of the block matrices
 (word j of the row vector the transition matrix multiplies from the right).
 
-Parity unpinned: the SplitMix64 finalizer constants (see ``orc.c``).
+The engine step is the product of the state with the block matrix the paper
+prints (X_2w, X_kw of equation eq:M, S_4w, S_8w), expanded block by block; the
+code figures are not transcribed.
+
+Parity unpinned (no fact of the paper fixes these; they follow the code
+figures or the cited publication, and no external test vector exists here):
+  * the SplitMix64 finalizer constants (shifts 30, 27, 31 and its two
+    multipliers), checked only by inverting the finalizer with the test's own
+    statement of them;
+  * the word that ``**`` scrambles (the first logical word of xoroshiro, word
+    1 of xoshiro);
+  * the word ``++`` adds back for the two-word xoroshiro (the first);
+  * the split of SplitMix64 outputs into the 32-bit generators' words (low
+    half first).
 """
 from __future__ import annotations
 

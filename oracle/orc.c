@@ -10,14 +10,13 @@
  * Everything is integer arithmetic, so the GPU result must match bit for bit.
  *
  * What follows which passage of the paper:
- *   - xoroshiro engine, two words:   Section "Linear engines", figure
- *     fig:xoroshiro128 and matrix X_2w.
- *   - xoroshiro engine, k > 2 words: figure fig:xoroshiro1024 (cyclic update
- *     with the index p) and the block matrix of equation eq:M.
- *   - xoshiro engines (4 and 8 words): figures fig:xoshiro256, fig:xoshiro512,
- *     matrices S_4w and S_8w.
- *   - scramblers +, *, ++, **: Section "Scramblers"; the words each scrambler
- *     reads are the ones named in the four code figures.
+ *   - engine steps: Section "Linear engines".  The step is the product of the
+ *     state row vector with the block matrix the paper prints (X_2w, X_kw of
+ *     equation eq:M, S_4w, S_8w), expanded block by block into xors of
+ *     shifted and rotated words; the code figures are not transcribed.
+ *   - scramblers +, *, ++, **: Section "Scramblers" (the formulas), with the
+ *     words each one reads taken from the code figures fig:xoroshiro128,
+ *     fig:xoroshiro1024, fig:xoshiro256 and fig:xoshiro512.
  *   - engine parameters: Table tab:par64 (64-bit) and the small-word instances
  *     quoted in Section "Equidistribution"; scrambler constants: tab:scr64.
  *   - characteristic polynomial by Berlekamp-Massey on one bit of the engine:
@@ -31,8 +30,8 @@
  *     prints no SplitMix constants.  The golden gamma is pinned by a test (the
  *     odd integer nearest 2^64/phi); the finalizer's shift amounts and
  *     multipliers are those of the SplitMix64 publication (Steele, Lea and
- *     Flood, OOPSLA 2014, mix64): parity unpinned against any external
- *     implementation, since no test vector is available.
+ *     Flood, OOPSLA 2014, mix64), pinned only by a test that inverts the
+ *     finalizer with its own statement of those constants.
  *   - 53-bit doubles: Section "Choosing a generator" (upper 53 bits); the
  *     value is (x >> 11) * 2^-53, exact.
  *   - 32-bit generators: Section "The 32-bit case", tables tab:par32 and
@@ -41,13 +40,24 @@
  *     Seeding them: the paper only remarks that a 32-bit SplitMix is
  *     immediate to define.  Reading taken here: the state array is filled
  *     with the output stream of SplitMix64, i.e. each 64-bit output gives two
- *     32-bit words, low half first (parity unpinned, like SplitMix itself).
+ *     32-bit words, low half first.
+ *
+ * Parity unpinned (no fact of the paper fixes these; they follow the code
+ * figures or the cited publication, and no external test vector exists here):
+ *   - the SplitMix64 finalizer constants (shifts 30, 27, 31 and the two
+ *     multipliers) against any external SplitMix64 implementation;
+ *   - the word that ** scrambles: the first logical word of xoroshiro, word 1
+ *     of xoshiro (the equidistribution results allow other words);
+ *   - the word ++ adds back for the two-word xoroshiro (the first; both
+ *     choices are 1-dimensionally equidistributed there);
+ *   - the split of SplitMix64 outputs into the 32-bit generators' words.
  *
  * State convention.  A state is k words in the "logical order" of the block
  * matrices: word j of the row vector x = <x_0 .. x_{k-1}> with the next state
  * equal to x * M.  For the two-word xoroshiro and for xoshiro this is the array
  * s[] of the figures.  For xoroshiro with k > 2 words the figure keeps an array
- * s[] and an index p; the logical order is x_j = s[(p + 1 + j) mod k].
+ * s[] and a cyclic index p; its logical order is x_j = s[(p + 1 + j) mod k],
+ * and the oracle stores the logical order directly.
  *
  * Word size w may be anything from 1 to 64 bits so that the small instances
  * the paper uses as counterexamples run through exactly the same code.
@@ -98,121 +108,142 @@ static u64 addw(u64 x, u64 y, int w) { return (x + y) & wmask(w); }
 static u64 mulw(u64 x, u64 y, int w) { return (x * y) & wmask(w); }
 
 /* ------------------------------------------------------------------ */
-/* Engine state in the layout of the figures                           */
+/* Transition matrices of Section "Linear engines", block by block     */
 /* ------------------------------------------------------------------ */
 
+/* The step is the product x' = x M of the state row vector x (k words in
+ * logical order) with the engine's kw x kw block matrix M.  Block (i, j) maps
+ * word i of x to its contribution to word j of x'; every block is a sum of
+ * identities I, shifts S^e and rotations R^e (e = a, b or c), so x'_j is the
+ * xor over i of those operators applied to x_i.  The blocks are written below
+ * as the paper prints them; the code figures play no part in the oracle's
+ * step. */
+
+/* S_4w and S_8w (xoshiro256 and xoshiro512), entry [i][j] as printed: "0" is
+ * the zero block, "I" the identity, "Sa" = S^a, "Rb" = R^b; '+' separates the
+ * terms of a sum. */
+static const char *const S4W[4][4] = {
+    {"I", "I", "I",  "0"},
+    {"I", "I", "Sa", "Rb"},
+    {"0", "I", "I",  "0"},
+    {"I", "0", "0",  "Rb"},
+};
+static const char *const S8W[8][8] = {
+    {"I", "I", "I", "0", "0", "0", "0",  "0"},
+    {"0", "I", "0", "0", "I", "I", "Sa", "0"},
+    {"0", "I", "I", "0", "0", "0", "0",  "0"},
+    {"0", "0", "0", "I", "0", "0", "I",  "Rb"},
+    {"0", "0", "0", "I", "I", "0", "0",  "0"},
+    {"0", "0", "0", "0", "I", "I", "0",  "0"},
+    {"I", "0", "0", "0", "0", "0", "I",  "0"},
+    {"0", "0", "0", "0", "0", "0", "I",  "Rb"},
+};
+
+/* X_kw of equation eq:M (X_2w when k = 2): the first row holds R^a + S^b + I
+ * and R^c in the last two columns, rows 1 .. k-2 hold one identity just left
+ * of the diagonal (the words move down by one position), and the last row
+ * holds S^b + I and R^c in the last two columns. */
+static const char *xoroshiro_block(int k, int i, int j)
+{
+    if (i == 0 && j == k - 2) return "Ra+Sb+I";
+    if (i == 0 && j == k - 1) return "Rc";
+    if (i == k - 1 && j == k - 2) return "Sb+I";
+    if (i == k - 1 && j == k - 1) return "Rc";
+    if (i >= 1 && i <= k - 2 && j == i - 1) return "I";
+    return "0";
+}
+
+enum { OP_I = 0, OP_S = 1, OP_R = 2 };
+
+/* One term of a block: word src, operator op with amount e, xored into word
+ * dst of the next state. */
+typedef struct { uint8_t src, dst, op, e; } term;
+
+#define ORC_MAXTERMS 64
+
 typedef struct {
-    u64 s[ORC_MAXK];
-    int p;           /* only for xoroshiro with k > 2 */
-} orc_state;
+    orc_gen g;
+    int nt;
+    term t[ORC_MAXTERMS];
+} engine;
 
-static void load_logical(const orc_gen *g, const u64 *x, orc_state *st)
+static int param(const orc_gen *g, char name)
 {
-    for (int j = 0; j < g->k; j++) st->s[j] = x[j] & wmask(g->w);
-    /* with p = k-1, s[(p+1+j) mod k] = s[j] = x_j */
-    st->p = g->k - 1;
+    return name == 'a' ? g->a : name == 'b' ? g->b : g->c;
 }
 
-static void store_logical(const orc_gen *g, const orc_state *st, u64 *x)
+/* Expand every block of the engine's matrix into its terms. */
+static void engine_init(const orc_gen *g, engine *m)
 {
-    if (g->family == ORC_XOROSHIRO && g->k > 2) {
-        for (int j = 0; j < g->k; j++) x[j] = st->s[(st->p + 1 + j) % g->k];
-    } else {
-        for (int j = 0; j < g->k; j++) x[j] = st->s[j];
+    m->g = *g;
+    m->nt = 0;
+    for (int i = 0; i < g->k; i++)
+        for (int j = 0; j < g->k; j++) {
+            const char *blk = g->family == ORC_XOSHIRO
+                                  ? (g->k == 4 ? S4W[i][j] : S8W[i][j])
+                                  : xoroshiro_block(g->k, i, j);
+            for (const char *c = blk; *c; c++) {
+                term t = {(uint8_t)i, (uint8_t)j, OP_I, 0};
+                if (*c == '0' || *c == '+') continue;
+                if (*c == 'S' || *c == 'R') {
+                    t.op = *c == 'S' ? OP_S : OP_R;
+                    t.e = (uint8_t)param(g, c[1]);
+                    c++;
+                }
+                if (m->nt < ORC_MAXTERMS) m->t[m->nt++] = t;
+            }
+        }
+}
+
+/* x <- x M (logical order). */
+static void step(const engine *m, u64 *x)
+{
+    const int w = m->g.w;
+    u64 y[ORC_MAXK] = {0};
+    for (int q = 0; q < m->nt; q++) {
+        const term *t = &m->t[q];
+        const u64 v = x[t->src];
+        y[t->dst] ^= t->op == OP_I ? v : t->op == OP_S ? shl(v, t->e, w) : rotl(v, t->e, w);
     }
+    memcpy(x, y, (size_t)m->g.k * 8);
 }
 
-/* Scrambled output of the current state (outputs are computed before the
- * state is advanced, as in all four code figures). */
-static u64 output(const orc_gen *g, const orc_state *st)
+/* Scrambled output of a state in logical order (Section "Scramblers"); the
+ * output is taken before the state is advanced.  The words each scrambler
+ * reads follow the code figures: for xoroshiro the first and last logical
+ * words (s0 and s1 of fig:xoroshiro128, s0 and s15 of fig:xoroshiro1024), for
+ * xoshiro256 words 0 and 3, for xoshiro512 words 0 and 2; ** scrambles the
+ * first word of xoroshiro and word 1 of xoshiro.  ++ adds back the first word
+ * for the two-word xoroshiro and xoshiro256, the last word for the longer
+ * xoroshiro, word 2 for xoshiro512. */
+static u64 output(const orc_gen *g, const u64 *x)
 {
     const int w = g->w;
+    u64 first, second, added, starred;
     if (g->family == ORC_XOROSHIRO) {
-        u64 s0, sl;
-        if (g->k == 2) { s0 = st->s[0]; sl = st->s[1]; }
-        else { s0 = st->s[(st->p + 1) % g->k]; sl = st->s[st->p]; }
-        switch (g->scr) {
-        case ORC_NONE: return s0;
-        case ORC_PLUS: return addw(s0, sl, w);
-        case ORC_PLUSPLUS:
-            /* fig:xoroshiro128 adds s0 after the rotation;
-             * fig:xoroshiro1024 adds s15, the last word */
-            if (g->k == 2) return addw(rotl(addw(s0, sl, w), g->r, w), s0, w);
-            return addw(rotl(addw(s0, sl, w), g->r, w), sl, w);
-        case ORC_STAR: return mulw(s0, g->ms, w);
-        case ORC_STARSTAR: return mulw(rotl(mulw(s0, g->ms, w), g->r, w), g->mt, w);
-        }
-        return 0;
+        first = x[0];
+        second = x[g->k - 1];
+        added = g->k == 2 ? first : second;
+        starred = x[0];
+    } else {
+        first = x[0];
+        second = x[g->k == 4 ? 3 : 2];
+        added = g->k == 4 ? first : second;
+        starred = x[1];
     }
-    const u64 *s = st->s;
-    if (g->k == 4) {
-        /* fig:xoshiro256 */
-        switch (g->scr) {
-        case ORC_NONE: return s[0];
-        case ORC_PLUS: return addw(s[0], s[3], w);
-        case ORC_PLUSPLUS: return addw(rotl(addw(s[0], s[3], w), g->r, w), s[0], w);
-        case ORC_STARSTAR: return mulw(rotl(mulw(s[1], g->ms, w), g->r, w), g->mt, w);
-        }
-        return 0;
-    }
-    /* fig:xoshiro512 */
     switch (g->scr) {
-    case ORC_NONE: return s[0];
-    case ORC_PLUS: return addw(s[0], s[2], w);
-    case ORC_PLUSPLUS: return addw(rotl(addw(s[0], s[2], w), g->r, w), s[2], w);
-    case ORC_STARSTAR: return mulw(rotl(mulw(s[1], g->ms, w), g->r, w), g->mt, w);
+    case ORC_NONE: return first;
+    case ORC_PLUS: return addw(first, second, w);
+    case ORC_PLUSPLUS: return addw(rotl(addw(first, second, w), g->r, w), added, w);
+    case ORC_STAR: return mulw(starred, g->ms, w);
+    case ORC_STARSTAR: return mulw(rotl(mulw(starred, g->ms, w), g->r, w), g->mt, w);
     }
     return 0;
 }
 
-/* One step of the linear engine, as the code figures write it. */
-static void step(const orc_gen *g, orc_state *st)
+static void load(const orc_gen *g, const u64 *src, u64 *x)
 {
-    const int w = g->w;
-    u64 *s = st->s;
-    if (g->family == ORC_XOROSHIRO) {
-        if (g->k == 2) {
-            /* fig:xoroshiro128 */
-            const u64 s0 = s[0];
-            u64 s1 = s[1];
-            s1 ^= s0;
-            s[0] = rotl(s0, g->a, w) ^ s1 ^ shl(s1, g->b, w);
-            s[1] = rotl(s1, g->c, w);
-        } else {
-            /* fig:xoroshiro1024, with 15 replaced by k-1 */
-            const int q = st->p;
-            st->p = (st->p + 1) % g->k;
-            const u64 s0 = s[st->p];
-            u64 sl = s[q];
-            sl ^= s0;
-            s[q] = rotl(s0, g->a, w) ^ sl ^ shl(sl, g->b, w);
-            s[st->p] = rotl(sl, g->c, w);
-        }
-        return;
-    }
-    if (g->k == 4) {
-        /* fig:xoshiro256 */
-        const u64 t = shl(s[1], g->a, w);
-        s[2] ^= s[0];
-        s[3] ^= s[1];
-        s[1] ^= s[2];
-        s[0] ^= s[3];
-        s[2] ^= t;
-        s[3] = rotl(s[3], g->b, w);
-    } else {
-        /* fig:xoshiro512 */
-        const u64 t = shl(s[1], g->a, w);
-        s[2] ^= s[0];
-        s[5] ^= s[1];
-        s[1] ^= s[2];
-        s[7] ^= s[3];
-        s[3] ^= s[4];
-        s[4] ^= s[5];
-        s[0] ^= s[6];
-        s[6] ^= s[7];
-        s[6] ^= t;
-        s[7] = rotl(s[7], g->b, w);
-    }
+    for (int j = 0; j < g->k; j++) x[j] = src[j] & wmask(g->w);
 }
 
 /* ------------------------------------------------------------------ */
@@ -236,44 +267,50 @@ int orc_valid(const orc_gen *g)
 /* x (k words, logical order) <- x * M^nsteps */
 void orc_advance(const orc_gen *g, u64 *x, u64 nsteps)
 {
-    orc_state st;
-    load_logical(g, x, &st);
-    for (u64 i = 0; i < nsteps; i++) step(g, &st);
-    store_logical(g, &st, x);
+    engine m;
+    engine_init(g, &m);
+    u64 s[ORC_MAXK];
+    load(g, x, s);
+    for (u64 i = 0; i < nsteps; i++) step(&m, s);
+    memcpy(x, s, (size_t)g->k * 8);
 }
 
 /* Scrambled output of one state (logical order). */
 u64 orc_output(const orc_gen *g, const u64 *x)
 {
-    orc_state st;
-    load_logical(g, x, &st);
-    return output(g, &st);
+    u64 s[ORC_MAXK];
+    load(g, x, s);
+    return output(g, s);
 }
 
 /* Serial generation for one stream: out[t] = scramble(x * M^t), t < n;
  * x is advanced by n steps. */
 void orc_generate1(const orc_gen *g, u64 *x, u64 n, u64 *out)
 {
-    orc_state st;
-    load_logical(g, x, &st);
+    engine m;
+    engine_init(g, &m);
+    u64 s[ORC_MAXK];
+    load(g, x, s);
     for (u64 t = 0; t < n; t++) {
-        out[t] = output(g, &st);
-        step(g, &st);
+        out[t] = output(g, s);
+        step(&m, s);
     }
-    store_logical(g, &st, x);
+    memcpy(x, s, (size_t)g->k * 8);
 }
 
 /* The same, but keep only outputs at times t_lo <= t < t_hi (the state is
  * still advanced through every step). */
 void orc_generate_window(const orc_gen *g, u64 *x, u64 t_lo, u64 t_hi, u64 *out)
 {
-    orc_state st;
-    load_logical(g, x, &st);
+    engine m;
+    engine_init(g, &m);
+    u64 s[ORC_MAXK];
+    load(g, x, s);
     for (u64 t = 0; t < t_hi; t++) {
-        if (t >= t_lo) out[t - t_lo] = output(g, &st);
-        step(g, &st);
+        if (t >= t_lo) out[t - t_lo] = output(g, s);
+        step(&m, s);
     }
-    store_logical(g, &st, x);
+    memcpy(x, s, (size_t)g->k * 8);
 }
 
 /* 53-bit double from the upper 53 bits (exact). */
@@ -307,14 +344,16 @@ static void *gen_worker(void *arg)
             if (j->dout) orc_to_double_array(j->out + i * j->ld, j->dout + i * j->ld, j->n);
         } else {
             /* doubles only */
-            orc_state st;
-            load_logical(j->g, x, &st);
+            engine m;
+            engine_init(j->g, &m);
+            u64 s[ORC_MAXK];
+            load(j->g, x, s);
             double *d = j->dout + i * j->ld;
             for (u64 t = 0; t < j->n; t++) {
-                d[t] = orc_to_double(output(j->g, &st));
-                step(j->g, &st);
+                d[t] = orc_to_double(output(j->g, s));
+                step(&m, s);
             }
-            store_logical(j->g, &st, x);
+            memcpy(x, s, (size_t)j->g->k * 8);
         }
     }
     return NULL;
@@ -495,15 +534,13 @@ long orc_charpoly(const orc_gen *g, const u64 *x0, u64 *p_out)
     const long n = (long)g->k * g->w;
     const long N = 2 * n;
     uint8_t *bits = malloc((size_t)N), *conn = malloc((size_t)N + 1);
-    orc_gen e = *g;
-    e.scr = ORC_NONE;
-    orc_state st;
-    load_logical(&e, x0, &st);
+    engine m;
+    engine_init(g, &m);
     u64 x[ORC_MAXK];
+    load(g, x0, x);
     for (long t = 0; t < N; t++) {
-        store_logical(&e, &st, x);
         bits[t] = (uint8_t)(x[0] & 1);
-        step(&e, &st);
+        step(&m, x);
     }
     long L = orc_berlekamp_massey(bits, N, conn);
     memset(p_out, 0, (size_t)(n / 64 + 1) * 8);
@@ -519,15 +556,13 @@ void orc_jump_poly(const orc_gen *g, u64 *x, const u64 *r)
 {
     const long n = (long)g->k * g->w;
     u64 acc[ORC_MAXK] = {0}, cur[ORC_MAXK];
-    orc_gen e = *g;
-    orc_state st;
-    load_logical(&e, x, &st);
+    engine m;
+    engine_init(g, &m);
+    load(g, x, cur);
     for (long i = 0; i < n; i++) {
-        if (pbit(r, i)) {
-            store_logical(&e, &st, cur);
+        if (pbit(r, i))
             for (int j = 0; j < g->k; j++) acc[j] ^= cur[j];
-        }
-        step(&e, &st);
+        step(&m, cur);
     }
     for (int j = 0; j < g->k; j++) x[j] = acc[j];
 }
@@ -596,14 +631,13 @@ void orc_jump_many(const orc_gen *g, u64 *states, u64 S, const u64 *r, int nthre
  * limit and returns 0 if the start state has not come back by then). */
 u64 orc_period(const orc_gen *g, const u64 *x0, u64 limit)
 {
-    orc_state st, st0;
-    load_logical(g, x0, &st);
-    st0 = st;
+    engine m;
+    engine_init(g, &m);
     u64 x[ORC_MAXK], y[ORC_MAXK];
-    store_logical(g, &st0, y);
+    load(g, x0, x);
+    memcpy(y, x, sizeof y);
     for (u64 t = 1; t <= limit; t++) {
-        step(g, &st);
-        store_logical(g, &st, x);
+        step(&m, x);
         if (memcmp(x, y, (size_t)g->k * 8) == 0) return t;
     }
     return 0;
@@ -619,15 +653,15 @@ int orc_tuple_counts(const orc_gen *g, int d, uint32_t *counts)
     if (n > 32 || d * g->w > 32) return -1;
     const u64 nstates = (u64)1 << n;
     memset(counts, 0, ((size_t)1 << (d * g->w)) * sizeof(uint32_t));
+    engine m;
+    engine_init(g, &m);
     u64 x[ORC_MAXK];
     for (u64 v = 0; v < nstates; v++) {
         for (int j = 0; j < g->k; j++) x[j] = (v >> (j * g->w)) & wmask(g->w);
-        orc_state st;
-        load_logical(g, x, &st);
         u64 idx = 0;
         for (int t = 0; t < d; t++) {
-            idx |= output(g, &st) << (t * g->w);
-            step(g, &st);
+            idx |= output(g, x) << (t * g->w);
+            step(&m, x);
         }
         counts[idx]++;
     }

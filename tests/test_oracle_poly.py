@@ -182,6 +182,44 @@ def test_charpoly_weights_match_table():
         assert bin(p).count("1") == int(wt), eng
 
 
+@pytest.mark.parametrize("engine,old,new", [
+    ("xoshiro256+", '{"I", "I", "Sa", "Rb"},', '{"I", "I", "I", "Rb"},'),
+    ("xoshiro256+", '{"I", "0", "0",  "Rb"},', '{"0", "I", "0",  "Rb"},'),
+    ("xoshiro512+", '{"0", "0", "0", "I", "0", "0", "I",  "Rb"},',
+     '{"0", "0", "0", "I", "0", "0", "0",  "Rb"},'),
+    ("xoroshiro128+", 'return "Sb+I";', 'return "Sb";'),
+    ("xoroshiro1024+", 'return "Ra+Sb+I";', 'return "Ra+I";'),
+    ("xoroshiro1024+", "j == i - 1) return", "j == i) return")])
+def test_planted_block_mistakes_fail_the_table_pins(tmp_path, engine, old, new):
+    # a block of the transition matrix mistyped in a copy of the oracle must
+    # fail the pins of Table tab:par64: degree n, the printed weight of p(x),
+    # irreducibility (a full-period engine)
+    import ctypes
+    import subprocess
+    src = open(O._SRC).read()
+    assert src.count(old) == 1
+    path = tmp_path / "orc_planted.c"
+    path.write_text(src.replace(old, new))
+    lib = tmp_path / "liborc_planted.so"
+    subprocess.check_call(["gcc", "-O2", "-std=c11", "-shared", "-fPIC", "-o", str(lib), str(path),
+                           "-lpthread"])
+    L = ctypes.CDLL(str(lib))
+    u64p = ctypes.POINTER(ctypes.c_uint64)
+    L.orc_charpoly.argtypes = [ctypes.POINTER(O._Gen), u64p, u64p]
+    L.orc_charpoly.restype = ctypes.c_long
+    g = O.GEN64[engine]
+    x0 = O.splitmix_fill(1, g.k)
+    out = np.zeros(g.n // 64 + 1, dtype=np.uint64)
+    cs = g.c_struct()
+    deg = L.orc_charpoly(ctypes.byref(cs), x0.ctypes.data_as(u64p), out.ctypes.data_as(u64p))
+    p = sum(int(w) << (64 * i) for i, w in enumerate(out.tolist()))
+    weights = {r[0]: int(r[4]) for r in read_golden("tab_par64.txt")}
+    row = {"xoshiro256+": "xoshiro256", "xoshiro512+": "xoshiro512", "xoroshiro128+": "xoroshiro128",
+           "xoroshiro1024+": "xoroshiro1024"}[engine]
+    passes = deg == g.n and bin(p).count("1") == weights[row] and rabin_irreducible_pow2(p)
+    assert not passes
+
+
 def test_charpoly_annihilates_the_matrix_sequence():
     # p(M) = 0: sum_i p_i (x M^i) = 0 for any x, on the state as a whole
     # (not only on the bit BM was run on)

@@ -157,11 +157,79 @@ def test_splitmix_gamma_is_odd_integer_nearest_2_64_over_phi():
     assert O.splitmix_gamma() == nearest
 
 
-def test_splitmix_finalizer_is_a_bijection_on_samples():
-    # distinct counters give distinct outputs (an equidistributed generator,
-    # Section "Choosing a generator"); checked on a window of counters
-    vals = {O.splitmix_mix(i * 0x9E3779B97F4A7C15 & ((1 << 64) - 1)) for i in range(20000)}
-    assert len(vals) == 20000
+# The SplitMix64 finalizer as the SplitMix publication states it (Steele, Lea
+# and Flood, OOPSLA 2014: xor-shift 30, multiply, xor-shift 27, multiply,
+# xor-shift 31).  The inverse below is derived here, independently of the
+# oracle's code: each xor-shift is undone by iterating it, each multiplication
+# by the multiplicative inverse modulo 2^64.
+MIX_SHIFTS = (30, 27, 31)
+MIX_MULTS = (0xBF58476D1CE4E5B9, 0x94D049BB133111EB)
+M64 = (1 << 64) - 1
+
+
+def _unxorshift(y, s):
+    # y = z ^ (z >> s)  =>  z = y ^ (y >> s) ^ (y >> 2s) ^ ...
+    z, t = y, y >> s
+    while t:
+        z ^= t
+        t >>= s
+    return z
+
+
+def _unmix(y):
+    s1, s2, s3 = MIX_SHIFTS
+    m1, m2 = MIX_MULTS
+    z = _unxorshift(y, s3)
+    z = (z * pow(m2, -1, 1 << 64)) & M64
+    z = _unxorshift(z, s2)
+    z = (z * pow(m1, -1, 1 << 64)) & M64
+    return _unxorshift(z, s1)
+
+
+def _round_trip_fails(mix, samples):
+    return [z for z in samples if _unmix(mix(z)) != z]
+
+
+def _samples(n=2000):
+    rng = np.random.default_rng(20140)
+    return [0, 1, M64, 1 << 63] + [int(v) for v in rng.integers(0, 2**64, n, dtype=np.uint64)]
+
+
+def test_splitmix_finalizer_inverts_on_random_inputs():
+    # Seeding, Section "Choosing a generator": the finalizer is a bijection of
+    # 64-bit words (so distinct counters give distinct outputs); its inverse,
+    # built from the publication's shifts and multipliers, undoes the oracle's
+    # finalizer on every sample.
+    assert _round_trip_fails(O.splitmix_mix, _samples()) == []
+    # and the inverse is a true inverse of the publication's finalizer
+    def mix_here(z):
+        z = ((z ^ (z >> 30)) * MIX_MULTS[0]) & M64
+        z = ((z ^ (z >> 27)) * MIX_MULTS[1]) & M64
+        return z ^ (z >> 31)
+    assert all(mix_here(_unmix(z)) == z for z in _samples(200))
+
+
+@pytest.mark.parametrize("old,new", [
+    ("z >> 30", "z >> 29"), ("z >> 27", "z >> 28"), ("z >> 31", "z >> 32"),
+    ("0xbf58476d1ce4e5b9ULL", "0xbf58476d1ce4e5bbULL"),
+    ("0x94d049bb133111ebULL", "0x94d049bb133111e9ULL")])
+def test_one_constant_edit_of_the_finalizer_fails_the_inversion(tmp_path, old, new):
+    # a planted mistake in a copy of the oracle: one shift or multiplier of
+    # the finalizer changed (the multiplier stays odd, the map stays a
+    # bijection) must make the inversion above fail
+    import ctypes
+    import subprocess
+    src = open(O._SRC).read()
+    assert src.count(old) == 1
+    path = tmp_path / "orc_planted.c"
+    path.write_text(src.replace(old, new))
+    lib = tmp_path / "liborc_planted.so"
+    subprocess.check_call(["gcc", "-O2", "-std=c11", "-shared", "-fPIC", "-o", str(lib), str(path),
+                           "-lpthread"])
+    L = ctypes.CDLL(str(lib))
+    L.orc_splitmix_mix.argtypes = [ctypes.c_uint64]
+    L.orc_splitmix_mix.restype = ctypes.c_uint64
+    assert len(_round_trip_fails(L.orc_splitmix_mix, _samples(200))) > 150
 
 
 def test_seeded_states_are_never_all_zero():
