@@ -71,16 +71,36 @@ def profiled_traffic() -> int | None:
     return int(fields["traffic_bytes_per_launch"])
 
 
+# Worker threads for the CPU oracle: the host threads this process may use,
+# at most 16 (a one-GPU machine's share of the host CPU, whatever nproc shows).
+CPU_THREAD_CAP = 16
+
+
+def host_cpu() -> dict:
+    """nproc, the usable host threads, the cap applied and the CPU model."""
+    model = None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    usable = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    return {"nproc": os.cpu_count(), "usable_threads": usable, "thread_cap": CPU_THREAD_CAP,
+            "threads": max(1, min(usable, CPU_THREAD_CAP)), "cpu_model": model}
+
+
 def cpu_baseline(batch: int, N: int, seconds: float = 15.0) -> dict:
     """The oracle (plain serial C, threaded over streams only) on a bounded
     sample of the same workload: for each of the eight generators in turn,
     batches of `batch` streams of the seed-1 chain, N outputs each, as uint64
     and as doubles, until `seconds` of host time are spent, on all the host
-    threads available (at most 16); then the same on one thread for a third
-    of the time."""
+    threads available up to CPU_THREAD_CAP; then the same on one thread for a
+    third of the time."""
     import oracle as O
-    nth = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
-    nth = max(1, min(nth, 16))
+    host = host_cpu()
+    nth = host["threads"]
     chains = {name: O.stream_chain(O.GEN64[name], 1, batch) for name in SWEEP}
 
     def run(threads: int, budget: float):
@@ -99,7 +119,7 @@ def cpu_baseline(batch: int, N: int, seconds: float = 15.0) -> dict:
 
     outs, rounds, dt = run(nth, seconds)
     outs1, rounds1, dt1 = run(1, seconds / 3)
-    return {"value": outs / dt, "unit": "outputs/s", "cores": nth, "kind": "oracle",
+    return {"value": outs / dt, "unit": "outputs/s", "cores": nth, "kind": "oracle", "host": host,
             "sample": f"{rounds} round(s) of 8 generators x {batch} streams x {N} outputs x "
                       f"(u64 + f64) from the seed-1 chains; {outs:.3g} outputs in {dt:.1f} s",
             "value_1thread": outs1 / dt1,
@@ -120,8 +140,7 @@ def cpu_per_config(budget: float = 3.0) -> dict:
     import oracle as O
     from paper_1805_01407_amd import workloads as W
     from paper_1805_01407_amd.binding import VARIANT_IDS
-    nth = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
-    nth = max(1, min(nth, 16))
+    nth = host_cpu()["threads"]
     out = {"cores": nth}
 
     g = O.GEN64["xoshiro256**"]
@@ -177,7 +196,7 @@ def cpu_per_config(budget: float = 3.0) -> dict:
     return out
 
 
-def batched_section(P, torch, stream, launches: int = 3) -> dict:
+def batched_section(P, torch, stream, launches: int = 3, forms=("graph", "plain")) -> dict:
     """The batched-requests workload (10,000 requests, generator uniform over
     the eight swept variants, lengths log-uniform in [1, 2^24), 30% doubles):
     one persistent launch replayed from a hipGraph, against the plain form (one
@@ -191,8 +210,10 @@ def batched_section(P, torch, stream, launches: int = 3) -> dict:
                            arena.data_ptr() + 8 * w["offset"])
     total = int(w["n"].sum())
     out = {"requests": len(w["n"]), "outputs": total}
-    for label, mode, reps in (("batched_graph", P.SLRNG_BATCH_GRAPH, launches),
-                              ("plain_per_request", P.SLRNG_BATCH_PLAIN, 1)):
+    chosen = [(label, mode, reps) for form, label, mode, reps in
+              (("graph", "batched_graph", P.SLRNG_BATCH_GRAPH, launches),
+               ("plain", "plain_per_request", P.SLRNG_BATCH_PLAIN, 1)) if form in forms]
+    for label, mode, reps in chosen:
         t0 = time.perf_counter()
         b = P.slrng_batch_plan(reqs, P.slrng_batch_default_opts(mode=mode))
         plan_ms = (time.perf_counter() - t0) * 1e3
@@ -215,6 +236,10 @@ def batched_section(P, torch, stream, launches: int = 3) -> dict:
                       "latency_p50_ms": round(float(np.percentile(lat, 50)), 3),
                       "latency_p99_ms": round(float(np.percentile(lat, 99)), 3),
                       "plan_ms": round(plan_ms, 1)}
+    # a plain copy of known size inside the arena, for scaling the hardware
+    # memory counters of a profiled run of this section
+    P.slrng_calib_copy(arena.data_ptr() + (4 << 30), arena.data_ptr(), 4 << 30, stream)
+    torch.cuda.synchronize()
     del arena
     torch.cuda.empty_cache()
     return out
@@ -461,36 +486,14 @@ def serving_section(P, seconds: float) -> dict:
     return out
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=8)
-    ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--streams", type=int, default=65536)
-    ap.add_argument("--n", type=int, default=65536)
-    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--no-batch", action="store_true", help="skip the batched-requests section")
-    ap.add_argument("--serve-seconds", type=float, default=10.0,
-                    help="length of the serving trace (0 skips the serving section)")
-    ap.add_argument("--cpu-streams", type=int, default=512, help="streams per oracle batch")
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
-    args = ap.parse_args()
+SECTIONS = ["sweep", "small", "jump", "gen32", "lincomp", "batch", "serve", "cpu"]
 
-    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only (the streams are independent and "
-              "would shard by stream range with no exchange); run with --gpus 1",
-              file=sys.stderr)
-        sys.exit(2)
 
-    import numpy as np
-    import torch
-
-    import paper_1805_01407_amd as P
-
-    dev = torch.device("cuda:0")
-    torch.cuda.set_device(dev)
-    S, N = args.streams, args.n
-    stream = torch.cuda.current_stream()
+def sweep_section(P, torch, stream, S: int, N: int, steps: int, warmup: int) -> dict:
+    """The headline: `steps` timed steps of the full family sweep (after
+    `warmup` untimed ones), HIP events around every generation launch, then
+    the fill kernel's rate into each of the two sweep buffers and a copy of
+    known size (for scaling the hardware memory counters)."""
     placement = placement_section(P, torch, stream, S, N)
     # output memory from the library's allocator: virtually contiguous, its
     # physical pages spread over the HBM (compact placement caps stores lower)
@@ -516,39 +519,49 @@ def main():
                     e1.record(stream)
                     gen_events.append((e0, e1))
 
-    for k in range(args.warmup):
+    for k in range(warmup):
         step(k, False)
     torch.cuda.synchronize()
 
     t0 = time.perf_counter()
-    for k in range(args.steps):
+    for k in range(steps):
         step(k, True)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
 
     outputs_per_step = len(SWEEP) * 2 * S * N
-    value = outputs_per_step * args.steps / dt
     durs = [a.elapsed_time(b) for a, b in gen_events]  # ms
     avg_ms = sum(durs) / len(durs)
     bytes_per_launch = 8 * S * N
-    achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
 
-    # write ceiling of the same store path, same size
-    for _ in range(2):
-        P.slrng_calib_write(buf_u.data_ptr(), bytes_per_launch, stream)
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record(stream)
-    reps = 5
-    for _ in range(reps):
-        P.slrng_calib_write(buf_u.data_ptr(), bytes_per_launch, stream)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    ceiling = bytes_per_launch * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    # write ceiling of each sweep buffer: the fill kernel (16-byte stores,
+    # grid-stride), same bytes, into the same memory
+    def fill_rate(buf, reps: int = 5) -> float:
+        for _ in range(2):
+            P.slrng_calib_write(buf.data_ptr(), bytes_per_launch, stream)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            P.slrng_calib_write(buf.data_ptr(), bytes_per_launch, stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return round(bytes_per_launch * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9, 1)
 
-    per_variant = {}
+    ceilings = {"u64_buffer": fill_rate(buf_u), "f64_buffer": fill_rate(buf_f)}
+
+    # launch j of the timed steps: generator (j // 2) % 8, kind j % 2
+    per_variant, per_kind = {}, {}
     for i, name in enumerate(SWEEP):
         ds = [durs[j] for j in range(len(durs)) if (j // 2) % len(SWEEP) == i]
         per_variant[name] = round(bytes_per_launch / (sum(ds) / len(ds) * 1e-3) / 1e9, 1)
+        per_kind[name] = {}
+        for kk, label in ((0, "u64"), (1, "f64")):
+            dk = [durs[j] for j in range(len(durs)) if (j // 2) % len(SWEEP) == i and j % 2 == kk]
+            per_kind[name][label] = round(bytes_per_launch / (sum(dk) / len(dk) * 1e-3) / 1e9, 1)
+    per_buffer = {}
+    for kk, label in ((0, "u64_buffer"), (1, "f64_buffer")):
+        dk = [durs[j] for j in range(len(durs)) if j % 2 == kk]
+        per_buffer[label] = round(bytes_per_launch / (sum(dk) / len(dk) * 1e-3) / 1e9, 1)
 
     # a plain copy of known size, for scaling the hardware memory counters
     copy_bytes = 4 << 30
@@ -559,25 +572,77 @@ def main():
         h.close()
     del buf_u, buf_f
     torch.cuda.empty_cache()
-    small = small_case_section(P, torch, stream)
-    positioned = positioning_section(P, torch, stream)
-    gen32 = gen32_section(P, torch, stream)
-    lincomp = lincomp_section(P, torch, stream)
-    batched = None if args.no_batch else batched_section(P, torch, stream)
-    served = None if args.serve_seconds <= 0 else serving_section(P, args.serve_seconds)
+    return {"dt": dt, "outputs": outputs_per_step * steps, "avg_ms": avg_ms,
+            "achieved": bytes_per_launch / (avg_ms * 1e-3) / 1e9, "ceilings": ceilings,
+            "per_buffer": per_buffer, "placement": placement, "per_variant": per_variant,
+            "per_kind": per_kind}
 
-    cpu = None if args.no_cpu else cpu_baseline(args.cpu_streams, N, args.cpu_seconds)
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=8)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--streams", type=int, default=65536)
+    ap.add_argument("--n", type=int, default=65536)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched-requests section")
+    ap.add_argument("--serve-seconds", type=float, default=60.0,
+                    help="length of the serving trace (0 skips the serving section)")
+    ap.add_argument("--cpu-streams", type=int, default=512, help="streams per oracle batch")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--sections", default=",".join(SECTIONS),
+                    help="comma-separated sections to run (default: all): " + ",".join(SECTIONS))
+    ap.add_argument("--batch-forms", default="graph,plain",
+                    help="forms of the batched section: graph (one persistent launch) and/or plain")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only (the streams are independent and "
+              "would shard by stream range with no exchange); run with --gpus 1",
+              file=sys.stderr)
+        sys.exit(2)
+    sections = set(args.sections.split(","))
+    unknown = sections - set(SECTIONS)
+    if unknown:
+        print(f"bench.py: unknown sections {sorted(unknown)}", file=sys.stderr)
+        sys.exit(2)
+    if args.no_cpu:
+        sections.discard("cpu")
+    if args.no_batch:
+        sections.discard("batch")
+    if args.serve_seconds <= 0:
+        sections.discard("serve")
+
+    import torch
+
+    import paper_1805_01407_amd as P
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    S, N = args.streams, args.n
+    stream = torch.cuda.current_stream()
+    sw = sweep_section(P, torch, stream, S, N, args.steps, args.warmup) if "sweep" in sections else None
+    small = small_case_section(P, torch, stream) if "small" in sections else None
+    positioned = positioning_section(P, torch, stream) if "jump" in sections else None
+    gen32 = gen32_section(P, torch, stream) if "gen32" in sections else None
+    lincomp = lincomp_section(P, torch, stream) if "lincomp" in sections else None
+    batched = batched_section(P, torch, stream, forms=args.batch_forms.split(",")) \
+        if "batch" in sections else None
+    served = serving_section(P, args.serve_seconds) if "serve" in sections else None
+
+    cpu = cpu_baseline(args.cpu_streams, N, args.cpu_seconds) if "cpu" in sections else None
     if cpu is not None:
         cpu["per_config"] = cpu_per_config()
 
     out = {
         "metric": "64-bit outputs/s (uint64 + [0,1) doubles), full family sweep",
-        "value": value,
+        "value": sw["outputs"] / sw["dt"] if sw else None,
         "unit": "outputs/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": dt / args.steps * 1e3,
+        "ms_per_step": sw["dt"] / args.steps * 1e3 if sw else None,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -586,12 +651,14 @@ def main():
         "config": {"workload": "full family sweep: 8 generators x 65,536 streams x 65,536 "
                                "outputs, uint64 + doubles, seeds 1..8",
                    "streams": S, "outputs_per_stream": N, "generators": SWEEP},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": profiled_traffic()},
-        "write_ceiling_GBs": ceiling,
-        "placement": placement,
-        "gen_GBs_per_generator": per_variant,
+        "roofline": {"bound": "hbm", "achieved": sw["achieved"], "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": sw["achieved"] / HBM_PEAK_GBS,
+                     "traffic": profiled_traffic()} if sw else None,
+        "write_ceiling_GBs": sw["ceilings"] if sw else None,
+        "gen_GBs_per_buffer": sw["per_buffer"] if sw else None,
+        "placement": sw["placement"] if sw else None,
+        "gen_GBs_per_generator": sw["per_variant"] if sw else None,
+        "gen_GBs_per_generator_kind": sw["per_kind"] if sw else None,
         "small_case": small,
         "jump_ahead_at_scale": positioned,
         "generators_32bit": gen32,
@@ -600,6 +667,8 @@ def main():
         "serving": served,
         "cpu_baseline": cpu,
     }
+    if sorted(sections) != sorted(SECTIONS):
+        out["sections"] = sorted(sections)
     print(json.dumps(out), flush=True)
 
 

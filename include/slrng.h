@@ -368,23 +368,42 @@ int slrng_batch_run(const slrng_request *reqs, size_t n_reqs, const slrng_batch_
  * seed, n_streams): the SplitMix64 base jumped j times.  Every request takes
  * the next positions of its stream in admission order, so request r on stream
  * j receives outputs pos_r .. pos_r + n_r - 1 of that stream, where pos_r is
- * the total length of the earlier requests on j: its values do not depend on
- * what else is in flight (the same request alone gives the same values).
+ * the stream's head when r was admitted: the total length of the earlier
+ * requests on j plus any slrng_server_advance of j (positions are 128-bit,
+ * modulo 2^128).  Its values do not depend on what else is in flight (the
+ * same request alone gives the same values).  The start state s_j M^pos_r is
+ * computed on the device from the digits of pos_r (jump functions, Section
+ * "Combining linear engines and scramblers"), with matrices M^(d 2^(b l))
+ * built once per device and engine when the first server of that engine is
+ * created (32 MiB for xoshiro256, 64 MiB for xoroshiro1024); no polynomial
+ * arithmetic is done per request.
  *
  * Admission (slrng_server_submit) reserves 8 n bytes of the device output
  * arena (budget_bytes).  When the arena is full it blocks until space is
  * released, or returns SLRNG_EAGAIN with SLRNG_SUBMIT_NONBLOCK.  A worker
  * thread batches every pending request into one iteration (request-state
  * kernel + persistent generation kernel) and launches it on one of
- * `inflight` HIP streams while earlier iterations still run; a completion
- * thread stamps latencies (submit to completion) when an iteration's event
- * completes.  Outputs are read from the arena pointer that poll/wait return,
- * then released (slrng_server_release), or released automatically at
- * completion with SLRNG_SUBMIT_AUTORELEASE (throughput runs).
+ * `inflight` HIP streams while earlier iterations still run; one completion
+ * thread per stream stamps latencies when its iteration's event completes, so
+ * iterations complete in any order.  Latency runs from the request's arrival
+ * (the submit call, before any wait for arena space; for slrng_server_replay
+ * the scheduled arrival time) to the completion of its iteration.  Outputs are
+ * read from the arena pointer that poll/wait return, then released
+ * (slrng_server_release), or released automatically at completion with
+ * SLRNG_SUBMIT_AUTORELEASE (throughput runs).
  *
  * slrng_server_poll: 1 when done, 0 while pending, SLRNG_EHIP if its iteration
  *   failed, SLRNG_EINVAL for an unknown or released ticket; fills the output
- *   pointer and the stream position.  slrng_server_wait: blocks until done.
+ *   pointer and the stream position (its low 64 bits).  slrng_server_wait:
+ *   blocks until done.
+ * slrng_server_advance: moves stream j's head by steps_hi 2^64 + steps_lo
+ *   (requests admitted later start that much further; earlier ones keep their
+ *   positions).  EINVAL for a bad stream id.
+ * slrng_server_intervals: the generation kernels' device intervals, one per
+ *   iteration in completion order (ms from a reference event of the server),
+ *   written up to `cap` entries; *count = the number recorded since creation
+ *   or the last reset_stats.  Iterations on different HIP streams overlap on
+ *   the device when one's interval starts before another's ends.
  * slrng_server_release: frees a completed request's arena range (EAGAIN while
  *   it is still pending or in flight).
  * slrng_server_drain: waits until every submitted request has completed.
@@ -440,6 +459,9 @@ int slrng_server_get_stats(slrng_server *sv, slrng_server_stats *out);
 int slrng_server_reset_stats(slrng_server *sv);
 int slrng_server_replay(slrng_server *sv, const double *t_arrival_s, const uint32_t *stream_ids,
                         const uint64_t *n, const int32_t *kinds, size_t count);
+int slrng_server_advance(slrng_server *sv, uint32_t stream_id, uint64_t steps_hi, uint64_t steps_lo);
+int slrng_server_intervals(slrng_server *sv, double *kernel_start_ms, double *kernel_end_ms, uint64_t cap,
+                           uint64_t *count);
 int slrng_server_destroy(slrng_server *sv);
 
 #ifdef __cplusplus

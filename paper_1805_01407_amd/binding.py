@@ -144,6 +144,9 @@ def lib():
         "slrng_server_replay": ([vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_uint32),
                                  u64p, ctypes.POINTER(ctypes.c_int32), ctypes.c_size_t], i32),
         "slrng_server_destroy": ([vp], i32),
+        "slrng_server_advance": ([vp, ctypes.c_uint32, u64, u64], i32),
+        "slrng_server_intervals": ([vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
+                                    u64, u64p], i32),
         "slrng_calib_write": ([vp, u64, vp], i32),
         "slrng_calib_copy": ([vp, vp, u64, vp], i32),
         "slrng_output_alloc": ([u64, ctypes.POINTER(vp)], i32),
@@ -575,6 +578,27 @@ def slrng_server_replay(sv: int, t_arrival_s, stream_ids, n, kinds) -> None:
 
 def slrng_server_destroy(sv: int) -> None:
     _check(lib().slrng_server_destroy(sv), "slrng_server_destroy")
+
+
+def slrng_server_advance(sv: int, stream_id: int, steps: int) -> None:
+    """Move a resident stream's head by `steps` (any value below 2^128)."""
+    steps %= 1 << 128
+    _check(lib().slrng_server_advance(sv, stream_id, steps >> 64, steps & ((1 << 64) - 1)),
+           "slrng_server_advance")
+
+
+def slrng_server_intervals(sv: int) -> np.ndarray:
+    """The generation kernels' device intervals, shape (iterations, 2), in ms."""
+    cnt = ctypes.c_uint64()
+    _check(lib().slrng_server_intervals(sv, None, None, 0, ctypes.byref(cnt)), "slrng_server_intervals")
+    n = cnt.value + 64  # room for iterations completing meanwhile
+    a = np.zeros(n, dtype=np.float64)
+    b = np.zeros(n, dtype=np.float64)
+    dp = ctypes.POINTER(ctypes.c_double)
+    _check(lib().slrng_server_intervals(sv, a.ctypes.data_as(dp), b.ctypes.data_as(dp), n, ctypes.byref(cnt)),
+           "slrng_server_intervals")
+    m = min(n, cnt.value)
+    return np.stack([a[:m], b[:m]], axis=1)
 
 
 # ---------------------------------------------------------------- object wrapper

@@ -79,6 +79,27 @@ int chunk_table(int device, int engine, uint64_t C, uint32_t need, ChunkTable *o
   return SLRNG_OK;
 }
 
+// The same entries computed into host memory (word-major, n entries).
+void chunk_table_host(int engine, uint64_t C, uint32_t n, std::vector<uint64_t> &h) {
+  const Field &f = engine_field(engine);
+  const int W = f.n / 64;
+  Poly step, cur;
+  uint64_t J[1] = {C};
+  f.xpow(J, 1, step);
+  cur.clear();
+  cur.w[0] = 1;
+  h.assign((size_t)W * n, 0);
+  for (uint32_t j = 0; j < n; j++) {
+    for (int w = 0; w < W; w++) h[(size_t)w * n + j] = cur.w[w];
+    Poly nx;
+    f.mulmod(cur, step, nx);
+    cur = nx;
+  }
+}
+
+std::mutex g_dr_mu;
+std::map<std::pair<int, int>, DigitRows> g_dr;  // (device, engine)
+
 // Relative cost of one output per variant (engine and scrambler work), for
 // ordering tiles heaviest first.
 uint64_t output_cost(int v) { return (v >= 6 && v <= 8) ? 3 : 2; }
@@ -87,7 +108,54 @@ uint64_t output_cost(int v) { return (v >= 6 && v <= 8) ? 3 : 2; }
 
 namespace slrng {
 
-int batch_grid_blocks(const slrng_batch_opts &o, int device, unsigned *blocks) {
+int digit_rows(int device, int variant, DigitRows *out) {
+  std::lock_guard<std::mutex> g(g_dr_mu);
+  const int engine = variant_engine(variant);
+  DigitRows &t = g_dr[std::make_pair(device, engine)];
+  if (t.dev) {
+    *out = t;
+    return SLRNG_OK;
+  }
+  const Field &f = engine_field(engine);
+  const int K = f.n / 64;
+  const int bits = K <= 4 ? 8 : 4;
+  const int levels = 128 / bits;
+  const unsigned per = 1u << bits, entries = (unsigned)levels * per;
+  // entry l 2^bits + d: x^(d 2^(bits l)) mod p, as powers of x^(2^(bits l))
+  std::vector<uint64_t> h((size_t)entries * 16, 0);
+  for (int l = 0; l < levels; l++) {
+    uint64_t J[2] = {0, 0};
+    J[(bits * l) >> 6] = 1ull << ((bits * l) & 63);
+    Poly base, cur;
+    f.xpow(J, 2, base);
+    cur.clear();
+    cur.w[0] = 1;
+    for (unsigned d = 0; d < per; d++) {
+      for (int w = 0; w < K; w++) h[((size_t)l * per + d) * 16 + w] = cur.w[w];
+      Poly nx;
+      f.mulmod(cur, base, nx);
+      cur = nx;
+    }
+  }
+  uint64_t *polys = nullptr, *rows = nullptr;
+  HIPCHK(hipMalloc(&polys, h.size() * 8));
+  hipError_t e = hipMalloc(&rows, (size_t)entries * f.n * K * 8);
+  if (e == hipSuccess) e = hipMemcpy(polys, h.data(), h.size() * 8, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = launch_digit_rows(variant, polys, entries, rows, nullptr);
+  if (e == hipSuccess) e = hipStreamSynchronize(nullptr);
+  (void)hipFree(polys);
+  if (e != hipSuccess) {
+    if (rows) (void)hipFree(rows);
+    return e == hipErrorOutOfMemory ? SLRNG_ENOMEM : hip_fail(e);
+  }
+  t.dev = rows;
+  t.bits = bits;
+  t.levels = levels;
+  *out = t;
+  return SLRNG_OK;
+}
+
+int batch_grid_blocks(const slrng_batch_opts &o, int device, unsigned *blocks, int variant) {
   int cus = 0;
   hipError_t e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device);
   if (e != hipSuccess) return hip_fail(e);
@@ -95,7 +163,7 @@ int batch_grid_blocks(const slrng_batch_opts &o, int device, unsigned *blocks) {
   // a persistent grid larger than what is resident at once only adds blocks
   // that start after the tiles are gone
   int per_cu = 0;
-  e = batch_resident_blocks_per_cu(o.tile, &per_cu);
+  e = batch_resident_blocks_per_cu(o.tile, &per_cu, variant);
   if (e != hipSuccess) return hip_fail(e);
   const int want = cus * wpc / (kBlock / kWave);
   const int cap = per_cu > 0 ? cus * per_cu : want;
@@ -129,8 +197,9 @@ int warm_fit_tables(int device, int variant, const slrng_batch_opts &o, uint64_t
 }
 
 int build_plan(const PlanReq *reqs, size_t n_reqs, const slrng_batch_opts &o, int device,
-               uint64_t grid_lanes, PlanHost &P, bool fit, uint64_t fit_floor) {
+               uint64_t grid_lanes, PlanHost &P, bool fit, uint64_t fit_floor, bool host_tables) {
   const bool plain = o.mode == SLRNG_BATCH_PLAIN;
+  if (plain && host_tables) return SLRNG_EINVAL;
   // chunk length per variant: the option value, rounded up to the tile and
   // raised if a request would need more than kMaxTable chunks
   uint64_t C[kNumVariants];
@@ -160,7 +229,8 @@ int build_plan(const PlanReq *reqs, size_t n_reqs, const slrng_batch_opts &o, in
     C[v] = c;
   }
   // request states: requests that start past their origin, and every request
-  // whose origin is a resident state
+  // whose origin is a resident state (those are positioned on the device from
+  // their 128-bit start, no polynomial here)
   std::vector<uint32_t> req_slot(n_reqs, kNoReqState);
   std::vector<std::vector<uint32_t>> by_var(kNumVariants);
   uint32_t nslots = 0;
@@ -254,7 +324,13 @@ int build_plan(const PlanReq *reqs, size_t n_reqs, const slrng_batch_opts &o, in
   for (int v = 0; v < kNumVariants; v++) {
     P.tab[v] = nullptr;
     P.tab_n[v] = 0;
+    P.host_tab[v].clear();
     if (!tab_need[v]) continue;
+    if (host_tables) {
+      chunk_table_host(variant_engine(v), C[v], tab_need[v], P.host_tab[v]);
+      P.tab_n[v] = tab_need[v];
+      continue;
+    }
     ChunkTable t;
     int rc = chunk_table(device, variant_engine(v), C[v], tab_need[v], &t);
     if (rc) return rc;
@@ -324,6 +400,12 @@ int build_plan(const PlanReq *reqs, size_t n_reqs, const slrng_batch_opts &o, in
       rs.seeds.push_back(reqs[r].seed);
       rs.origin_idx.push_back(reqs[r].origin_idx);
       rs.slot.push_back(req_slot[r]);
+      if (reqs[r].from_state) {
+        // positioned on the device from the digits of its 128-bit start
+        rs.pos.push_back(reqs[r].start);
+        rs.pos.push_back(reqs[r].start_hi);
+        continue;
+      }
       Poly pr;
       if (reqs[r].start) {
         uint64_t J[1] = {reqs[r].start};
@@ -354,7 +436,7 @@ struct slrng_batch {
   uint64_t *d_req_state = nullptr;
   uint64_t *d_req_seed = nullptr, *d_req_poly = nullptr;
   uint32_t *d_req_slot = nullptr;
-  unsigned *d_counter = nullptr;  // one counter per unit
+  unsigned *d_counter = nullptr;  // two counters per unit (claims, finished waves)
   std::vector<std::pair<int, ReqArgs>> req_launches;
   BatchArgs args;
   unsigned blocks = 0;
@@ -405,11 +487,9 @@ static int enqueue_unit(slrng_batch *b, const PlanUnit &u, unsigned *counter, hi
   }
   a.tiles = b->d_tiles + u.tile0;
   a.ntiles = u.ntiles;
-  a.counter = counter;
-  hipError_t e = launch_batch_reset(counter, st);
-  if (e != hipSuccess) return hip_fail(e);
+  a.counter = counter;  // zero: from the upload, then reset by each launch's last wave
   const unsigned blocks = std::min<unsigned>(b->blocks, (u.ntiles + 3) / 4);
-  e = launch_batch(a, b->opts.tile, blocks, st);
+  hipError_t e = launch_batch(a, b->opts.tile, blocks, st);
   return e == hipSuccess ? SLRNG_OK : hip_fail(e);
 }
 
@@ -425,7 +505,7 @@ static int enqueue_req_states(slrng_batch *b, hipStream_t st) {
 static int enqueue_all(slrng_batch *b, hipStream_t st) {
   int rc = enqueue_req_states(b, st);
   for (size_t i = 0; i < b->plan.units.size() && !rc; i++)
-    rc = enqueue_unit(b, b->plan.units[i], b->d_counter + (b->plan.units.size() > 1 ? i : 0), st);
+    rc = enqueue_unit(b, b->plan.units[i], b->d_counter + 2 * i, st);
   return rc;
 }
 
@@ -476,7 +556,7 @@ extern "C" int slrng_batch_plan(const slrng_request *reqs, size_t n_reqs,
     if (!rc) rc = upload((void **)&b->d_lanes, P.lanes.data(), P.lanes.size() * sizeof(LaneDesc));
     if (!rc) rc = upload((void **)&b->d_runs, P.runs.data(), P.runs.size() * sizeof(RunDesc));
     if (!rc) {
-      std::vector<unsigned> zeros(P.units.size(), 0);
+      std::vector<unsigned> zeros(2 * P.units.size(), 0);  // two counters per unit
       rc = upload((void **)&b->d_counter, zeros.data(), zeros.size() * sizeof(unsigned));
     }
     if (!rc && P.rs.nslots) {
@@ -493,6 +573,7 @@ extern "C" int slrng_batch_plan(const slrng_request *reqs, size_t n_reqs,
         ra.origin_stride = 0;
         ra.origin_idx = nullptr;
         ra.polys = b->d_req_poly + (size_t)off * 16;
+        ra.pos = nullptr;
         ra.slot = b->d_req_slot + off;
         ra.req_state = b->d_req_state;
         ra.m = P.rs.runs[k].second;
@@ -587,7 +668,7 @@ extern "C" int slrng_batch_latencies(slrng_batch *b, hipStream_t stream, double 
     } else if (!rc) {
       rc = enqueue_req_states(b, stream);
       for (size_t i = 0; i < units.size() && !rc; i++) {
-        rc = enqueue_unit(b, units[i], b->d_counter + (units.size() > 1 ? i : 0), stream);
+        rc = enqueue_unit(b, units[i], b->d_counter + 2 * i, stream);
         if (!rc) {
           hipError_t e = hipEventRecord(ev[i + 1], stream);
           if (e != hipSuccess) rc = hip_fail(e);

@@ -141,6 +141,28 @@ __device__ __forceinline__ void batch_tile(const BatchArgs &a, const TileDesc &t
   }
 }
 
+// Claims the wave's next tile into t; false when none is left.  Every wave
+// gets false exactly once (the claim counter only grows during the launch),
+// and the last wave to get it knows that no wave will claim again: it returns
+// both counters to zero for the next launch, so no reset kernel is needed
+// between launches.
+__device__ __forceinline__ bool next_tile(const BatchArgs &a, int lane, unsigned &t) {
+  unsigned v = 0;
+  if (lane == 0) v = atomicAdd(a.counter, 1u);
+  t = (unsigned)__builtin_amdgcn_readfirstlane((int)v);
+  if (t < a.ntiles) return true;
+  if (lane == 0) {
+    const unsigned waves = gridDim.x * (kBlock / kWave);
+    if (atomicAdd(a.counter + 1, 1u) == waves - 1) {
+      atomicExch(a.counter, 0u);
+      atomicExch(a.counter + 1, 0u);
+    }
+  }
+  return false;
+}
+
+// Every variant and kind: the switch on the tile's (variant, kind) is uniform
+// per wave (the tile index is read through readfirstlane).
 template <int T>
 __global__ __launch_bounds__(kBlock) void k_batch(BatchArgs a) {
   __shared__ __attribute__((aligned(16))) u64 lds_all[(kBlock / kWave) * TileGeom<T>::kWaveLds];
@@ -150,11 +172,8 @@ __global__ __launch_bounds__(kBlock) void k_batch(BatchArgs a) {
   u64 *lds = lds_all + wave * TileGeom<T>::kWaveLds;
   u64 *rowptr = rowptr_all + wave * kWave;
   unsigned *rowlen = rowlen_all + wave * kWave;
-  for (;;) {
-    unsigned t = 0;
-    if (lane == 0) t = atomicAdd(a.counter, 1u);
-    t = (unsigned)__builtin_amdgcn_readfirstlane((int)t);
-    if (t >= a.ntiles) break;  // every wave reaches this: the counter only grows
+  unsigned t = 0;
+  while (next_tile(a, lane, t)) {
     const TileDesc td = a.tiles[t];
     switch (td.variant * 2 + td.kind) {
 #define SL_CASE(V)                                                  \
@@ -169,8 +188,24 @@ __global__ __launch_bounds__(kBlock) void k_batch(BatchArgs a) {
   }
 }
 
-__global__ void k_batch_reset(unsigned *counter) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) *counter = 0;
+// The same loop for tiles of one variant (the server's): the registers of
+// the other variants' code do not count, so more waves fit on a CU.
+template <int V, int T>
+__global__ __launch_bounds__(kBlock) void k_batch1(BatchArgs a) {
+  __shared__ __attribute__((aligned(16))) u64 lds_all[(kBlock / kWave) * TileGeom<T>::kWaveLds];
+  __shared__ u64 rowptr_all[kBlock];
+  __shared__ unsigned rowlen_all[kBlock];
+  const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+  u64 *lds = lds_all + wave * TileGeom<T>::kWaveLds;
+  u64 *rowptr = rowptr_all + wave * kWave;
+  unsigned *rowlen = rowlen_all + wave * kWave;
+  unsigned t = 0;
+  while (next_tile(a, lane, t)) {
+    const TileDesc td = a.tiles[t];
+    if (td.kind) batch_tile<V, 1, T>(a, td, lds, rowptr, rowlen, lane);
+    else batch_tile<V, 0, T>(a, td, lds, rowptr, rowlen, lane);
+    wave_sync();
+  }
 }
 
 template <int V>
@@ -261,21 +296,139 @@ __global__ __launch_bounds__(kBlock) void k_req_state_basis(ReqArgs a, const u64
   }
 }
 
-hipError_t launch_batch(const BatchArgs &a, int tile, unsigned blocks, hipStream_t st) {
+// Rows of the digit matrices: rows[(e n + i) k + w] = word w of e_i M^(J_e),
+// where e_i is the state whose only set bit is bit i (word i / 64, bit i % 64,
+// logical order) and x^(J_e) mod p is polys[e * 16 ..] (one lane per row).
+template <int V>
+__global__ __launch_bounds__(kBlock) void k_digit_rows(const u64 *__restrict__ polys,
+                                                       u64 *__restrict__ rows) {
+  constexpr int K = Params<V>::k;
+  constexpr int N = 64 * K;
+  const unsigned i = blockIdx.x * kBlock + threadIdx.x;
+  if (i - (threadIdx.x % kWave) >= (unsigned)N) return;  // uniform per wave (64 divides N)
+  const u64 e = blockIdx.y;
+  u64 s[K];
+#pragma unroll
+  for (int w = 0; w < K; w++) s[w] = (w == (int)(i / 64)) ? (u64)1 << (i % 64) : 0;
+  jump_uniform<V>(s, polys + e * 16);
+#pragma unroll
+  for (int w = 0; w < K; w++) rows[(e * N + i) * K + w] = s[w];
+}
+
+// Request start states from a 128-bit position, all on the device: s M^pos is
+// the origin s multiplied, for every nonzero digit d_l of pos in radix 2^bits,
+// by the matrix M^(d_l 2^(bits l)), whose rows are in `rows` (entry
+// l 2^bits + d_l).  A product s M^J is the xor of the rows selected by the set
+// bits of s: one wave per request, lane `lane` takes rows lane, lane + 64, ...
+// (consecutive lanes read consecutive rows), then an xor reduction across the
+// wave leaves the product in every lane for the next digit.
+template <int V>
+__global__ __launch_bounds__(kBlock) void k_req_state_digits(ReqArgs a, const u64 *__restrict__ rows,
+                                                             int bits, int levels) {
+  constexpr int K = Params<V>::k;
+  constexpr int N = 64 * K;
+  const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+  const unsigned r = blockIdx.x * (kBlock / kWave) + wave;
+  if (r >= a.m) return;  // uniform per wave
+  u64 s[K];
+  if (a.origin_state) {
+    const u64 j = a.origin_idx[r];
+#pragma unroll
+    for (int w = 0; w < K; w++) s[w] = a.origin_state[(u64)w * a.origin_stride + j];
+  } else {
+    splitmix64_fill<K>(a.seeds[r], s);
+  }
+  const u64 pos[2] = {a.pos[2 * (u64)r], a.pos[2 * (u64)r + 1]};
+  const u64 dmask = ((u64)1 << bits) - 1;
+  for (int l = 0; l < levels; l++) {
+    const int b0 = l * bits;  // bits divides 64: a digit never straddles the two words
+    const unsigned d = (unsigned)((pos[b0 >> 6] >> (b0 & 63)) & dmask);
+    if (!d) continue;  // uniform
+    const u64 *R = rows + ((((u64)l << bits) + d) * N) * K;
+    unsigned lo[K], hi[K];
+#pragma unroll
+    for (int w = 0; w < K; w++) lo[w] = hi[w] = 0;
+#pragma unroll
+    for (int q = 0; q < K; q++) {
+      if ((s[q] >> lane) & 1) {
+        const u64 *row = R + (u64)(64 * q + lane) * K;
+#pragma unroll
+        for (int w = 0; w < K; w++) {
+          const u64 v = row[w];
+          lo[w] ^= (unsigned)v;
+          hi[w] ^= (unsigned)(v >> 32);
+        }
+      }
+    }
+#pragma unroll
+    for (int off = kWave / 2; off > 0; off >>= 1) {
+#pragma unroll
+      for (int w = 0; w < K; w++) {
+        lo[w] ^= (unsigned)__shfl_xor((int)lo[w], off);
+        hi[w] ^= (unsigned)__shfl_xor((int)hi[w], off);
+      }
+    }
+#pragma unroll
+    for (int w = 0; w < K; w++) s[w] = ((u64)hi[w] << 32) | lo[w];
+  }
+  if (lane == 0) {
+#pragma unroll
+    for (int w = 0; w < K; w++) a.req_state[(u64)a.slot[r] * 16 + w] = s[w];
+  }
+}
+
+template <int V>
+static hipError_t batch1_v(const BatchArgs &a, int tile, unsigned blocks, hipStream_t st) {
+  if (tile == 16) hipLaunchKernelGGL((k_batch1<V, 16>), dim3(blocks), dim3(kBlock), 0, st, a);
+  else hipLaunchKernelGGL((k_batch1<V, 32>), dim3(blocks), dim3(kBlock), 0, st, a);
+  return hipGetLastError();
+}
+
+template <int V>
+static hipError_t batch1_occupancy_v(int tile, int *blocks) {
+  return tile == 16 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, k_batch1<V, 16>, kBlock, 0)
+                    : hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, k_batch1<V, 32>, kBlock, 0);
+}
+
+#define SL_DISPATCH64(v, EXPR)           \
+  switch (v) {                           \
+    case 0: return EXPR(0);              \
+    case 1: return EXPR(1);              \
+    case 2: return EXPR(2);              \
+    case 3: return EXPR(3);              \
+    case 4: return EXPR(4);              \
+    case 5: return EXPR(5);              \
+    case 6: return EXPR(6);              \
+    case 7: return EXPR(7);              \
+    case 8: return EXPR(8);              \
+    case 9: return EXPR(9);              \
+    case 10: return EXPR(10);            \
+    case 11: return EXPR(11);            \
+    case 12: return EXPR(12);            \
+    case 13: return EXPR(13);            \
+    default: return hipErrorInvalidValue; \
+  }
+
+hipError_t launch_batch(const BatchArgs &a, int tile, unsigned blocks, hipStream_t st, int variant) {
+  if (variant >= 0) {
+#define SL_B1(V) batch1_v<V>(a, tile, blocks, st)
+    SL_DISPATCH64(variant, SL_B1)
+#undef SL_B1
+  }
   if (tile == 16) hipLaunchKernelGGL(k_batch<16>, dim3(blocks), dim3(kBlock), 0, st, a);
   else hipLaunchKernelGGL(k_batch<32>, dim3(blocks), dim3(kBlock), 0, st, a);
   return hipGetLastError();
 }
 
-hipError_t batch_resident_blocks_per_cu(int tile, int *blocks) {
+hipError_t batch_resident_blocks_per_cu(int tile, int *blocks, int variant) {
+  if (variant >= 0) {
+#define SL_O1(V) batch1_occupancy_v<V>(tile, blocks)
+    SL_DISPATCH64(variant, SL_O1)
+#undef SL_O1
+  }
   return tile == 16
              ? hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, k_batch<16>, kBlock, 0)
              : hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, k_batch<32>, kBlock, 0);
-}
-
-hipError_t launch_batch_reset(unsigned *counter, hipStream_t st) {
-  hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(64), 0, st, counter);
-  return hipGetLastError();
 }
 
 template <int V>
@@ -299,30 +452,42 @@ static hipError_t req_basis_v(const ReqArgs &a, const u64 *basis, hipStream_t st
   return hipGetLastError();
 }
 
-#define SL_DISPATCH64(v, EXPR)           \
-  switch (v) {                           \
-    case 0: return EXPR(0);              \
-    case 1: return EXPR(1);              \
-    case 2: return EXPR(2);              \
-    case 3: return EXPR(3);              \
-    case 4: return EXPR(4);              \
-    case 5: return EXPR(5);              \
-    case 6: return EXPR(6);              \
-    case 7: return EXPR(7);              \
-    case 8: return EXPR(8);              \
-    case 9: return EXPR(9);              \
-    case 10: return EXPR(10);            \
-    case 11: return EXPR(11);            \
-    case 12: return EXPR(12);            \
-    case 13: return EXPR(13);            \
-    default: return hipErrorInvalidValue; \
-  }
 
 hipError_t launch_basis(int variant, const uint64_t *state, uint64_t S, uint64_t *basis,
                         hipStream_t st) {
 #define SL_B(V) basis_v<V>(state, S, basis, st)
   SL_DISPATCH64(variant, SL_B)
 #undef SL_B
+}
+
+template <int V>
+static hipError_t digit_rows_v(const u64 *polys, unsigned entries, u64 *rows, hipStream_t st) {
+  constexpr int N = 64 * Params<V>::k;
+  dim3 grid((N + kBlock - 1) / kBlock, entries);
+  hipLaunchKernelGGL((k_digit_rows<V>), grid, dim3(kBlock), 0, st, polys, rows);
+  return hipGetLastError();
+}
+
+template <int V>
+static hipError_t req_digits_v(const ReqArgs &a, const u64 *rows, int bits, int levels, hipStream_t st) {
+  dim3 grid((a.m + (kBlock / kWave) - 1) / (kBlock / kWave));
+  hipLaunchKernelGGL((k_req_state_digits<V>), grid, dim3(kBlock), 0, st, a, rows, bits, levels);
+  return hipGetLastError();
+}
+
+hipError_t launch_digit_rows(int variant, const uint64_t *polys, unsigned entries, uint64_t *rows,
+                             hipStream_t st) {
+#define SL_DR(V) digit_rows_v<V>(polys, entries, rows, st)
+  SL_DISPATCH64(variant, SL_DR)
+#undef SL_DR
+}
+
+hipError_t launch_req_state_digits(int variant, const ReqArgs &a, const uint64_t *rows, int bits,
+                                   int levels, hipStream_t st) {
+  if (a.m == 0) return hipSuccess;
+#define SL_RD(V) req_digits_v<V>(a, rows, bits, levels, st)
+  SL_DISPATCH64(variant, SL_RD)
+#undef SL_RD
 }
 
 hipError_t launch_req_state_basis(int variant, const ReqArgs &a, const uint64_t *basis,

@@ -64,7 +64,8 @@ struct BatchArgs {
   const uint64_t *req_state;          // [r][16] start states of requests with start > 0
   const uint64_t *tab[kNumVariants];  // chunk tables, word-major: word w of entry j at [w*tab_n + j]
   uint32_t tab_n[kNumVariants];
-  unsigned *counter;                  // tile claim counter (zeroed by k_batch_reset)
+  unsigned *counter;                  // [0] tiles claimed, [1] waves finished: both zero
+                                      // at launch; the last wave to finish zeroes them
 };
 
 // Request start states: the origin of request i (SplitMix64(seeds[i]), or, when
@@ -76,23 +77,34 @@ struct ReqArgs {
   const uint64_t *origin_state;  // resident states, word-major, or null
   uint64_t origin_stride;
   const uint32_t *origin_idx;    // [m] (state origins)
-  const uint64_t *polys;         // [m][16]
+  const uint64_t *polys;         // [m][16] (host-computed jump polynomials)
+  const uint64_t *pos;           // [m][2] 128-bit positions, low word first (digit kernel)
   const uint32_t *slot;          // [m] index into req_state
   uint64_t *req_state;           // [..][16]
   uint32_t m;
 };
 
-hipError_t launch_batch(const BatchArgs &a, int tile, unsigned blocks, hipStream_t st);
-// Workgroups of the persistent kernel that fit on one CU at once (LDS and
-// registers decide).
-hipError_t batch_resident_blocks_per_cu(int tile, int *blocks);
-hipError_t launch_batch_reset(unsigned *counter, hipStream_t st);
+// The persistent kernel over all tiles: any variant (variant < 0), or the
+// kernel specialised to one variant when every tile is of that variant.
+hipError_t launch_batch(const BatchArgs &a, int tile, unsigned blocks, hipStream_t st, int variant = -1);
+// Workgroups of that kernel that fit on one CU at once (LDS and registers
+// decide).
+hipError_t batch_resident_blocks_per_cu(int tile, int *blocks, int variant = -1);
 hipError_t launch_req_state(int variant, const ReqArgs &a, hipStream_t st);
 
 // Basis states of S resident streams (word-major states): B_j[i] = s_j M^i,
 // i < n, at basis[(j n + i) k + w] (n k words per stream).
 hipError_t launch_basis(int variant, const uint64_t *state, uint64_t S, uint64_t *basis,
                         hipStream_t st);
+// Rows of digit matrices: entry e of `polys` (16 words each, x^(J_e) mod p)
+// gives rows e_i M^(J_e), i < n, at rows[(e n + i) k + w].
+hipError_t launch_digit_rows(int variant, const uint64_t *polys, unsigned entries, uint64_t *rows,
+                             hipStream_t st);
+// Request states s M^pos from 128-bit positions (a.pos) with the digit
+// matrices of radix 2^bits (`levels` digits; entry l 2^bits + d holds
+// M^(d 2^(bits l))), one wave per request; origins from origin_state or seeds.
+hipError_t launch_req_state_digits(int variant, const ReqArgs &a, const uint64_t *rows, int bits,
+                                   int levels, hipStream_t st);
 // Request states of resident-origin requests from their streams' bases (one
 // wave per request; uses origin_idx, polys, slot, req_state and m).
 hipError_t launch_req_state_basis(int variant, const ReqArgs &a, const uint64_t *basis,

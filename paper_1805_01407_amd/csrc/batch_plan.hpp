@@ -22,6 +22,7 @@ struct PlanReq {
   uint64_t seed;
   uint32_t origin_idx;
   uint64_t tag;  // caller's request index (the plain form's unit)
+  uint64_t start_hi = 0;  // state origins: upper word of the 128-bit start position
 };
 
 struct PlanUnit {
@@ -36,7 +37,8 @@ struct PlanUnit {
 struct PlanReqStates {
   std::vector<uint64_t> seeds;       // per entry (seed origins)
   std::vector<uint32_t> origin_idx;  // per entry (state origins)
-  std::vector<uint64_t> polys;       // 16 words per entry
+  std::vector<uint64_t> polys;       // 16 words per entry (seed origins: x^start mod p)
+  std::vector<uint64_t> pos;         // 2 words per entry (state origins: the 128-bit start)
   std::vector<uint32_t> slot;        // request-state slot per entry
   std::vector<std::pair<int, uint32_t>> runs;  // (variant, entries) in order
   uint32_t nslots = 0;
@@ -50,6 +52,7 @@ struct PlanHost {
   PlanReqStates rs;
   const uint64_t *tab[kNumVariants] = {nullptr};
   uint32_t tab_n[kNumVariants] = {0};
+  std::vector<uint64_t> host_tab[kNumVariants];  // with host_tables: the tables themselves
   uint64_t total_outputs = 0;
 };
 
@@ -58,16 +61,34 @@ struct PlanHost {
 // chunk length shrinks until the batch's lane-chunks cover the grid about
 // four times over, down to `fit_floor` outputs, by default the larger of 512
 // and 2n so that the per-lane jump of n steps stays amortised); `from_state`
-// requests always get a request state.  Returns SLRNG_OK or an error code.
+// requests always get a request state.  With `host_tables` the chunk tables
+// are computed into host_tab (tab_n entries each, word-major; tab stays null)
+// instead of being taken from the device cache, so that planning allocates no
+// device memory (not for the plain form: EINVAL).  Returns SLRNG_OK or an
+// error code.
 int build_plan(const PlanReq *reqs, size_t n, const slrng_batch_opts &o, int device,
-               uint64_t grid_lanes, PlanHost &out, bool fit = false, uint64_t fit_floor = 0);
+               uint64_t grid_lanes, PlanHost &out, bool fit = false, uint64_t fit_floor = 0,
+               bool host_tables = false);
 
 // Builds ahead of time the chunk tables (x^(jC) mod p, all entries) of every
 // chunk length that fitting can choose for `variant`, so that no iteration
 // pays for building one.
 int warm_fit_tables(int device, int variant, const slrng_batch_opts &o, uint64_t fit_floor);
 
-// The persistent grid (blocks of 4 waves) for the options on `device`.
-int batch_grid_blocks(const slrng_batch_opts &o, int device, unsigned *blocks);
+// Digit matrices of one engine on one device, for positioning requests from a
+// 128-bit position entirely on the device: entry l 2^bits + d holds the n rows
+// e_i M^(d 2^(bits l)) (k words each), l < levels = 128 / bits.  Built once
+// per (device, engine) with a kernel, kept until the process ends: 8-bit
+// digits for n <= 256 (32 MiB for n = 256), 4-bit digits above (64 MiB for
+// n = 1024).
+struct DigitRows {
+  const uint64_t *dev = nullptr;
+  int bits = 0, levels = 0;
+};
+int digit_rows(int device, int variant, DigitRows *out);
+
+// The persistent grid (blocks of 4 waves) for the options on `device`, for
+// the kernel of all variants or (variant >= 0) the one specialised to it.
+int batch_grid_blocks(const slrng_batch_opts &o, int device, unsigned *blocks, int variant = -1);
 
 }  // namespace slrng

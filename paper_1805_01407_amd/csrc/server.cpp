@@ -4,19 +4,22 @@
 // slrng_streams_create) and a device output arena of a fixed budget.
 //  * submit: admission reserves the request's output bytes in the arena (or
 //    returns EAGAIN / waits when the budget is full) and assigns it the next
-//    positions of its stream: pos = head[stream], head[stream] += n.  A
-//    request is thus fully defined by (stream, pos, n): its values are the
-//    stream's outputs pos .. pos+n-1, whatever else is in flight.
+//    positions of its stream: pos = head[stream], head[stream] += n (128-bit
+//    positions).  A request is thus fully defined by (stream, pos, n): its
+//    values are the stream's outputs pos .. pos+n-1, whatever else is in
+//    flight.  Its latency counts from the moment it arrived (the call, or the
+//    scheduled arrival of a replayed trace), admission wait included.
 //  * iteration thread: takes every pending request (up to max_batch), plans
-//    them as one batch (request start state = resident state jumped by pos,
-//    lane-chunks, tiles), copies the descriptors into one of `inflight`
-//    preallocated slots and launches [request-state kernel -> persistent
-//    generation kernel] on that slot's HIP stream.  Requests that arrive while
-//    earlier iterations run join the next iteration, which may run
+//    them as one batch (lane-chunks, tiles; no polynomial arithmetic per
+//    request: the start state s M^pos is computed on the device from the
+//    digits of pos), copies the descriptors into one of `inflight`
+//    preallocated slots with one upload and launches [request-state kernel ->
+//    persistent generation kernel] on that slot's HIP stream.  Requests that
+//    arrive while earlier iterations run join the next iteration, which runs
 //    concurrently on another slot.
-//  * completion thread: waits for each iteration's event, stamps the
-//    completion time of its requests (latency = completion - submit), frees
-//    auto-released arena ranges and the slot.
+//  * completion: one thread per slot waits for that slot's iteration (so
+//    iterations complete in any order), stamps the completion time of its
+//    requests, frees auto-released arena ranges and the slot.
 #include <hip/hip_runtime_api.h>
 #include <string.h>
 
@@ -26,6 +29,7 @@
 #include <condition_variable>
 #include <deque>
 #include <map>
+#include <memory>
 #include <mutex>
 #include <new>
 #include <thread>
@@ -49,7 +53,6 @@ double secs(Clock::time_point a, Clock::time_point b) {
 }
 
 constexpr uint64_t kAlign = 256;  // arena allocation granularity (bytes)
-constexpr uint64_t kMaxBasisBytes = 1ull << 30;  // largest basis kept resident
 constexpr size_t kInitialPackBytes = 4u << 20;    // per-slot upload buffer at creation
 constexpr size_t kInitialReqs = 1024;             // per-slot request states at creation
 
@@ -101,10 +104,10 @@ enum ReqState { R_PENDING = 0, R_INFLIGHT = 1, R_DONE = 2, R_FAILED = 3 };
 struct Req {
   uint32_t stream;
   int kind;
-  uint64_t n, pos, off;
+  uint64_t n, pos, pos_hi, off;  // position pos_hi 2^64 + pos
   bool auto_release;
   int state;
-  Clock::time_point t_submit;
+  Clock::time_point t_arrival;   // latency origin
 };
 
 // One in-flight slot: a HIP stream, events and reusable buffers.  Everything
@@ -114,7 +117,11 @@ struct Req {
 struct Slot {
   hipStream_t st = nullptr;
   hipEvent_t ev0 = nullptr, evk = nullptr, ev1 = nullptr;  // start, generation kernel start, end
-  bool busy = false;
+  bool busy = false;      // taken by the worker until its iteration has completed
+  bool launched = false;  // an iteration is in flight (the slot's completer waits for it)
+  std::vector<uint64_t> tickets;  // that iteration's requests
+  std::condition_variable cv;     // wakes the slot's completer
+  std::thread completer;
   size_t cap_pack = 0, cap_req = 0;
   uint8_t *d_pack = nullptr, *h_pack = nullptr;
   uint64_t *d_req_state = nullptr;
@@ -122,23 +129,25 @@ struct Slot {
 
 // Byte offsets of the parts of a packed upload (each 256-byte aligned).
 struct PackLayout {
-  size_t counter = 0, tiles, lanes, runs, poly, idx, slot, total;
+  size_t counter = 0, tiles, lanes, runs, pos, idx, slot, total;
   PackLayout(size_t nt, size_t nl, size_t nr, size_t nreq) {
     auto up = [](size_t x) { return (x + 255) & ~(size_t)255; };
     tiles = 256;
     lanes = up(tiles + nt * sizeof(TileDesc));
     runs = up(lanes + nl * sizeof(LaneDesc));
-    poly = up(runs + nr * sizeof(RunDesc));
-    idx = up(poly + nreq * 16 * 8);
+    pos = up(runs + nr * sizeof(RunDesc));
+    idx = up(pos + nreq * 2 * 8);
     slot = up(idx + nreq * 4);
     total = up(slot + nreq * 4);
   }
 };
 
-struct Iteration {
-  int slot;
-  std::vector<uint64_t> tickets;
-};
+// 128-bit position arithmetic: (hi, lo) += (bhi, blo) modulo 2^128.
+void add128(uint64_t &hi, uint64_t &lo, uint64_t bhi, uint64_t blo) {
+  const uint64_t s = lo + blo;
+  hi += bhi + (s < lo ? 1 : 0);
+  lo = s;
+}
 
 }  // namespace
 
@@ -149,9 +158,9 @@ struct slrng_server {
   unsigned blocks = 0;
   slrng_streams *streams = nullptr;
   uint8_t *arena_dev = nullptr;
-  uint64_t *basis = nullptr;  // resident streams' basis states, or null
+  DigitRows digits;  // the engine's digit matrices (positioning from 128-bit positions)
   Arena arena;
-  std::vector<uint64_t> head;
+  std::vector<uint64_t> head, head_hi;  // next position of each stream (128-bit)
 
   std::mutex mu;
   std::condition_variable cv_work, cv_space, cv_done;
@@ -159,14 +168,15 @@ struct slrng_server {
   uint64_t pending_bytes = 0;
   std::unordered_map<uint64_t, Req> reqs;
   uint64_t next_ticket = 1;
-  std::vector<Slot> slots;
-  std::deque<Iteration> inflight;
+  std::unique_ptr<Slot[]> slots;
+  int nslots = 0;
+  int launched = 0;  // slots with an iteration in flight
   bool stop = false, worker_done = false;
   int error = 0;
   hipEvent_t ref = nullptr;                           // time origin of the busy intervals
   std::vector<std::pair<double, double>> busy_ivals;    // device [start, end) ms per iteration
   std::vector<std::pair<double, double>> kernel_ivals;  // generation kernel [start, end) ms
-  std::thread worker, completer;
+  std::thread worker;
 
   // statistics
   Clock::time_point t0;
@@ -219,17 +229,17 @@ static int launch_iteration(slrng_server *sv, int si, const std::vector<PlanReq>
   int rc = build_plan(pr.data(), pr.size(), sv->bo, sv->device, (uint64_t)sv->blocks * kBlock, P,
                       /*fit=*/true, (uint64_t)sv->o.min_chunk);
   if (rc) return rc;
-  const size_t nreq = P.rs.seeds.size();
+  const size_t nreq = P.rs.origin_idx.size();
   const PackLayout L(P.tiles.size(), P.lanes.size(), P.runs.size(), nreq);
   rc = slot_reserve(s, L.total, nreq);
   if (rc) return rc;
   uint8_t *h = s.h_pack;
-  memset(h + L.counter, 0, 256);  // the claim counter starts at zero
+  memset(h + L.counter, 0, 256);  // the claim counters start at zero
   if (!P.tiles.empty()) memcpy(h + L.tiles, P.tiles.data(), P.tiles.size() * sizeof(TileDesc));
   if (!P.lanes.empty()) memcpy(h + L.lanes, P.lanes.data(), P.lanes.size() * sizeof(LaneDesc));
   if (!P.runs.empty()) memcpy(h + L.runs, P.runs.data(), P.runs.size() * sizeof(RunDesc));
   if (nreq) {
-    memcpy(h + L.poly, P.rs.polys.data(), P.rs.polys.size() * 8);
+    memcpy(h + L.pos, P.rs.pos.data(), P.rs.pos.size() * 8);
     memcpy(h + L.idx, P.rs.origin_idx.data(), P.rs.origin_idx.size() * 4);
     memcpy(h + L.slot, P.rs.slot.data(), P.rs.slot.size() * 4);
   }
@@ -237,7 +247,7 @@ static int launch_iteration(slrng_server *sv, int si, const std::vector<PlanReq>
   const TileDesc *d_tiles = reinterpret_cast<const TileDesc *>(d + L.tiles);
   const LaneDesc *d_lanes = reinterpret_cast<const LaneDesc *>(d + L.lanes);
   const RunDesc *d_runs = reinterpret_cast<const RunDesc *>(d + L.runs);
-  const uint64_t *d_poly = reinterpret_cast<const uint64_t *>(d + L.poly);
+  const uint64_t *d_pos = reinterpret_cast<const uint64_t *>(d + L.pos);
   const uint32_t *d_idx = reinterpret_cast<const uint32_t *>(d + L.idx);
   const uint32_t *d_slot = reinterpret_cast<const uint32_t *>(d + L.slot);
   unsigned *d_counter = reinterpret_cast<unsigned *>(d + L.counter);
@@ -252,12 +262,12 @@ static int launch_iteration(slrng_server *sv, int si, const std::vector<PlanReq>
     ra.origin_state = streams_state_ptr(sv->streams);
     ra.origin_stride = sv->o.n_streams;
     ra.origin_idx = d_idx + off;
-    ra.polys = d_poly + (size_t)off * 16;
+    ra.polys = nullptr;
+    ra.pos = d_pos + (size_t)off * 2;
     ra.slot = d_slot + off;
     ra.req_state = s.d_req_state;
     ra.m = run.second;
-    e = sv->basis ? launch_req_state_basis(run.first, ra, sv->basis, st)
-                  : launch_req_state(run.first, ra, st);
+    e = launch_req_state_digits(run.first, ra, sv->digits.dev, sv->digits.bits, sv->digits.levels, st);
     if (e != hipSuccess) return hip_fail(e);
     off += run.second;
   }
@@ -277,46 +287,49 @@ static int launch_iteration(slrng_server *sv, int si, const std::vector<PlanReq>
     e = hipEventRecord(s.evk, st);
     if (e != hipSuccess) return hip_fail(e);
     const unsigned blocks = std::min<unsigned>(sv->blocks, ((unsigned)P.tiles.size() + 3) / 4);
-    e = launch_batch(a, sv->bo.tile, blocks, st);
+    e = launch_batch(a, sv->bo.tile, blocks, st, sv->o.variant);
+    if (e != hipSuccess) return hip_fail(e);
+  } else {
+    e = hipEventRecord(s.evk, st);
     if (e != hipSuccess) return hip_fail(e);
   }
   e = hipEventRecord(s.ev1, st);
   return e == hipSuccess ? SLRNG_OK : hip_fail(e);
 }
 
+static int free_slot_index(slrng_server *sv) {
+  for (int i = 0; i < sv->nslots; i++)
+    if (!sv->slots[i].busy) return i;
+  return -1;
+}
+
 static void worker_main(slrng_server *sv) {
   (void)hipSetDevice(sv->device);
   std::unique_lock<std::mutex> lk(sv->mu);
   for (;;) {
-    int si = -1;
     sv->cv_work.wait(lk, [&] {
       if (sv->pending.empty()) return sv->stop;
-      for (size_t i = 0; i < sv->slots.size(); i++)
-        if (!sv->slots[i].busy) return true;
-      return false;
+      return free_slot_index(sv) >= 0;
     });
     if (sv->pending.empty()) {  // stop requested and nothing left to launch
       sv->worker_done = true;
+      for (int i = 0; i < sv->nslots; i++) sv->slots[i].cv.notify_all();
       sv->cv_done.notify_all();
       return;
     }
     // batching window: hold the iteration until the oldest pending request
     // has waited window_us, unless enough bytes are pending already
     if (sv->o.window_us > 0 && !sv->stop) {
-      const auto due = sv->reqs[sv->pending.front()].t_submit + std::chrono::microseconds(sv->o.window_us);
+      const auto due = sv->reqs[sv->pending.front()].t_arrival + std::chrono::microseconds(sv->o.window_us);
       if (Clock::now() < due && sv->pending_bytes < sv->o.window_bytes) {
         sv->cv_work.wait_until(lk, due, [&] { return sv->stop || sv->pending_bytes >= sv->o.window_bytes; });
         continue;  // re-check slots and pending
       }
     }
-    for (size_t i = 0; i < sv->slots.size(); i++)
-      if (!sv->slots[i].busy) {
-        si = (int)i;
-        break;
-      }
+    const int si = free_slot_index(sv);
     if (si < 0) continue;
-    Iteration it;
-    it.slot = si;
+    Slot &slot = sv->slots[si];
+    slot.tickets.clear();
     std::vector<PlanReq> pr;
     const size_t take = std::min<size_t>(sv->pending.size(), (size_t)sv->o.max_batch);
     for (size_t k = 0; k < take; k++) {
@@ -325,22 +338,24 @@ static void worker_main(slrng_server *sv) {
       Req &q = sv->reqs[t];
       sv->pending_bytes -= q.n * 8;
       q.state = R_INFLIGHT;
-      it.tickets.push_back(t);
-      pr.push_back(PlanReq{sv->o.variant, q.kind, q.n, (uint64_t)(uintptr_t)(sv->arena_dev + q.off), q.pos,
-                           true, 0, q.stream, (uint64_t)k});
+      slot.tickets.push_back(t);
+      PlanReq p{sv->o.variant, q.kind, q.n, (uint64_t)(uintptr_t)(sv->arena_dev + q.off), q.pos,
+                true, 0, q.stream, (uint64_t)k};
+      p.start_hi = q.pos_hi;
+      pr.push_back(p);
     }
-    sv->slots[si].busy = true;
+    slot.busy = true;
     lk.unlock();
     const int rc = launch_iteration(sv, si, pr);
     // after a failed launch, let whatever was queued on the slot's stream
     // (the upload reads the slot's pinned buffer) finish before the slot is
     // handed out again
-    if (rc) (void)hipStreamSynchronize(sv->slots[si].st);
+    if (rc) (void)hipStreamSynchronize(slot.st);
     lk.lock();
     if (rc) {
       // the launch failed: fail exactly these requests and free the slot
       sv->error = rc;
-      for (uint64_t t : it.tickets) {
+      for (uint64_t t : slot.tickets) {
         auto f = sv->reqs.find(t);
         if (f == sv->reqs.end()) continue;
         f->second.state = R_FAILED;
@@ -350,29 +365,31 @@ static void worker_main(slrng_server *sv) {
           sv->reqs.erase(f);
         }
       }
-      sv->slots[si].busy = false;
+      slot.tickets.clear();
+      slot.busy = false;
       sv->cv_done.notify_all();
       sv->cv_space.notify_all();
       continue;
     }
     sv->iterations++;
-    sv->batch_sum += it.tickets.size();
-    sv->max_batch_seen = std::max<uint64_t>(sv->max_batch_seen, it.tickets.size());
-    sv->inflight.push_back(std::move(it));
-    sv->max_inflight = std::max<uint64_t>(sv->max_inflight, sv->inflight.size());
-    sv->cv_done.notify_all();  // wakes the completion thread
+    sv->batch_sum += slot.tickets.size();
+    sv->max_batch_seen = std::max<uint64_t>(sv->max_batch_seen, slot.tickets.size());
+    slot.launched = true;
+    sv->launched++;
+    sv->max_inflight = std::max<uint64_t>(sv->max_inflight, (uint64_t)sv->launched);
+    slot.cv.notify_all();  // wakes the slot's completer
   }
 }
 
-static void completer_main(slrng_server *sv) {
+// Completion of the iterations of one slot: waits for the slot's end event,
+// whatever the other slots are doing.
+static void completer_main(slrng_server *sv, int si) {
   (void)hipSetDevice(sv->device);
+  Slot &s = sv->slots[si];
   std::unique_lock<std::mutex> lk(sv->mu);
   for (;;) {
-    sv->cv_done.wait(lk, [&] { return sv->worker_done || !sv->inflight.empty(); });
-    if (sv->inflight.empty()) return;  // the worker has exited and all work completed
-    Iteration it = sv->inflight.front();
-    sv->inflight.pop_front();
-    Slot &s = sv->slots[it.slot];
+    s.cv.wait(lk, [&] { return s.launched || sv->worker_done; });
+    if (!s.launched) return;  // the worker has exited and this slot is idle
     lk.unlock();
     hipError_t e = hipEventSynchronize(s.ev1);
     const Clock::time_point now = Clock::now();
@@ -387,7 +404,7 @@ static void completer_main(slrng_server *sv) {
       sv->busy_ivals.push_back({a, b});
       sv->kernel_ivals.push_back({k, b});
     }
-    for (uint64_t t : it.tickets) {
+    for (uint64_t t : s.tickets) {
       auto f = sv->reqs.find(t);
       if (f == sv->reqs.end()) continue;
       Req &q = f->second;
@@ -395,7 +412,7 @@ static void completer_main(slrng_server *sv) {
         q.state = R_DONE;
         sv->completed++;
         sv->outputs += q.n;
-        sv->lat_us.push_back(secs(q.t_submit, now) * 1e6);
+        sv->lat_us.push_back(secs(q.t_arrival, now) * 1e6);
       } else {
         q.state = R_FAILED;
         sv->failed++;
@@ -406,7 +423,10 @@ static void completer_main(slrng_server *sv) {
         sv->reqs.erase(f);
       }
     }
+    s.tickets.clear();
+    s.launched = false;
     s.busy = false;
+    sv->launched--;
     sv->cv_work.notify_all();
     sv->cv_space.notify_all();
     sv->cv_done.notify_all();
@@ -441,19 +461,22 @@ static void destroy_server(slrng_server *sv) {
   sv->cv_done.notify_all();
   sv->cv_space.notify_all();
   if (sv->worker.joinable()) sv->worker.join();
-  // the worker has launched everything it took; wait for those iterations
+  // the worker has launched everything it took; the completers finish those
+  // iterations and exit
   {
-    std::unique_lock<std::mutex> lk(sv->mu);
-    sv->cv_done.notify_all();
+    std::lock_guard<std::mutex> g(sv->mu);
+    sv->worker_done = true;
+    for (int i = 0; i < sv->nslots; i++) sv->slots[i].cv.notify_all();
   }
-  if (sv->completer.joinable()) sv->completer.join();
-  for (auto &s : sv->slots) {
+  for (int i = 0; i < sv->nslots; i++)
+    if (sv->slots[i].completer.joinable()) sv->slots[i].completer.join();
+  for (int i = 0; i < sv->nslots; i++) {
+    Slot &s = sv->slots[i];
     if (s.st) (void)hipStreamSynchronize(s.st);
     free_slot(s);
   }
   if (sv->ref) (void)hipEventDestroy(sv->ref);
   if (sv->arena_dev) (void)hipFree(sv->arena_dev);
-  if (sv->basis) (void)hipFree(sv->basis);
   if (sv->streams) slrng_streams_destroy(sv->streams);
   delete sv;
 }
@@ -487,25 +510,15 @@ extern "C" int slrng_server_create(const slrng_server_opts *opts, slrng_server *
       delete sv;
       return hip_fail(e);
     }
-    rc = batch_grid_blocks(bo, sv->device, &sv->blocks);
+    rc = batch_grid_blocks(bo, sv->device, &sv->blocks, o.variant);
     // every chunk table an iteration can pick, built now rather than in the
     // middle of serving (one table of 65,536 polynomials takes milliseconds)
     if (!rc) rc = warm_fit_tables(sv->device, o.variant, bo, (uint64_t)o.min_chunk);
     if (!rc) rc = slrng_streams_create(o.variant, o.seed, o.n_streams, nullptr, &sv->streams);
-    // The basis states s_j M^i (i < n) of every resident stream, when they fit
-    // in kMaxBasisBytes: a request's start state is then a sum of basis states
-    // selected by x^pos mod p, computed by a whole wave at once, instead of n
-    // serial steps of one lane.
-    if (!rc) {
-      const uint64_t k = (uint64_t)variant_words(o.variant);
-      const uint64_t bytes = (uint64_t)o.n_streams * 64 * k * k * 8;
-      if (bytes <= kMaxBasisBytes) {
-        e = hipMalloc(&sv->basis, bytes);
-        if (e == hipSuccess) e = launch_basis(o.variant, streams_state_ptr(sv->streams), o.n_streams,
-                                              sv->basis, nullptr);
-        if (e != hipSuccess) rc = e == hipErrorOutOfMemory ? SLRNG_ENOMEM : hip_fail(e);
-      }
-    }
+    // the engine's digit matrices: a request's start state s_j M^pos is then
+    // computed on the device from the digits of pos (built once per device
+    // and engine)
+    if (!rc) rc = digit_rows(sv->device, o.variant, &sv->digits);
     if (!rc) {
       e = hipDeviceSynchronize();
       if (e != hipSuccess) rc = hip_fail(e);
@@ -520,8 +533,11 @@ extern "C" int slrng_server_create(const slrng_server_opts *opts, slrng_server *
     if (!rc) {
       sv->arena.init(o.budget_bytes / kAlign * kAlign);
       sv->head.assign(o.n_streams, 0);
-      sv->slots.resize(o.inflight);
-      for (auto &s : sv->slots) {
+      sv->head_hi.assign(o.n_streams, 0);
+      sv->slots.reset(new Slot[o.inflight]);
+      sv->nslots = o.inflight;
+      for (int i = 0; i < sv->nslots; i++) {
+        Slot &s = sv->slots[i];
         e = hipStreamCreateWithFlags(&s.st, hipStreamNonBlocking);
         if (e == hipSuccess) e = hipEventCreate(&s.ev0);
         if (e == hipSuccess) e = hipEventCreate(&s.evk);
@@ -548,8 +564,8 @@ extern "C" int slrng_server_create(const slrng_server_opts *opts, slrng_server *
       return rc;
     }
     sv->t0 = Clock::now();
+    for (int i = 0; i < sv->nslots; i++) sv->slots[i].completer = std::thread(completer_main, sv, i);
     sv->worker = std::thread(worker_main, sv);
-    sv->completer = std::thread(completer_main, sv);
     *out = sv;
     return SLRNG_OK;
   });
@@ -563,41 +579,74 @@ extern "C" int slrng_server_destroy(slrng_server *sv) {
   });
 }
 
+// Admission of one request that arrived at `arrival` (the latency origin).
+static int submit_at(slrng_server *sv, uint32_t stream_id, uint64_t n, int kind, int flags,
+                     uint64_t *ticket, Clock::time_point arrival) {
+  if (!sv || !ticket || (kind != SLRNG_U64 && kind != SLRNG_F64)) return SLRNG_EINVAL;
+  if (stream_id >= sv->o.n_streams || n == 0) return SLRNG_EINVAL;
+  if (n > sv->arena.size / 8) return SLRNG_ERANGE;
+  std::unique_lock<std::mutex> lk(sv->mu);
+  uint64_t off = 0;
+  for (;;) {
+    if (sv->stop) return SLRNG_EINVAL;
+    if (sv->arena.alloc(n * 8, &off)) break;
+    if (flags & SLRNG_SUBMIT_NONBLOCK) {
+      sv->rejected++;
+      return SLRNG_EAGAIN;
+    }
+    sv->cv_space.wait(lk);
+  }
+  sv->peak_reserved = std::max(sv->peak_reserved, sv->arena.used);
+  Req q;
+  q.stream = stream_id;
+  q.kind = kind;
+  q.n = n;
+  q.pos = sv->head[stream_id];
+  q.pos_hi = sv->head_hi[stream_id];
+  add128(sv->head_hi[stream_id], sv->head[stream_id], 0, n);
+  q.off = off;
+  q.auto_release = (flags & SLRNG_SUBMIT_AUTORELEASE) != 0;
+  q.state = R_PENDING;
+  q.t_arrival = arrival;
+  const uint64_t t = sv->next_ticket++;
+  sv->reqs.emplace(t, q);
+  sv->pending.push_back(t);
+  sv->pending_bytes += n * 8;
+  sv->submitted++;
+  *ticket = t;
+  sv->cv_work.notify_one();
+  return SLRNG_OK;
+}
+
 extern "C" int slrng_server_submit(slrng_server *sv, uint32_t stream_id, uint64_t n, int kind,
                                    int flags, uint64_t *ticket) {
   return guarded([&]() -> int {
-    if (!sv || !ticket || (kind != SLRNG_U64 && kind != SLRNG_F64)) return SLRNG_EINVAL;
-    if (stream_id >= sv->o.n_streams || n == 0) return SLRNG_EINVAL;
-    if (n > sv->arena.size / 8) return SLRNG_ERANGE;
-    std::unique_lock<std::mutex> lk(sv->mu);
-    uint64_t off = 0;
-    for (;;) {
-      if (sv->stop) return SLRNG_EINVAL;
-      if (sv->arena.alloc(n * 8, &off)) break;
-      if (flags & SLRNG_SUBMIT_NONBLOCK) {
-        sv->rejected++;
-        return SLRNG_EAGAIN;
-      }
-      sv->cv_space.wait(lk);
+    // the request arrives now: a wait for arena space counts in its latency
+    return submit_at(sv, stream_id, n, kind, flags, ticket, Clock::now());
+  });
+}
+
+extern "C" int slrng_server_advance(slrng_server *sv, uint32_t stream_id, uint64_t steps_hi,
+                                    uint64_t steps_lo) {
+  return guarded([&]() -> int {
+    if (!sv || stream_id >= sv->o.n_streams) return SLRNG_EINVAL;
+    std::lock_guard<std::mutex> g(sv->mu);
+    add128(sv->head_hi[stream_id], sv->head[stream_id], steps_hi, steps_lo);
+    return SLRNG_OK;
+  });
+}
+
+extern "C" int slrng_server_intervals(slrng_server *sv, double *kernel_start_ms, double *kernel_end_ms,
+                                      uint64_t cap, uint64_t *count) {
+  return guarded([&]() -> int {
+    if (!sv || !count || (cap && (!kernel_start_ms || !kernel_end_ms))) return SLRNG_EINVAL;
+    std::lock_guard<std::mutex> g(sv->mu);
+    const uint64_t n = sv->kernel_ivals.size();
+    for (uint64_t i = 0; i < n && i < cap; i++) {
+      kernel_start_ms[i] = sv->kernel_ivals[i].first;
+      kernel_end_ms[i] = sv->kernel_ivals[i].second;
     }
-    sv->peak_reserved = std::max(sv->peak_reserved, sv->arena.used);
-    Req q;
-    q.stream = stream_id;
-    q.kind = kind;
-    q.n = n;
-    q.pos = sv->head[stream_id];
-    sv->head[stream_id] += n;
-    q.off = off;
-    q.auto_release = (flags & SLRNG_SUBMIT_AUTORELEASE) != 0;
-    q.state = R_PENDING;
-    q.t_submit = Clock::now();
-    const uint64_t t = sv->next_ticket++;
-    sv->reqs.emplace(t, q);
-    sv->pending.push_back(t);
-    sv->pending_bytes += n * 8;
-    sv->submitted++;
-    *ticket = t;
-    sv->cv_work.notify_one();
+    *count = n;
     return SLRNG_OK;
   });
 }
@@ -650,9 +699,9 @@ extern "C" int slrng_server_drain(slrng_server *sv) {
     if (!sv) return SLRNG_EINVAL;
     std::unique_lock<std::mutex> lk(sv->mu);
     sv->cv_done.wait(lk, [&] {
-      if (!sv->pending.empty() || !sv->inflight.empty()) return false;
-      for (auto &s : sv->slots)
-        if (s.busy) return false;
+      if (!sv->pending.empty()) return false;
+      for (int i = 0; i < sv->nslots; i++)
+        if (sv->slots[i].busy) return false;
       return true;
     });
     return sv->error ? sv->error : SLRNG_OK;
@@ -739,8 +788,11 @@ extern "C" int slrng_server_replay(slrng_server *sv, const double *t_arrival_s, 
         if (due - now > std::chrono::microseconds(200))
           std::this_thread::sleep_for(due - now - std::chrono::microseconds(100));
       }
+      // the latency of a replayed request counts from its scheduled arrival,
+      // so that a late submission (the replay falling behind, a wait for
+      // arena space) shows in the statistics
       uint64_t t = 0;
-      int rc = slrng_server_submit(sv, stream_ids[i], n[i], kinds[i], SLRNG_SUBMIT_AUTORELEASE, &t);
+      int rc = submit_at(sv, stream_ids[i], n[i], kinds[i], SLRNG_SUBMIT_AUTORELEASE, &t, due);
       if (rc) return rc;
     }
     return slrng_server_drain(sv);

@@ -2,9 +2,11 @@
 configuration bench.py times (default tuning), bit for bit against the oracle.
 
 * sweep: 65,536 streams x 65,536 outputs (32 GiB per kind, written into
-  memory from slrng_output_alloc as bench.py does) — xoshiro256** compared
-  in full (uint64 and doubles); xoroshiro1024** and xoroshiro128+ on sampled
-  rows plus every final state;
+  memory from slrng_output_alloc as bench.py does) — xoshiro256** (seed 3)
+  compared in full (uint64 and doubles); each of the eight swept generators
+  on its own seed (generator i on seed i + 1, as the sweep's steps use them)
+  in its tuned launch shape, on rows covering every stagger class and slot
+  boundary, plus every final state;
 * jump-ahead: 1,048,576 xoshiro256++ streams positioned by the jump chain,
   then long-jumped once: all states compared, then 1,024 outputs per stream
   (8 GiB) compared in full.
@@ -71,30 +73,57 @@ def test_sweep_full_size_xoshiro256ss_complete(P):
     torch.cuda.empty_cache()
 
 
-@pytest.mark.parametrize("name", ["xoroshiro1024**", "xoroshiro128+"])
-def test_sweep_full_size_sampled_rows(P, name):
+SWEEP = ["xoroshiro128+", "xoroshiro128++", "xoroshiro128**", "xoshiro256+", "xoshiro256++",
+         "xoshiro256**", "xoshiro512**", "xoroshiro1024**"]
+
+
+def sweep_rows(S, seed):
+    """Rows that cover every stagger class of the slot boundaries (the class
+    of a row is its group of 64 streams modulo the skew, at most 16), with the
+    first, a middle and the last lane of each chosen group; plus the first and
+    last rows of the launch.  Every row spans every slot boundary."""
+    rng = np.random.default_rng(seed)
+    groups = S // 64
+    rows = {0, 1, S - 2, S - 1}
+    for d in range(16):
+        g = d + 16 * int(rng.integers(0, groups // 16))
+        rows |= {g * 64, g * 64 + 31, g * 64 + 63}
+    rows |= {(groups - 1) * 64, (groups - 1) * 64 + 63}
+    return sorted(rows)
+
+
+@pytest.mark.parametrize("gi", range(len(SWEEP)))
+def test_sweep_full_size_every_generator(P, gi):
+    """Generator i of the sweep on seed i + 1 at 65,536 x 65,536, uint64 and
+    doubles, in the launch shape the autotuner chose for it (the one bench.py
+    times): sampled rows covering every stagger class and slot boundary, and
+    every stream's final state after each kind."""
     import torch
-    seed, S, N = 5, 65536, 65536
+    name, seed, S, N = SWEEP[gi], gi + 1, 65536, 65536
     g = O.GEN64[name]
-    announce("sweep sampled", name, S, N)
+    announce("sweep full size", name, "seed", seed, S, N)
     st0 = O.stream_chain(g, seed, S)
-    rows = sorted({0, 1, 63, 64, 65, 1023, 1024, 4095, 32767, 65472, 65535} |
-                  set(np.random.default_rng(0).integers(0, S, 8).tolist()))
+    exp_fin = O.jump_many(g, st0, N, nthreads=16)
+    rows = sweep_rows(S, seed)
+    idx = None
     buf = P.output_empty((S, N), torch.int64)
+    exp_u, _ = O.generate_many(g, st0[rows], N, kind="u64", nthreads=16)
     with P.Streams(name, seed, S) as h:
         assert np.array_equal(h.get_state(), st0)
         for kind in (P.SLRNG_U64, P.SLRNG_F64):
             h.seed(seed)
             P.slrng_generate(h.h, kind, N, buf.data_ptr(), N, 0)
             torch.cuda.synchronize()
-            idx = torch.tensor(rows, device="cuda")
+            if idx is None:
+                idx = torch.tensor(rows, device="cuda")
             got = buf.index_select(0, idx).cpu().numpy().view(np.uint64)
-            exp, _ = O.generate_many(g, st0[rows], N, kind="u64", nthreads=16)
+            exp = exp_u
             if kind == P.SLRNG_F64:
-                exp = ((exp >> np.uint64(11)).astype(np.float64) * 2.0**-53).view(np.uint64)
-            assert np.array_equal(got, exp)
-        fin = h.get_state()
-    assert np.array_equal(fin, O.jump_many(g, st0, N, nthreads=16))
+                exp = ((exp_u >> np.uint64(11)).astype(np.float64) * 2.0**-53).view(np.uint64)
+            if not np.array_equal(got, exp):
+                bad = np.argwhere(got != exp)[0]
+                raise AssertionError(f"{name} kind {kind}: row {rows[bad[0]]} output {bad[1]} differs")
+            assert np.array_equal(h.get_state(), exp_fin), (name, kind)
     del buf
     torch.cuda.empty_cache()
 

@@ -1,7 +1,9 @@
 """GPU tests of the serving loop: every served request equals the oracle and the
-same request run alone (a fresh handle advanced to the request's position);
-admission never exceeds the budget; requests submitted while others are in
-flight are batched into overlapping iterations."""
+same request run alone (a fresh handle advanced to the request's position),
+at positions up to and past 2^64 (start states computed on the device from
+the digits of the position); admission never exceeds the budget; requests
+submitted while others are in flight run in iterations that overlap on the
+device (shown by the iterations' device intervals)."""
 import ctypes
 import sys
 import threading
@@ -136,7 +138,7 @@ def test_budget_admission_and_overlap(P):
         P.slrng_server_release(sv, done[0])
         for t in held[1:]:
             P.slrng_server_release(sv, t)
-        # a burst of auto-released requests: iterations overlap on the device
+        # a burst of auto-released requests, batched into fewer iterations
         P.slrng_server_reset_stats(sv)
         for i in range(3000):
             P.slrng_server_submit(sv, i % S, 8000, flags=P.SLRNG_SUBMIT_AUTORELEASE)
@@ -146,8 +148,95 @@ def test_budget_admission_and_overlap(P):
         P.slrng_server_destroy(sv)
     assert st["completed"] == 3000 and st["failed"] == 0
     assert st["peak_reserved_bytes"] <= budget
-    assert st["max_inflight"] >= 2
     assert st["iterations"] < 3000  # requests were batched
+
+
+def test_iterations_overlap_on_the_device(P):
+    """A long iteration (one request of two lane-chunks of 2^20 outputs, tens
+    of ms on two lanes) and short requests submitted while it runs: the short
+    ones complete in iterations on other HIP streams whose device intervals
+    lie inside the long one's, and every value is right."""
+    import time
+    S = 8
+    g = O.GEN64[NAME]
+    chain = O.stream_chain(g, 9, S)
+    opts = P.slrng_server_default_opts(n_streams=S, budget_bytes=64 << 20, seed=9, variant=NAME,
+                                       inflight=3, window_us=0, chunk=1 << 20, min_chunk=1 << 20)
+    sv = P.slrng_server_create(opts)
+    try:
+        long_t = P.slrng_server_submit(sv, 0, 1 << 21)
+        time.sleep(0.003)
+        short = []
+        for k in range(4):
+            short.append((P.slrng_server_submit(sv, 1 + k, 1000 + k), 1 + k, 1000 + k))
+            time.sleep(0.002)
+        outs = []
+        for t, st, n in short:
+            ptr, pos = P.slrng_server_wait(sv, t)
+            outs.append((st, pos, n, d2h(ptr, n)))
+        ptr, pos = P.slrng_server_wait(sv, long_t)
+        head, tail = d2h(ptr, 4096), d2h(ptr + 8 * ((1 << 21) - 4096), 4096)
+        iv = P.slrng_server_intervals(sv)
+        stats = P.slrng_server_get_stats(sv)
+    finally:
+        P.slrng_server_destroy(sv)
+    announce("overlap intervals (ms)", iv.round(3).tolist())
+    assert stats["failed"] == 0 and stats["iterations"] >= 2
+    # the long iteration completes last; some other iteration ran entirely
+    # inside its interval on the device
+    lo, hi = iv[-1]
+    assert hi - lo > 1.0
+    inside = [(a, b) for a, b in iv[:-1] if lo < a and b < hi]
+    assert inside, iv.tolist()
+    for st, pos, n, out in outs:
+        assert np.array_equal(out, expected(chain, st, pos, n)), (st, pos, n)
+    assert np.array_equal(head, O.generate(g, chain[0], 4096)[0])
+    assert np.array_equal(tail, O.generate(g, O.jump(g, chain[0], (1 << 21) - 4096), 4096)[0])
+
+
+@pytest.mark.parametrize("name", [NAME, "xoroshiro1024**", "xoroshiro128++"])
+def test_served_positions_past_2_64(P, name):
+    """Heads moved with slrng_server_advance to positions around and far past
+    2^64 (one request straddles 2^64, one starts near 2^128 and wraps): the
+    served values equal the oracle's jump to the same position and a fresh
+    handle advanced there."""
+    S = 6
+    g = O.GEN64[name]
+    chain = O.stream_chain(g, 21, S)
+    skips = [(1 << 64) - 3, (1 << 64) + 12345, (1 << 100) + (1 << 70) + 99, (1 << 128) - 5,
+             0x0123456789ABCDEF_FEDCBA9876543210, 5]
+    opts = P.slrng_server_default_opts(n_streams=S, budget_bytes=64 << 20, seed=21, variant=name)
+    sv = P.slrng_server_create(opts)
+    got = []
+    try:
+        for st, k in enumerate(skips):
+            P.slrng_server_advance(sv, st, k)
+        tickets = []
+        for st in range(S):
+            for n in (10, 70000, 3):
+                tickets.append((P.slrng_server_submit(sv, st, n, st % 2), st, n, st % 2))
+        for t, st, n, kind in tickets:
+            ptr, pos = P.slrng_server_wait(sv, t)
+            got.append((st, pos, n, kind, d2h(ptr, n)))
+            P.slrng_server_release(sv, t)
+    finally:
+        P.slrng_server_destroy(sv)
+    announce("served past 2^64", name, len(got))
+    heads = list(skips)
+    for st, pos, n, kind, out in got:
+        full = heads[st] % (1 << 128)
+        assert pos == full % (1 << 64)
+        heads[st] = full + n
+        e, _ = O.generate(g, O.jump(g, chain[st], full), n)
+        if kind == 1:
+            e = ((e >> np.uint64(11)).astype(np.float64) * 2.0**-53).view(np.uint64)
+        assert np.array_equal(out, e), (name, st, full, n)
+    # the same request alone: a fresh handle advanced by the full position
+    st, pos, n, kind, out = got[4]  # stream 1, 70,000 outputs past 2^64 + 12,355
+    with P.Streams(name, states=chain[st]) as h:
+        h.advance((1 << 64) + 12345 + 10)
+        alone = h.generate(n, kind).cpu().numpy().view(np.uint64)[0]
+    assert np.array_equal(alone, out)
 
 
 def test_replay_small_trace(P):
@@ -167,9 +256,9 @@ def test_replay_small_trace(P):
 
 @pytest.mark.parametrize("name", ["xoroshiro128+", "xoshiro512**", "xoroshiro1024++"])
 def test_served_requests_other_generators(P, name):
-    """Request start states come from the resident streams' basis states
-    (s M^i, i < n): two-word, eight-word and the cyclic sixteen-word engines,
-    positions from 0 to past several basis lengths."""
+    """Request start states computed on the device from the digits of the
+    position: two-word, eight-word and the cyclic sixteen-word engines,
+    positions from 0 to past several digit levels."""
     S = 8
     g = O.GEN64[name]
     chain = O.stream_chain(g, 3, S)
