@@ -361,6 +361,32 @@ int slrng_batch_destroy(slrng_batch *b);
 int slrng_batch_run(const slrng_request *reqs, size_t n_reqs, const slrng_batch_opts *opts,
                     hipStream_t stream);
 
+/* slrng_batch_run_static: slrng_batch_run for callers that cannot allocate
+ * device memory (code that must not call hipMalloc, tight serving loops).
+ * Same requests, options, values and errors as slrng_batch_run, with these
+ * differences:
+ *  - it calls no hipMalloc, hipFree or other allocating routine: the
+ *    descriptors, claim counters, request start states and chunk tables go
+ *    into a fixed device array of SLRNG_BATCH_STATIC_SCRATCH_BYTES (32 MiB)
+ *    that the library holds on every device it runs on until the process
+ *    ends (its device address is taken once per device, on the first call);
+ *  - it runs the persistent form only: SLRNG_BATCH_GRAPH runs as
+ *    SLRNG_BATCH_PERSISTENT (instantiating a graph allocates), and
+ *    SLRNG_BATCH_PLAIN is EINVAL;
+ *  - SLRNG_ERANGE when the plan needs more than the array holds (about
+ *    32 bytes per 64-output lane-chunk plus 16 per tile, 128 per request that
+ *    starts past its origin, and the chunk tables: n/8 bytes per chunk of the
+ *    longest request of each generator);
+ *  - every call on one device shares that device's array, which keeps the
+ *    last call's contents.  Calls are synchronous (the work is finished when
+ *    the call returns) and calls from several host threads on one device are
+ *    serialised inside the library; the array is not meant to be touched by
+ *    anything else.
+ * The caller still provides the output buffers (request dev_out). */
+#define SLRNG_BATCH_STATIC_SCRATCH_BYTES (32u << 20)
+int slrng_batch_run_static(const slrng_request *reqs, size_t n_reqs, const slrng_batch_opts *opts,
+                           hipStream_t stream);
+
 /* ---------------------------------------------------------------- serving
  *
  * A request server with continuous batching over device-resident streams.

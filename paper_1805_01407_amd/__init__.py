@@ -20,10 +20,10 @@ from .binding import (  # noqa: F401
     slrng_get_tuning, slrng_set_tuning, slrng_calib_write, slrng_calib_copy,
     slrng_output_alloc, slrng_output_free, output_empty,
     SLRNG_U64, SLRNG_F64, SLRNG_U32, SLRNG_F32, SLRNG_JUMP, SLRNG_LONG_JUMP,
-    SLRNG_BATCH_GRAPH, SLRNG_BATCH_PERSISTENT, SLRNG_BATCH_PLAIN,
+    SLRNG_BATCH_GRAPH, SLRNG_BATCH_PERSISTENT, SLRNG_BATCH_PLAIN, SLRNG_BATCH_STATIC_SCRATCH_BYTES,
     REQUEST_DTYPE, make_requests,
     slrng_batch_default_opts, slrng_batch_plan, slrng_batch_launch, slrng_batch_info,
-    slrng_batch_destroy, slrng_batch_run, slrng_batch_latencies,
+    slrng_batch_destroy, slrng_batch_run, slrng_batch_run_static, slrng_batch_latencies,
     set_batch_defaults,
     SLRNG_SUBMIT_NONBLOCK, SLRNG_SUBMIT_AUTORELEASE, slrng_server_default_opts,
     slrng_server_create, slrng_server_submit, slrng_server_poll, slrng_server_wait,

@@ -50,6 +50,7 @@ class _Tuning(ctypes.Structure):
 
 NUM_VARIANTS = 14
 SLRNG_BATCH_GRAPH, SLRNG_BATCH_PERSISTENT, SLRNG_BATCH_PLAIN = 0, 1, 2
+SLRNG_BATCH_STATIC_SCRATCH_BYTES = 32 << 20  # the fixed device array of slrng_batch_run_static
 
 # slrng_request as a numpy record (40 bytes, the C layout)
 REQUEST_DTYPE = np.dtype([("variant", "<i4"), ("kind", "<i4"), ("seed", "<u8"), ("start", "<u8"),
@@ -132,6 +133,7 @@ def lib():
         "slrng_batch_latencies": ([vp, vp, ctypes.POINTER(ctypes.c_double)], i32),
         "slrng_batch_destroy": ([vp], i32),
         "slrng_batch_run": ([vp, ctypes.c_size_t, ctypes.POINTER(_BatchOpts), vp], i32),
+        "slrng_batch_run_static": ([vp, ctypes.c_size_t, ctypes.POINTER(_BatchOpts), vp], i32),
         "slrng_server_default_opts": ([ctypes.POINTER(_ServerOpts)], i32),
         "slrng_server_create": ([ctypes.POINTER(_ServerOpts), ctypes.POINTER(vp)], i32),
         "slrng_server_submit": ([vp, ctypes.c_uint32, u64, i32, i32, u64p], i32),
@@ -506,6 +508,12 @@ def slrng_batch_run(reqs: np.ndarray, opts=None, stream=None) -> None:
     reqs, ptr, n = _reqs(reqs)
     _check(lib().slrng_batch_run(ptr, n, ctypes.byref(opts) if opts is not None else None,
                                  _stream(stream)), "slrng_batch_run")
+
+
+def slrng_batch_run_static(reqs: np.ndarray, opts=None, stream=None) -> None:
+    reqs, ptr, n = _reqs(reqs)
+    _check(lib().slrng_batch_run_static(ptr, n, ctypes.byref(opts) if opts is not None else None,
+                                        _stream(stream)), "slrng_batch_run_static")
 
 
 def slrng_server_default_opts(**overrides):
