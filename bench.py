@@ -55,6 +55,54 @@ def kernel_source_sha() -> str:
     return h.hexdigest()
 
 
+# Sources of the batched kernel: a change to any of them invalidates its
+# committed counter summary.
+BATCH_SOURCES = ["batch.hip", "batch.hpp", "gen_device.hpp", "engines.hpp", "kernels.hpp"]
+
+
+def batch_source_sha() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for name in BATCH_SOURCES:
+        with open(os.path.join(ROOT, "paper_1805_01407_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def profiled_batch_traffic() -> int | None:
+    """HBM bytes per launch of the batched workload's persistent kernel from
+    the committed counter summary (FETCH_SIZE and WRITE_SIZE scaled by a copy
+    kernel), or None when its sources have changed since."""
+    path = os.path.join(ROOT, "profiles", "k_batch_batched_requests_pmc.md")
+    try:
+        fields = dict(line.split(": ", 1) for line in open(path).read().splitlines()
+                      if line.startswith(("traffic_bytes_per_launch: ", "source_sha256: ")))
+        sha = batch_source_sha()
+    except (OSError, ValueError):
+        return None
+    if fields.get("source_sha256") != sha:
+        return None
+    return int(fields["traffic_bytes_per_launch"])
+
+
+def profiled_valu() -> dict | None:
+    """VALU instructions per dispatch of the positioning kernels (k_position,
+    k_jump, k_advance_each for xoshiro256++ at 2^20 streams) from the
+    committed counter summary (SQ_INSTS_VALU), or None when the kernel
+    sources have changed since those counters were taken."""
+    path = os.path.join(ROOT, "profiles", "jump_kernels_valu_pmc.md")
+    try:
+        lines = open(path).read().splitlines()
+        sha = kernel_source_sha()
+    except OSError:
+        return None
+    fields = dict(line.split(": ", 1) for line in lines if line.startswith(("valu_", "source_sha256: ")))
+    if fields.get("source_sha256") != sha:
+        return None
+    return {k[len("valu_insts_per_dispatch_"):]: int(v) for k, v in fields.items()
+            if k.startswith("valu_insts_per_dispatch_")}
+
+
 def profiled_traffic() -> int | None:
     """HBM bytes per generation launch from the committed counter summary
     (FETCH_SIZE and WRITE_SIZE, scaled by a copy kernel), or None when the
@@ -232,10 +280,13 @@ def batched_section(P, torch, stream, launches: int = 3, forms=("graph", "plain"
             P.slrng_batch_destroy(b)
         gbs = 8 * total / (ms * 1e-3) / 1e9
         out[label] = {"ms_per_launch": round(ms, 3), "outputs_per_s": total / (ms * 1e-3),
+                      "bytes_per_launch": 8 * total,
                       "GBs": round(gbs, 1), "frac_of_hbm_peak": round(gbs / HBM_PEAK_GBS, 4),
                       "latency_p50_ms": round(float(np.percentile(lat, 50)), 3),
                       "latency_p99_ms": round(float(np.percentile(lat, 99)), 3),
                       "plan_ms": round(plan_ms, 1)}
+    if "batched_graph" in out:
+        out["batched_graph"]["traffic"] = profiled_batch_traffic()
     # a plain copy of known size inside the arena, for scaling the hardware
     # memory counters of a profiled run of this section
     P.slrng_calib_copy(arena.data_ptr() + (4 << 30), arena.data_ptr(), 4 << 30, stream)
@@ -313,14 +364,16 @@ def positioning_section(P, torch, stream, reps: int = 5) -> dict:
     the SplitMix64 base state jumped i times by 2^128), every stream then
     long-jumped once (2^192), then 1,024 outputs per stream (8 GiB).
 
-    Positioning and the long jump are bound by integer VALU work, not by HBM:
-    a uniform jump costs n = 256 engine steps (12 VALU instructions each for
-    xoshiro256 on gfx950) plus, for each set coefficient of the polynomial
-    (about half), a 4-word xor (8 instructions).  `alu_frac` compares that
-    count with the chip's 32-bit VALU rate: 256 CUs x 128 lanes per clock x
-    2.4 GHz = 78.6 T lane-operations/s (the rate behind the 157.3 TFLOP/s
-    fp32 vector peak, an FMA counting as two).  The section also times the
-    advance of every stream by its own random 128-bit distance."""
+    Positioning and the long jump are bound by integer VALU issue, not by
+    HBM.  Their instruction counts come from the hardware counters
+    (SQ_INSTS_VALU per dispatch, committed under profiles/ with the hash of
+    the kernel sources): lane-operations = instructions x 64 lanes, divided
+    by the launch time measured here.  gfx950 issues one VALU instruction per
+    SIMD every four clocks, and a second one from another wave in the same
+    slot (dual issue, counted by SQ_ACTIVE_INST_VALU2): 256 CUs x 4 SIMDs x
+    16 lanes x 2.4 GHz = 39.3 T lane-operations/s single issue, 78.6 T with
+    dual issue in every slot; both fractions are reported.  The section also
+    times the advance of every stream by its own random 128-bit distance."""
     name, seed, S, N = "xoshiro256++", 42, 1 << 20, 1024
     buf = P.output_empty((S, N), torch.int64)
     ev = lambda: torch.cuda.Event(enable_timing=True)  # noqa: E731
@@ -349,27 +402,30 @@ def positioning_section(P, torch, stream, reps: int = 5) -> dict:
                 acc["advance_each"] += e[3].elapsed_time(e4) / reps
     del buf, dist
     torch.cuda.empty_cache()
-    n_bits = 256
-    ops_per_jump = n_bits * 12 + (n_bits // 2) * 8
-    # per-stream advance: 13 radix-1024 digits, each a per-lane jump of n
-    # steps at 21 VALU instructions (12 engine, 8 masked accumulate, 1 mask)
-    ops_per_advance = 13 * n_bits * 21
-    lane_ops_peak = 256 * 128 * 2.4e9
     jump_s = acc["long_jump"] * 1e-3
     gbs = 8 * S * N / (acc["generate"] * 1e-3) / 1e9
-    return {"generator": name, "streams": S, "outputs_per_stream": N,
-            "position_ms": round(acc["position"], 4),
-            "positioned_streams_per_s": S / (acc["position"] * 1e-3),
-            "long_jump_ms": round(acc["long_jump"], 4),
-            "jumps_per_s": S / jump_s,
-            "ns_per_jump_aggregate": round(jump_s / S * 1e9, 4),
-            "alu_frac": round(S * ops_per_jump / jump_s / lane_ops_peak, 4),
-            "advance_each_ms": round(acc["advance_each"], 4),
-            "advance_each_per_s": S / (acc["advance_each"] * 1e-3),
-            "advance_each_alu_frac": round(S * ops_per_advance / (acc["advance_each"] * 1e-3)
-                                           / lane_ops_peak, 4),
-            "generate_ms": round(acc["generate"], 4), "generate_GBs": round(gbs, 1),
-            "generate_frac_of_hbm_peak": round(gbs / HBM_PEAK_GBS, 4)}
+    out = {"generator": name, "streams": S, "outputs_per_stream": N,
+           "position_ms": round(acc["position"], 4),
+           "positioned_streams_per_s": S / (acc["position"] * 1e-3),
+           "long_jump_ms": round(acc["long_jump"], 4),
+           "jumps_per_s": S / jump_s,
+           "ns_per_jump_aggregate": round(jump_s / S * 1e9, 4),
+           "advance_each_ms": round(acc["advance_each"], 4),
+           "advance_each_per_s": S / (acc["advance_each"] * 1e-3),
+           "generate_ms": round(acc["generate"], 4), "generate_GBs": round(gbs, 1),
+           "generate_frac_of_hbm_peak": round(gbs / HBM_PEAK_GBS, 4)}
+    valu = profiled_valu()
+    if valu:
+        single, dual = 256 * 4 * 16 * 2.4e9, 256 * 4 * 32 * 2.4e9
+        for label, key, ms in (("position", "k_position", acc["position"]),
+                               ("long_jump", "k_jump", acc["long_jump"]),
+                               ("advance_each", "k_advance_each", acc["advance_each"])):
+            if key in valu:
+                rate = valu[key] * 64 / (ms * 1e-3)
+                out[f"{label}_valu"] = {"insts_per_launch": valu[key], "lane_ops_per_s": rate,
+                                        "frac_single_issue": round(rate / single, 4),
+                                        "frac_dual_issue": round(rate / dual, 4)}
+    return out
 
 
 SWEEP32 = ["xoroshiro64*", "xoroshiro64**", "xoshiro128+", "xoshiro128++", "xoshiro128**"]
@@ -451,19 +507,22 @@ def lincomp_section(P, torch, stream, reps: int = 3) -> dict:
 def serving_section(P, seconds: float) -> dict:
     """The serving workload: Poisson arrivals at 20,000 requests/s on 4,096
     device-resident xoshiro256** streams (seed 42), sizes log-uniform in
-    64 B .. 256 MiB, admission under a 16 GB output budget; continuous batching
-    (default options: an iteration starts as soon as a slot is free) against
-    the plain form (one launch per request), on the same trace, plus one
-    throughput-leaning operating point of continuous batching (iterations
-    gather up to 4 ms or 1 GiB of requests) that shows what the generation
-    kernels reach when iterations are large."""
+    64 B .. 256 MiB, admission under a 16 GB output budget, replayed in real
+    time; latency runs from each request's scheduled arrival to the
+    completion of its iteration.  Three operating points on the same trace:
+    continuous batching with the default options (an iteration starts as soon
+    as a slot is free), the plain form (one request per iteration), and the
+    throughput operating point of continuous batching (iterations gather up
+    to 8 ms or 2 GiB of requests), whose kernel-active time is compared with
+    the HBM roof: kernel_active_frac_of_hbm_peak = bytes written / union of
+    the generation kernels' device intervals / 8 TB/s."""
     from paper_1805_01407_amd import workloads as W
     tr = W.serve_trace(seconds=seconds)
     out = {"seconds": seconds, "requests": int(tr["t"].size), "outputs": int(tr["n"].sum()),
            "offered_GBs": round(8 * float(tr["n"].sum()) / seconds / 1e9, 1)}
     for label, kw in (("continuous_batching", {}), ("plain_per_request", {"max_batch": 1}),
-                      ("continuous_batching_window_4ms", {"window_us": 4000,
-                                                          "window_bytes": 1 << 30})):
+                      ("continuous_batching_window_8ms", {"window_us": 8000,
+                                                          "window_bytes": 2 << 30})):
         sv = P.slrng_server_create(P.slrng_server_default_opts(**kw))
         try:
             t0 = time.perf_counter()
@@ -474,7 +533,8 @@ def serving_section(P, seconds: float) -> dict:
             P.slrng_server_destroy(sv)
         log(f"bench: serving replay ({label}) done in {wall:.1f} s")
         kgbs = 8 * st["outputs"] / max(st["kernel_s"], 1e-12) / 1e9
-        out[label] = {"latency_p50_us": round(st["p50_us"], 1), "latency_p99_us": round(st["p99_us"], 1),
+        out[label] = {"options": kw, "latency_p50_us": round(st["p50_us"], 1),
+                      "latency_p99_us": round(st["p99_us"], 1),
                       "latency_max_us": round(st["max_us"], 1), "outputs_per_s": st["outputs"] / wall,
                       "wall_s": round(wall, 3), "iterations": st["iterations"],
                       "mean_batch": round(st["mean_batch"], 2), "max_inflight": st["max_inflight"],

@@ -240,10 +240,13 @@ int slrng_streams_destroy(slrng_streams *h);
  * near 5.5 TB/s where the same bytes spread over about four times the span
  * reach 6.5-6.9 TB/s.  From 1 GiB up the buffer is made of physical pieces of
  * P = 256 MiB .. 1 GiB (a power of two near bytes / 64): gap x M pieces are
- * created in order, every gap-th is kept and mapped back to back into one
- * virtual range aligned to P, and the others are returned at once (gap = 4,
- * lower when free memory is short: gap x M x P bytes are held only during the
- * call).  Below 1 GiB, and on a device without the HIP virtual memory API
+ * created in order, every gap-th is kept and the others are returned at once
+ * (gap = 4, lower when free memory is short: gap x M x P bytes are held only
+ * during the call); the kept pieces are mapped into one virtual range aligned
+ * to P in bit-reversed order of their creation, so that any contiguous part
+ * of the buffer is spread over the whole span too (a few GB written into the
+ * start of a buffer measured 6.1-6.5 TB/s this way, 5.3-5.5 in creation
+ * order).  Below 1 GiB, and on a device without the HIP virtual memory API
  * or when the pieces cannot be mapped, it is a plain device allocation
  * (256-byte aligned); placement changes speed only, never values.
  * The memory is uninitialised and usable like any device pointer (kernels,
@@ -461,6 +464,12 @@ typedef struct slrng_server_opts {
                             fitted to an iteration (0 = default: the larger of
                             512 and 2n, n the state bits) */
   uint64_t window_bytes; /* ... or until this many bytes are pending */
+  int32_t arena_plain;   /* 1: the arena is one plain device allocation; 0 (default):
+                            memory from slrng_output_alloc (physical pages spread
+                            over the HBM) */
+  int32_t store;         /* output stores of the generation kernel: 0 (default)
+                            write-through, 1 plain, 2 nontemporal (values never
+                            change) */
 } slrng_server_opts;
 
 enum { SLRNG_SUBMIT_NONBLOCK = 1, SLRNG_SUBMIT_AUTORELEASE = 2 };

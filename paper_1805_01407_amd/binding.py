@@ -72,7 +72,8 @@ class _ServerOpts(ctypes.Structure):
                 ("variant", ctypes.c_int32), ("max_batch", ctypes.c_int32),
                 ("inflight", ctypes.c_int32), ("tile", ctypes.c_int32),
                 ("waves_per_cu", ctypes.c_int32), ("window_us", ctypes.c_int32),
-                ("min_chunk", ctypes.c_int32), ("window_bytes", ctypes.c_uint64)]
+                ("min_chunk", ctypes.c_int32), ("window_bytes", ctypes.c_uint64),
+                ("arena_plain", ctypes.c_int32), ("store", ctypes.c_int32)]
 
 
 class _ServerStats(ctypes.Structure):

@@ -14,9 +14,19 @@
 
 namespace slrng {
 
+// Output store of the batched kernels by policy: 0 write-through (sc1, the
+// default: rows of a tile are consecutive chunks of one request), 1 plain,
+// 2 nontemporal.
+template <int ST, typename VT>
+__device__ __forceinline__ void out_store_pol(VT *p, VT v) {
+  if constexpr (ST == 0) out_store_wt(p, v);
+  else if constexpr (ST == 1) out_store(p, v);
+  else out_store_nt(p, v);
+}
+
 // Store a staged tile with per-row destinations and lengths: row r writes
 // outputs t0 + c for c < m and t0 + c < len[r].
-template <int T, bool A16>
+template <int T, bool A16, int ST>
 __device__ __forceinline__ void store_tile_rows(const u64 *lds, int lane, const u64 *rowptr,
                                                 const unsigned *rowlen, int nrows, unsigned t0,
                                                 int m) {
@@ -34,8 +44,8 @@ __device__ __forceinline__ void store_tile_rows(const u64 *lds, int lane, const 
         if (col < len) {
           const u64x2 v = *reinterpret_cast<const u64x2 *>(lds + r * S + c);
           u64 *dst = reinterpret_cast<u64 *>(rowptr[r]) + col;
-          if (col + 1 < len && c + 1 < m) out_store_wt(reinterpret_cast<u64x2 *>(dst), v);
-          else out_store_wt(dst, v.x);
+          if (col + 1 < len && c + 1 < m) out_store_pol<ST>(reinterpret_cast<u64x2 *>(dst), v);
+          else out_store_pol<ST>(dst, v.x);
         }
       }
     }
@@ -48,7 +58,7 @@ __device__ __forceinline__ void store_tile_rows(const u64 *lds, int lane, const 
       const int c = lane % LPR;
       if (r < nrows && c < m) {
         const unsigned col = t0 + (unsigned)c;
-        if (col < rowlen[r]) out_store_wt(reinterpret_cast<u64 *>(rowptr[r]) + col, lds[r * S + c]);
+        if (col < rowlen[r]) out_store_pol<ST>(reinterpret_cast<u64 *>(rowptr[r]) + col, lds[r * S + c]);
       }
     }
   }
@@ -58,7 +68,7 @@ __device__ __forceinline__ void store_tile_rows(const u64 *lds, int lane, const 
 // 16-byte aligned rows): lane (r0, c) of the 16-byte layout writes rows
 // q*RPI + r0, whose destinations (column c) it holds in dst[q].  All LDS reads
 // first, then the stores, so that the reads overlap.
-template <int T>
+template <int T, int ST>
 __device__ __forceinline__ void store_tile_full(const u64 *lds, int lane, const u64 (&dst)[T / 2],
                                                 unsigned t0) {
   constexpr int S = TileGeom<T>::kStride;
@@ -71,10 +81,10 @@ __device__ __forceinline__ void store_tile_full(const u64 *lds, int lane, const 
   for (int q = 0; q < T / 2; q++) v[q] = *reinterpret_cast<const u64x2 *>(lds + (q * RPI + r0) * S + c);
   __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-  for (int q = 0; q < T / 2; q++) out_store_wt(reinterpret_cast<u64x2 *>(dst[q] + (u64)t0 * 8), v[q]);
+  for (int q = 0; q < T / 2; q++) out_store_pol<ST>(reinterpret_cast<u64x2 *>(dst[q] + (u64)t0 * 8), v[q]);
 }
 
-template <int V, int KIND, int T>
+template <int V, int KIND, int T, int ST = 0>
 __device__ __forceinline__ void batch_tile(const BatchArgs &a, const TileDesc &td, u64 *lds,
                                            u64 *rowptr, unsigned *rowlen, int lane) {
   constexpr int K = Params<V>::k;
@@ -110,7 +120,10 @@ __device__ __forceinline__ void batch_tile(const BatchArgs &a, const TileDesc &t
     const u64 *tab = a.tab[V];
     const u64 tn = a.tab_n[V];
     const u64 jj = ld.jidx;
-    jump_lane<V>(s, [&](int wi) { return tab[(u64)wi * tn + jj]; });
+    auto word = [&](int wi) { return tab[(u64)wi * tn + jj]; };
+    // a run tile's lanes all start from the request's start state
+    if (td.flags & kTileRun) jump_lane_from_uniform<V>(s, word);
+    else jump_lane<V>(s, word);
   }
   rowptr[lane] = ld.out;
   rowlen[lane] = ld.len;
@@ -134,9 +147,9 @@ __device__ __forceinline__ void batch_tile(const BatchArgs &a, const TileDesc &t
     else gen_tile_partial<V, KIND, T>(s, myrow, m);
     wave_sync();
     const bool full = nrows == kWave && m == T && t0 + T <= td.min_len;
-    if (a16 && full) store_tile_full<T>(lds, lane, dst, t0);
-    else if (a16) store_tile_rows<T, true>(lds, lane, rowptr, rowlen, nrows, t0, m);
-    else store_tile_rows<T, false>(lds, lane, rowptr, rowlen, nrows, t0, m);
+    if (a16 && full) store_tile_full<T, ST>(lds, lane, dst, t0);
+    else if (a16) store_tile_rows<T, true, ST>(lds, lane, rowptr, rowlen, nrows, t0, m);
+    else store_tile_rows<T, false, ST>(lds, lane, rowptr, rowlen, nrows, t0, m);
     wave_sync();
   }
 }
@@ -190,7 +203,7 @@ __global__ __launch_bounds__(kBlock) void k_batch(BatchArgs a) {
 
 // The same loop for tiles of one variant (the server's): the registers of
 // the other variants' code do not count, so more waves fit on a CU.
-template <int V, int T>
+template <int V, int T, int ST>
 __global__ __launch_bounds__(kBlock) void k_batch1(BatchArgs a) {
   __shared__ __attribute__((aligned(16))) u64 lds_all[(kBlock / kWave) * TileGeom<T>::kWaveLds];
   __shared__ u64 rowptr_all[kBlock];
@@ -202,8 +215,8 @@ __global__ __launch_bounds__(kBlock) void k_batch1(BatchArgs a) {
   unsigned t = 0;
   while (next_tile(a, lane, t)) {
     const TileDesc td = a.tiles[t];
-    if (td.kind) batch_tile<V, 1, T>(a, td, lds, rowptr, rowlen, lane);
-    else batch_tile<V, 0, T>(a, td, lds, rowptr, rowlen, lane);
+    if (td.kind) batch_tile<V, 1, T, ST>(a, td, lds, rowptr, rowlen, lane);
+    else batch_tile<V, 0, T, ST>(a, td, lds, rowptr, rowlen, lane);
     wave_sync();
   }
 }
@@ -228,71 +241,6 @@ __global__ __launch_bounds__(kBlock) void k_req_state(ReqArgs a) {
   if (live) {
 #pragma unroll
     for (int w = 0; w < K; w++) a.req_state[(u64)a.slot[i] * 16 + w] = s[w];
-  }
-}
-
-// Basis states of resident streams: B_j[i] = s_j * M^i for i < n, stream-major
-// (word w of B_j[i] at basis[(j * n + i) * K + w]), in logical word order.
-template <int V>
-__global__ __launch_bounds__(kBlock) void k_basis(const u64 *__restrict__ state, u64 S,
-                                                  u64 *__restrict__ basis) {
-  constexpr int K = Params<V>::k;
-  constexpr int N = 64 * K;
-  constexpr int BLK = block_steps<V>();
-  const u64 j = (u64)blockIdx.x * kBlock + threadIdx.x;
-  if (j >= S) return;
-  u64 s[K];
-#pragma unroll
-  for (int w = 0; w < K; w++) s[w] = state[(u64)w * S + j];
-  u64 *out = basis + j * N * K;
-  for (int i0 = 0; i0 < N; i0 += BLK) {
-    static_for<BLK>([&](auto P) {
-      u64 *rec = out + (u64)(i0 + P) * K;
-#pragma unroll
-      for (int w = 0; w < K; w++) rec[w] = s[K == 16 ? ((P + w) & 15) : w];
-      step<V, P>(s);
-    });
-  }
-}
-
-// Request start states from the basis: s_j * M^pos = sum_i r_i B_j[i] with
-// r = x^pos mod p (Cayley-Hamilton).  One wave per request: lane l xors the
-// basis states of the set coefficients l, l + 64, ... (consecutive lanes read
-// consecutive records), then an xor reduction across the wave.
-template <int V>
-__global__ __launch_bounds__(kBlock) void k_req_state_basis(ReqArgs a, const u64 *__restrict__ basis) {
-  constexpr int K = Params<V>::k;
-  constexpr int N = 64 * K;
-  const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
-  const unsigned r = blockIdx.x * (kBlock / kWave) + wave;
-  if (r >= a.m) return;  // uniform per wave
-  const u64 *rec = basis + (u64)a.origin_idx[r] * N * K;
-  const u64 *poly = a.polys + (u64)r * 16;
-  unsigned lo[K], hi[K];
-#pragma unroll
-  for (int w = 0; w < K; w++) lo[w] = hi[w] = 0;
-  for (int wi = 0; wi < K; wi++) {  // n / 64 = K words of the polynomial
-    if ((poly[wi] >> lane) & 1) {
-      const u64 *b = rec + (u64)(64 * wi + lane) * K;
-#pragma unroll
-      for (int w = 0; w < K; w++) {
-        const u64 v = b[w];
-        lo[w] ^= (unsigned)v;
-        hi[w] ^= (unsigned)(v >> 32);
-      }
-    }
-  }
-#pragma unroll
-  for (int off = kWave / 2; off > 0; off >>= 1) {
-#pragma unroll
-    for (int w = 0; w < K; w++) {
-      lo[w] ^= (unsigned)__shfl_xor((int)lo[w], off);
-      hi[w] ^= (unsigned)__shfl_xor((int)hi[w], off);
-    }
-  }
-  if (lane == 0) {
-#pragma unroll
-    for (int w = 0; w < K; w++) a.req_state[(u64)a.slot[r] * 16 + w] = ((u64)hi[w] << 32) | lo[w];
   }
 }
 
@@ -377,17 +325,24 @@ __global__ __launch_bounds__(kBlock) void k_req_state_digits(ReqArgs a, const u6
   }
 }
 
-template <int V>
-static hipError_t batch1_v(const BatchArgs &a, int tile, unsigned blocks, hipStream_t st) {
-  if (tile == 16) hipLaunchKernelGGL((k_batch1<V, 16>), dim3(blocks), dim3(kBlock), 0, st, a);
-  else hipLaunchKernelGGL((k_batch1<V, 32>), dim3(blocks), dim3(kBlock), 0, st, a);
+template <int V, int ST>
+static hipError_t batch1_vs(const BatchArgs &a, int tile, unsigned blocks, hipStream_t st) {
+  if (tile == 16) hipLaunchKernelGGL((k_batch1<V, 16, ST>), dim3(blocks), dim3(kBlock), 0, st, a);
+  else hipLaunchKernelGGL((k_batch1<V, 32, ST>), dim3(blocks), dim3(kBlock), 0, st, a);
   return hipGetLastError();
 }
 
 template <int V>
+static hipError_t batch1_v(const BatchArgs &a, int tile, unsigned blocks, hipStream_t st, int store) {
+  if (store == 1) return batch1_vs<V, 1>(a, tile, blocks, st);
+  if (store == 2) return batch1_vs<V, 2>(a, tile, blocks, st);
+  return batch1_vs<V, 0>(a, tile, blocks, st);
+}
+
+template <int V>
 static hipError_t batch1_occupancy_v(int tile, int *blocks) {
-  return tile == 16 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, k_batch1<V, 16>, kBlock, 0)
-                    : hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, k_batch1<V, 32>, kBlock, 0);
+  return tile == 16 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, k_batch1<V, 16, 0>, kBlock, 0)
+                    : hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, k_batch1<V, 32, 0>, kBlock, 0);
 }
 
 #define SL_DISPATCH64(v, EXPR)           \
@@ -409,9 +364,10 @@ static hipError_t batch1_occupancy_v(int tile, int *blocks) {
     default: return hipErrorInvalidValue; \
   }
 
-hipError_t launch_batch(const BatchArgs &a, int tile, unsigned blocks, hipStream_t st, int variant) {
+hipError_t launch_batch(const BatchArgs &a, int tile, unsigned blocks, hipStream_t st, int variant,
+                        int store) {
   if (variant >= 0) {
-#define SL_B1(V) batch1_v<V>(a, tile, blocks, st)
+#define SL_B1(V) batch1_v<V>(a, tile, blocks, st, store)
     SL_DISPATCH64(variant, SL_B1)
 #undef SL_B1
   }
@@ -436,28 +392,6 @@ static hipError_t req_v(const ReqArgs &a, hipStream_t st) {
   dim3 grid((a.m + kBlock - 1) / kBlock);
   hipLaunchKernelGGL((k_req_state<V>), grid, dim3(kBlock), 0, st, a);
   return hipGetLastError();
-}
-
-template <int V>
-static hipError_t basis_v(const u64 *state, u64 S, u64 *basis, hipStream_t st) {
-  dim3 grid((unsigned)((S + kBlock - 1) / kBlock));
-  hipLaunchKernelGGL((k_basis<V>), grid, dim3(kBlock), 0, st, state, S, basis);
-  return hipGetLastError();
-}
-
-template <int V>
-static hipError_t req_basis_v(const ReqArgs &a, const u64 *basis, hipStream_t st) {
-  dim3 grid((a.m + (kBlock / kWave) - 1) / (kBlock / kWave));
-  hipLaunchKernelGGL((k_req_state_basis<V>), grid, dim3(kBlock), 0, st, a, basis);
-  return hipGetLastError();
-}
-
-
-hipError_t launch_basis(int variant, const uint64_t *state, uint64_t S, uint64_t *basis,
-                        hipStream_t st) {
-#define SL_B(V) basis_v<V>(state, S, basis, st)
-  SL_DISPATCH64(variant, SL_B)
-#undef SL_B
 }
 
 template <int V>
@@ -488,13 +422,6 @@ hipError_t launch_req_state_digits(int variant, const ReqArgs &a, const uint64_t
 #define SL_RD(V) req_digits_v<V>(a, rows, bits, levels, st)
   SL_DISPATCH64(variant, SL_RD)
 #undef SL_RD
-}
-
-hipError_t launch_req_state_basis(int variant, const ReqArgs &a, const uint64_t *basis,
-                                  hipStream_t st) {
-#define SL_RB(V) req_basis_v<V>(a, basis, st)
-  SL_DISPATCH64(variant, SL_RB)
-#undef SL_RB
 }
 
 hipError_t launch_req_state(int variant, const ReqArgs &a, hipStream_t st) {

@@ -85,17 +85,16 @@ struct ReqArgs {
 };
 
 // The persistent kernel over all tiles: any variant (variant < 0), or the
-// kernel specialised to one variant when every tile is of that variant.
-hipError_t launch_batch(const BatchArgs &a, int tile, unsigned blocks, hipStream_t st, int variant = -1);
+// kernel specialised to one variant when every tile is of that variant, with
+// its output stores write-through (store 0), plain (1) or nontemporal (2);
+// the kernel of all variants always writes through.
+hipError_t launch_batch(const BatchArgs &a, int tile, unsigned blocks, hipStream_t st, int variant = -1,
+                        int store = 0);
 // Workgroups of that kernel that fit on one CU at once (LDS and registers
 // decide).
 hipError_t batch_resident_blocks_per_cu(int tile, int *blocks, int variant = -1);
 hipError_t launch_req_state(int variant, const ReqArgs &a, hipStream_t st);
 
-// Basis states of S resident streams (word-major states): B_j[i] = s_j M^i,
-// i < n, at basis[(j n + i) k + w] (n k words per stream).
-hipError_t launch_basis(int variant, const uint64_t *state, uint64_t S, uint64_t *basis,
-                        hipStream_t st);
 // Rows of digit matrices: entry e of `polys` (16 words each, x^(J_e) mod p)
 // gives rows e_i M^(J_e), i < n, at rows[(e n + i) k + w].
 hipError_t launch_digit_rows(int variant, const uint64_t *polys, unsigned entries, uint64_t *rows,
@@ -105,9 +104,4 @@ hipError_t launch_digit_rows(int variant, const uint64_t *polys, unsigned entrie
 // M^(d 2^(bits l))), one wave per request; origins from origin_state or seeds.
 hipError_t launch_req_state_digits(int variant, const ReqArgs &a, const uint64_t *rows, int bits,
                                    int levels, hipStream_t st);
-// Request states of resident-origin requests from their streams' bases (one
-// wave per request; uses origin_idx, polys, slot, req_state and m).
-hipError_t launch_req_state_basis(int variant, const ReqArgs &a, const uint64_t *basis,
-                                  hipStream_t st);
-
 }  // namespace slrng

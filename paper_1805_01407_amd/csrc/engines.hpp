@@ -178,7 +178,22 @@ SL_HD u64 output(const u64 (&s)[Params<V>::k]) {
 
 // ---------------------------------------------------------------- step
 
-template <int V, int P>
+// The step's rotations and three-way xors, either as the VALU forms above or
+// (SCALAR) as plain shifts and xors, which the compiler can keep on the
+// scalar unit when the state is the same in every lane.
+template <int R, bool SCALAR>
+SL_HD u64 rot_sel(u64 x) {
+  if constexpr (SCALAR) return (x << R) | (x >> (64 - R));
+  else return rotl<R>(x);
+}
+
+template <bool SCALAR>
+SL_HD u64 xor3_sel(u64 a, u64 b, u64 c) {
+  if constexpr (SCALAR) return a ^ b ^ c;
+  else return xor3(a, b, c);
+}
+
+template <int V, int P, bool SCALAR = false>
 SL_HD void step(u64 (&s)[Params<V>::k]) {
   using Q = Params<V>;
   constexpr int K = Q::k;
@@ -190,20 +205,20 @@ SL_HD void step(u64 (&s)[Params<V>::k]) {
     // the updated pair lands in the slots of s[q] and s[p] of the figure:
     // for two words that is s[0] and s[1]; for 16 words s[P+15] and s[P]
     if constexpr (K == 2) {
-      s[0] = xor3(rotl<Q::a>(s0), t, t << Q::b);
-      s[1] = rotl<Q::c>(t);
+      s[0] = xor3_sel<SCALAR>(rot_sel<Q::a, SCALAR>(s0), t, t << Q::b);
+      s[1] = rot_sel<Q::c, SCALAR>(t);
     } else {
-      s[il] = xor3(rotl<Q::a>(s0), t, t << Q::b);
-      s[i0] = rotl<Q::c>(t);
+      s[il] = xor3_sel<SCALAR>(rot_sel<Q::a, SCALAR>(s0), t, t << Q::b);
+      s[i0] = rot_sel<Q::c, SCALAR>(t);
     }
   } else if constexpr (K == 4) {
     // the figure's six in-place updates, each word written once from the
     // old values: s2 ^= s0; s3 ^= s1; s1 ^= s2; s0 ^= s3; s2 ^= t; rotate s3
     const u64 t = s[1] << Q::a;
-    const u64 n0 = xor3(s[0], s[3], s[1]);
-    const u64 n1 = xor3(s[1], s[2], s[0]);
-    const u64 n2 = xor3(s[2], s[0], t);
-    const u64 n3 = rotl<Q::b>(s[3] ^ s[1]);
+    const u64 n0 = xor3_sel<SCALAR>(s[0], s[3], s[1]);
+    const u64 n1 = xor3_sel<SCALAR>(s[1], s[2], s[0]);
+    const u64 n2 = xor3_sel<SCALAR>(s[2], s[0], t);
+    const u64 n3 = rot_sel<Q::b, SCALAR>(s[3] ^ s[1]);
     s[0] = n0;
     s[1] = n1;
     s[2] = n2;
@@ -213,13 +228,13 @@ SL_HD void step(u64 (&s)[Params<V>::k]) {
     // s7 ^= s3; s3 ^= s4; s4 ^= s5; s0 ^= s6; s6 ^= s7; s6 ^= t; rotate s7
     const u64 t = s[1] << Q::a;
     const u64 n0 = s[0] ^ s[6];
-    const u64 n1 = xor3(s[1], s[2], s[0]);
+    const u64 n1 = xor3_sel<SCALAR>(s[1], s[2], s[0]);
     const u64 n2 = s[2] ^ s[0];
     const u64 n3 = s[3] ^ s[4];
-    const u64 n4 = xor3(s[4], s[5], s[1]);
+    const u64 n4 = xor3_sel<SCALAR>(s[4], s[5], s[1]);
     const u64 n5 = s[5] ^ s[1];
-    const u64 n6 = xor3(s[6], s[7], s[3] ^ t);
-    const u64 n7 = rotl<Q::b>(s[7] ^ s[3]);
+    const u64 n6 = xor3_sel<SCALAR>(s[6], s[7], s[3] ^ t);
+    const u64 n7 = rot_sel<Q::b, SCALAR>(s[7] ^ s[3]);
     s[0] = n0;
     s[1] = n1;
     s[2] = n2;

@@ -119,6 +119,44 @@ __device__ __forceinline__ void jump_lane(u64 (&s)[Params<V>::k], GetWord &&r_wo
   for (int j = 0; j < K; j++) s[j] = acc[j];
 }
 
+// The same when the start state s is the same in every lane (the chunks of
+// one request in a run tile), each lane with its own polynomial: the state
+// sequence s M^i is common to the wave, so it advances once, on the scalar
+// unit, and each lane only accumulates its own selection of it.
+__device__ __forceinline__ u64 uniform64(u64 x) {
+  const u64 lo = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)x);
+  const u64 hi = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)(x >> 32));
+  return lo | (hi << 32);
+}
+
+template <int V, typename GetWord>
+__device__ __forceinline__ void jump_lane_from_uniform(u64 (&s)[Params<V>::k], GetWord &&r_word) {
+  constexpr int K = Params<V>::k;
+  constexpr int BLK = block_steps<V>();
+  u64 su[K], acc[K];
+#pragma unroll
+  for (int j = 0; j < K; j++) {
+    su[j] = uniform64(s[j]);
+    acc[j] = 0;
+  }
+  for (int wi = 0; wi < K; wi++) {
+    const u64 word = r_word(wi);
+    const unsigned half[2] = {(unsigned)word, (unsigned)(word >> 32)};
+#pragma unroll
+    for (int h = 0; h < 2; h++) {
+      for (int b = 0; b < 32; b += BLK) {
+        static_for<BLK>([&](auto P) {
+          const unsigned m = (unsigned)__builtin_amdgcn_sbfe((int)half[h], b + P, 1);
+          acc_xor_masked<V, P>(acc, su, m);
+          step<V, P, true>(su);
+        });
+      }
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < K; j++) s[j] = acc[j];
+}
+
 // ---------------------------------------------------------------- generation tiles
 
 template <int T>

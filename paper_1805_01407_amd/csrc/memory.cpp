@@ -16,8 +16,13 @@
 //     and the others are released at once, so the kept pieces lie about
 //     gap x P apart (gap = 4, lower when free memory is short; the full
 //     gap x M x P bytes are held only during the call);
-//   * the kept pieces are mapped back to back into one reserved virtual range
-//     aligned to P, read-write for the current device.
+//   * the kept pieces are mapped into one reserved virtual range aligned to
+//     P, read-write for the current device, in bit-reversed order of their
+//     creation (virtual piece v holds kept piece rev(v)): a contiguous part of
+//     the buffer is then spread over the whole physical span too, not only
+//     the buffer as a whole (measured: 1-17 GB written into the first pieces
+//     of a 32 GiB buffer mapped in creation order ran at 5.3-5.5 TB/s, the
+//     whole buffer at 6.4).
 // Requests below 1 GiB are a plain device allocation, and so is any request
 // on a device without the virtual memory API or whose pieces cannot be mapped
 // (placement changes speed only, never values).
@@ -95,15 +100,32 @@ hipError_t take_pieces(int dev, uint64_t P, uint64_t M, int gap,
   return hipSuccess;
 }
 
+// The indices 0 .. M-1 in bit-reversed order (of ceil(log2 M) bits, the
+// values >= M skipped): every run of consecutive entries is spread over the
+// whole range.
+std::vector<uint64_t> bit_reversed_order(uint64_t M) {
+  int bits = 0;
+  while ((1ull << bits) < M) bits++;
+  std::vector<uint64_t> order;
+  order.reserve(M);
+  for (uint64_t i = 0; i < (1ull << bits); i++) {
+    uint64_t r = 0;
+    for (int b = 0; b < bits; b++) r |= ((i >> b) & 1) << (bits - 1 - b);
+    if (r < M) order.push_back(r);
+  }
+  return order;
+}
+
 hipError_t map_pieces(int dev, uint64_t P, std::vector<hipMemGenericAllocationHandle_t> &keep,
                       void **out) {
   const uint64_t span = P * keep.size();
   void *va = nullptr;
   hipError_t e = hipMemAddressReserve(&va, span, P, nullptr, 0);
   if (e != hipSuccess) return e;
+  const std::vector<uint64_t> order = bit_reversed_order(keep.size());
   uint64_t mapped = 0;
   for (; mapped < keep.size(); mapped++) {
-    e = hipMemMap(static_cast<char *>(va) + mapped * P, P, 0, keep[mapped], 0);
+    e = hipMemMap(static_cast<char *>(va) + mapped * P, P, 0, keep[order[mapped]], 0);
     if (e != hipSuccess) break;
   }
   if (e == hipSuccess) {

@@ -41,6 +41,7 @@
 #include "batch.hpp"
 #include "batch_plan.hpp"
 #include "kernels.hpp"
+#include "memory.hpp"
 
 using namespace slrng;
 
@@ -287,7 +288,7 @@ static int launch_iteration(slrng_server *sv, int si, const std::vector<PlanReq>
     e = hipEventRecord(s.evk, st);
     if (e != hipSuccess) return hip_fail(e);
     const unsigned blocks = std::min<unsigned>(sv->blocks, ((unsigned)P.tiles.size() + 3) / 4);
-    e = launch_batch(a, sv->bo.tile, blocks, st, sv->o.variant);
+    e = launch_batch(a, sv->bo.tile, blocks, st, sv->o.variant, sv->o.store);
     if (e != hipSuccess) return hip_fail(e);
   } else {
     e = hipEventRecord(s.evk, st);
@@ -476,7 +477,10 @@ static void destroy_server(slrng_server *sv) {
     free_slot(s);
   }
   if (sv->ref) (void)hipEventDestroy(sv->ref);
-  if (sv->arena_dev) (void)hipFree(sv->arena_dev);
+  if (sv->arena_dev) {
+    if (sv->o.arena_plain) (void)hipFree(sv->arena_dev);
+    else (void)spread_free(sv->arena_dev);
+  }
   if (sv->streams) slrng_streams_destroy(sv->streams);
   delete sv;
 }
@@ -491,7 +495,8 @@ extern "C" int slrng_server_create(const slrng_server_opts *opts, slrng_server *
     if (!valid_variant64(o.variant) || o.n_streams == 0 || o.budget_bytes < kAlign) return SLRNG_EINVAL;
     if (o.max_batch <= 0) o.max_batch = 4096;
     if (o.inflight <= 0) o.inflight = 3;
-    if (o.inflight > 8 || o.min_chunk < 0 || o.window_us < 0) return SLRNG_EINVAL;
+    if (o.inflight > 8 || o.min_chunk < 0 || o.window_us < 0 || o.store < 0 || o.store > 2)
+      return SLRNG_EINVAL;
     if (o.tile == 0) o.tile = 32;
     slrng_batch_opts bo;
     slrng_batch_default_opts(&bo);
@@ -524,10 +529,11 @@ extern "C" int slrng_server_create(const slrng_server_opts *opts, slrng_server *
       if (e != hipSuccess) rc = hip_fail(e);
     }
     if (!rc) {
-      // a plain allocation: served iterations are latency-bound, and spreading
-      // the arena's physical pages (slrng_output_alloc) measured no faster
-      // while holding four times the budget during creation
-      e = hipMalloc(&sv->arena_dev, o.budget_bytes);
+      // spread physical pages by default: iterations of hundreds of MB and
+      // more write measurably faster there (creation briefly holds a few
+      // times the budget); a plain allocation on request
+      e = o.arena_plain ? hipMalloc(&sv->arena_dev, o.budget_bytes)
+                        : spread_alloc(o.budget_bytes, (void **)&sv->arena_dev);
       if (e != hipSuccess) rc = e == hipErrorOutOfMemory ? SLRNG_ENOMEM : hip_fail(e);
     }
     if (!rc) {
