@@ -241,8 +241,9 @@ int slrng_streams_destroy(slrng_streams *h);
  * reach 6.5-6.9 TB/s.  From 1 GiB up the buffer is made of physical pieces of
  * P = 256 MiB .. 1 GiB (a power of two near bytes / 64): gap x M pieces are
  * created in order, every gap-th is kept and the others are returned at once
- * (gap = 4, lower when free memory is short: gap x M x P bytes are held only
- * during the call); the kept pieces are mapped into one virtual range aligned
+ * (gap = 16, lower when free memory is short: gap x M x P bytes are held
+ * only during the call, so a 32 GiB buffer gets about 8 on an empty device);
+ * the kept pieces are mapped into one virtual range aligned
  * to P in bit-reversed order of their creation, so that any contiguous part
  * of the buffer is spread over the whole span too (a few GB written into the
  * start of a buffer measured 6.1-6.5 TB/s this way, 5.3-5.5 in creation
@@ -462,7 +463,7 @@ typedef struct slrng_server_opts {
                             the next iteration) ... */
   int32_t min_chunk;     /* smallest lane-chunk (outputs) when the chunk length is
                             fitted to an iteration (0 = default: the larger of
-                            512 and 2n, n the state bits) */
+                            64 and n/2, n the state bits) */
   uint64_t window_bytes; /* ... or until this many bytes are pending */
   int32_t arena_plain;   /* 1: the arena is one plain device allocation; 0 (default):
                             memory from slrng_output_alloc (physical pages spread

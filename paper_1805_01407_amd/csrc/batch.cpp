@@ -98,7 +98,7 @@ void chunk_table_host(int engine, uint64_t C, uint32_t n, std::vector<uint64_t> 
 }
 
 std::mutex g_dr_mu;
-std::map<std::pair<int, int>, DigitRows> g_dr;  // (device, engine)
+std::map<std::pair<int, int>, DigitMatrices> g_dr;  // (device, engine)
 
 // Relative cost of one output per variant (engine and scrambler work), for
 // ordering tiles heaviest first.
@@ -108,10 +108,10 @@ uint64_t output_cost(int v) { return (v >= 6 && v <= 8) ? 3 : 2; }
 
 namespace slrng {
 
-int digit_rows(int device, int variant, DigitRows *out) {
+int digit_matrices(int device, int variant, DigitMatrices *out) {
   std::lock_guard<std::mutex> g(g_dr_mu);
   const int engine = variant_engine(variant);
-  DigitRows &t = g_dr[std::make_pair(device, engine)];
+  DigitMatrices &t = g_dr[std::make_pair(device, engine)];
   if (t.dev) {
     *out = t;
     return SLRNG_OK;
@@ -137,18 +137,18 @@ int digit_rows(int device, int variant, DigitRows *out) {
       cur = nx;
     }
   }
-  uint64_t *polys = nullptr, *rows = nullptr;
+  uint64_t *polys = nullptr, *cols = nullptr;
   HIPCHK(hipMalloc(&polys, h.size() * 8));
-  hipError_t e = hipMalloc(&rows, (size_t)entries * f.n * K * 8);
+  hipError_t e = hipMalloc(&cols, (size_t)entries * f.n * K * 8);
   if (e == hipSuccess) e = hipMemcpy(polys, h.data(), h.size() * 8, hipMemcpyHostToDevice);
-  if (e == hipSuccess) e = launch_digit_rows(variant, polys, entries, rows, nullptr);
+  if (e == hipSuccess) e = launch_digit_cols(variant, polys, entries, cols, nullptr);
   if (e == hipSuccess) e = hipStreamSynchronize(nullptr);
   (void)hipFree(polys);
   if (e != hipSuccess) {
-    if (rows) (void)hipFree(rows);
+    if (cols) (void)hipFree(cols);
     return e == hipErrorOutOfMemory ? SLRNG_ENOMEM : hip_fail(e);
   }
-  t.dev = rows;
+  t.dev = cols;
   t.bits = bits;
   t.levels = levels;
   *out = t;
@@ -179,9 +179,11 @@ static uint64_t option_chunk(const slrng_batch_opts &o, int v) {
   return c;
 }
 
-// Smallest fitted chunk: the option, else the larger of 512 and 2n.
+// Smallest fitted chunk: the option, else the larger of 64 and n/2 (128 for
+// xoshiro256: short requests spread over more lanes; the run tiles' jumps
+// from the request's common start state are cheap enough for that).
 static uint64_t fit_floor_for(int v, uint64_t fit_floor) {
-  return fit_floor ? fit_floor : std::max<uint64_t>(512, 2 * 64 * (uint64_t)variant_words(v));
+  return fit_floor ? fit_floor : std::max<uint64_t>(64, 32 * (uint64_t)variant_words(v));
 }
 
 int warm_fit_tables(int device, int variant, const slrng_batch_opts &o, uint64_t fit_floor) {

@@ -244,37 +244,52 @@ __global__ __launch_bounds__(kBlock) void k_req_state(ReqArgs a) {
   }
 }
 
-// Rows of the digit matrices: rows[(e n + i) k + w] = word w of e_i M^(J_e),
-// where e_i is the state whose only set bit is bit i (word i / 64, bit i % 64,
-// logical order) and x^(J_e) mod p is polys[e * 16 ..] (one lane per row).
+// Columns of the digit matrices.  Matrix e is M^(J_e) with x^(J_e) mod p =
+// polys[e * 16 ..]; its row i is e_i M^(J_e), e_i the state whose only set
+// bit is bit i (word i / 64, bit i % 64, logical order), and its column b is
+// stored as k words: bit r of word w is bit b of row 64 w + r, at
+// cols[(e n + b) k + w].  One lane per row: the lane steps e_i through the
+// jump, then each wave turns its 64 rows into one word of every column with
+// one ballot per bit.
 template <int V>
-__global__ __launch_bounds__(kBlock) void k_digit_rows(const u64 *__restrict__ polys,
-                                                       u64 *__restrict__ rows) {
+__global__ __launch_bounds__(kBlock) void k_digit_cols(const u64 *__restrict__ polys,
+                                                       u64 *__restrict__ cols) {
   constexpr int K = Params<V>::k;
   constexpr int N = 64 * K;
   const unsigned i = blockIdx.x * kBlock + threadIdx.x;
   if (i - (threadIdx.x % kWave) >= (unsigned)N) return;  // uniform per wave (64 divides N)
+  const int lane = threadIdx.x % kWave;
+  const unsigned w = i / 64;  // this wave's word of every column
   const u64 e = blockIdx.y;
   u64 s[K];
 #pragma unroll
-  for (int w = 0; w < K; w++) s[w] = (w == (int)(i / 64)) ? (u64)1 << (i % 64) : 0;
+  for (int q = 0; q < K; q++) s[q] = (q == (int)w) ? (u64)1 << (i % 64) : 0;
   jump_uniform<V>(s, polys + e * 16);
+  u64 *out = cols + e * N * K;
 #pragma unroll
-  for (int w = 0; w < K; w++) rows[(e * N + i) * K + w] = s[w];
+  for (int q = 0; q < K; q++) {
+    for (int r = 0; r < 64; r++) {
+      const u64 m = __ballot((int)((s[q] >> r) & 1));
+      if (lane == r) out[(u64)(64 * q + r) * K + w] = m;
+    }
+  }
 }
 
 // Request start states from a 128-bit position, all on the device: s M^pos is
 // the origin s multiplied, for every nonzero digit d_l of pos in radix 2^bits,
-// by the matrix M^(d_l 2^(bits l)), whose rows are in `rows` (entry
-// l 2^bits + d_l).  A product s M^J is the xor of the rows selected by the set
-// bits of s: one wave per request, lane `lane` takes rows lane, lane + 64, ...
-// (consecutive lanes read consecutive rows), then an xor reduction across the
-// wave leaves the product in every lane for the next digit.
+// by the matrix M^(d_l 2^(bits l)) (entry l 2^bits + d_l of `cols`).  One
+// wave per request; bit b of s M^J is the parity of s AND column b: lane
+// `lane` takes bits lane, lane + 64, ... (consecutive lanes read consecutive
+// columns), and one ballot per state word gathers the product, the same in
+// every lane, for the next digit.  The columns a digit needs do not depend on
+// the state, so the next nonzero digit's are loaded while the current one is
+// applied (two-, four-word engines).
 template <int V>
-__global__ __launch_bounds__(kBlock) void k_req_state_digits(ReqArgs a, const u64 *__restrict__ rows,
+__global__ __launch_bounds__(kBlock) void k_req_state_digits(ReqArgs a, const u64 *__restrict__ cols,
                                                              int bits, int levels) {
   constexpr int K = Params<V>::k;
   constexpr int N = 64 * K;
+  constexpr bool kAhead = K <= 4;
   const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
   const unsigned r = blockIdx.x * (kBlock / kWave) + wave;
   if (r >= a.m) return;  // uniform per wave
@@ -288,36 +303,60 @@ __global__ __launch_bounds__(kBlock) void k_req_state_digits(ReqArgs a, const u6
   }
   const u64 pos[2] = {a.pos[2 * (u64)r], a.pos[2 * (u64)r + 1]};
   const u64 dmask = ((u64)1 << bits) - 1;
-  for (int l = 0; l < levels; l++) {
+  auto digit = [&](int l) -> unsigned {
     const int b0 = l * bits;  // bits divides 64: a digit never straddles the two words
-    const unsigned d = (unsigned)((pos[b0 >> 6] >> (b0 & 63)) & dmask);
-    if (!d) continue;  // uniform
-    const u64 *R = rows + ((((u64)l << bits) + d) * N) * K;
-    unsigned lo[K], hi[K];
-#pragma unroll
-    for (int w = 0; w < K; w++) lo[w] = hi[w] = 0;
+    return (unsigned)((pos[b0 >> 6] >> (b0 & 63)) & dmask);
+  };
+  auto next_level = [&](int l) {
+    while (l < levels && !digit(l)) l++;
+    return l;
+  };
+  // this lane's columns of one matrix: K columns of K words
+  auto load = [&](int l, u64 (&c)[K][K]) {
+    const u64 *C = cols + ((((u64)l << bits) + digit(l)) * N) * K;
 #pragma unroll
     for (int q = 0; q < K; q++) {
-      if ((s[q] >> lane) & 1) {
-        const u64 *row = R + (u64)(64 * q + lane) * K;
 #pragma unroll
-        for (int w = 0; w < K; w++) {
-          const u64 v = row[w];
-          lo[w] ^= (unsigned)v;
-          hi[w] ^= (unsigned)(v >> 32);
-        }
-      }
+      for (int w = 0; w < K; w++) c[q][w] = C[(u64)(64 * q + lane) * K + w];
     }
+  };
+  auto apply = [&](const u64 (&c)[K][K]) {
+    u64 t[K];
 #pragma unroll
-    for (int off = kWave / 2; off > 0; off >>= 1) {
+    for (int q = 0; q < K; q++) {
+      unsigned cnt = 0;
 #pragma unroll
       for (int w = 0; w < K; w++) {
-        lo[w] ^= (unsigned)__shfl_xor((int)lo[w], off);
-        hi[w] ^= (unsigned)__shfl_xor((int)hi[w], off);
+        const u64 v = s[w] & c[q][w];
+        cnt += __popc((unsigned)v) + __popc((unsigned)(v >> 32));
       }
+      t[q] = __ballot((int)(cnt & 1));
     }
 #pragma unroll
-    for (int w = 0; w < K; w++) s[w] = ((u64)hi[w] << 32) | lo[w];
+    for (int q = 0; q < K; q++) s[q] = t[q];
+  };
+  int l = next_level(0);
+  if constexpr (kAhead) {
+    u64 cur[K][K], nxt[K][K];
+    if (l < levels) load(l, cur);
+    while (l < levels) {
+      const int ln = next_level(l + 1);
+      if (ln < levels) load(ln, nxt);
+      apply(cur);
+#pragma unroll
+      for (int q = 0; q < K; q++) {
+#pragma unroll
+        for (int w = 0; w < K; w++) cur[q][w] = nxt[q][w];
+      }
+      l = ln;
+    }
+  } else {
+    while (l < levels) {
+      u64 cur[K][K];
+      load(l, cur);
+      apply(cur);
+      l = next_level(l + 1);
+    }
   }
   if (lane == 0) {
 #pragma unroll
@@ -395,31 +434,31 @@ static hipError_t req_v(const ReqArgs &a, hipStream_t st) {
 }
 
 template <int V>
-static hipError_t digit_rows_v(const u64 *polys, unsigned entries, u64 *rows, hipStream_t st) {
+static hipError_t digit_cols_v(const u64 *polys, unsigned entries, u64 *cols, hipStream_t st) {
   constexpr int N = 64 * Params<V>::k;
   dim3 grid((N + kBlock - 1) / kBlock, entries);
-  hipLaunchKernelGGL((k_digit_rows<V>), grid, dim3(kBlock), 0, st, polys, rows);
+  hipLaunchKernelGGL((k_digit_cols<V>), grid, dim3(kBlock), 0, st, polys, cols);
   return hipGetLastError();
 }
 
 template <int V>
-static hipError_t req_digits_v(const ReqArgs &a, const u64 *rows, int bits, int levels, hipStream_t st) {
+static hipError_t req_digits_v(const ReqArgs &a, const u64 *cols, int bits, int levels, hipStream_t st) {
   dim3 grid((a.m + (kBlock / kWave) - 1) / (kBlock / kWave));
-  hipLaunchKernelGGL((k_req_state_digits<V>), grid, dim3(kBlock), 0, st, a, rows, bits, levels);
+  hipLaunchKernelGGL((k_req_state_digits<V>), grid, dim3(kBlock), 0, st, a, cols, bits, levels);
   return hipGetLastError();
 }
 
-hipError_t launch_digit_rows(int variant, const uint64_t *polys, unsigned entries, uint64_t *rows,
+hipError_t launch_digit_cols(int variant, const uint64_t *polys, unsigned entries, uint64_t *cols,
                              hipStream_t st) {
-#define SL_DR(V) digit_rows_v<V>(polys, entries, rows, st)
+#define SL_DR(V) digit_cols_v<V>(polys, entries, cols, st)
   SL_DISPATCH64(variant, SL_DR)
 #undef SL_DR
 }
 
-hipError_t launch_req_state_digits(int variant, const ReqArgs &a, const uint64_t *rows, int bits,
+hipError_t launch_req_state_digits(int variant, const ReqArgs &a, const uint64_t *cols, int bits,
                                    int levels, hipStream_t st) {
   if (a.m == 0) return hipSuccess;
-#define SL_RD(V) req_digits_v<V>(a, rows, bits, levels, st)
+#define SL_RD(V) req_digits_v<V>(a, cols, bits, levels, st)
   SL_DISPATCH64(variant, SL_RD)
 #undef SL_RD
 }

@@ -95,13 +95,14 @@ hipError_t launch_batch(const BatchArgs &a, int tile, unsigned blocks, hipStream
 hipError_t batch_resident_blocks_per_cu(int tile, int *blocks, int variant = -1);
 hipError_t launch_req_state(int variant, const ReqArgs &a, hipStream_t st);
 
-// Rows of digit matrices: entry e of `polys` (16 words each, x^(J_e) mod p)
-// gives rows e_i M^(J_e), i < n, at rows[(e n + i) k + w].
-hipError_t launch_digit_rows(int variant, const uint64_t *polys, unsigned entries, uint64_t *rows,
+// Columns of digit matrices: entry e of `polys` (16 words each, x^(J_e) mod
+// p) gives the matrix M^(J_e); its column b at cols[(e n + b) k + w], bit r of
+// word w being bit b of row 64 w + r (row i = e_i M^(J_e)).
+hipError_t launch_digit_cols(int variant, const uint64_t *polys, unsigned entries, uint64_t *cols,
                              hipStream_t st);
 // Request states s M^pos from 128-bit positions (a.pos) with the digit
 // matrices of radix 2^bits (`levels` digits; entry l 2^bits + d holds
 // M^(d 2^(bits l))), one wave per request; origins from origin_state or seeds.
-hipError_t launch_req_state_digits(int variant, const ReqArgs &a, const uint64_t *rows, int bits,
+hipError_t launch_req_state_digits(int variant, const ReqArgs &a, const uint64_t *cols, int bits,
                                    int levels, hipStream_t st);
 }  // namespace slrng

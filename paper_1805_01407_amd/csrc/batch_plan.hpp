@@ -59,8 +59,8 @@ struct PlanHost {
 // Builds the plan.  `grid_lanes` is the persistent grid size in lanes (used to
 // size the plain form's chunks, and with `fit` those of the whole batch: the
 // chunk length shrinks until the batch's lane-chunks cover the grid about
-// four times over, down to `fit_floor` outputs, by default the larger of 512
-// and 2n so that the per-lane jump of n steps stays amortised); `from_state`
+// four times over, down to `fit_floor` outputs, by default the larger of 64
+// and n/2); `from_state`
 // requests always get a request state.  With `host_tables` the chunk tables
 // are computed into host_tab (tab_n entries each, word-major; tab stays null)
 // instead of being taken from the device cache, so that planning allocates no
@@ -76,16 +76,16 @@ int build_plan(const PlanReq *reqs, size_t n, const slrng_batch_opts &o, int dev
 int warm_fit_tables(int device, int variant, const slrng_batch_opts &o, uint64_t fit_floor);
 
 // Digit matrices of one engine on one device, for positioning requests from a
-// 128-bit position entirely on the device: entry l 2^bits + d holds the n rows
-// e_i M^(d 2^(bits l)) (k words each), l < levels = 128 / bits.  Built once
-// per (device, engine) with a kernel, kept until the process ends: 8-bit
+// 128-bit position entirely on the device: entry l 2^bits + d holds the n
+// columns (k words each) of M^(d 2^(bits l)), l < levels = 128 / bits.  Built
+// once per (device, engine) with a kernel, kept until the process ends: 8-bit
 // digits for n <= 256 (32 MiB for n = 256), 4-bit digits above (64 MiB for
 // n = 1024).
-struct DigitRows {
+struct DigitMatrices {
   const uint64_t *dev = nullptr;
   int bits = 0, levels = 0;
 };
-int digit_rows(int device, int variant, DigitRows *out);
+int digit_matrices(int device, int variant, DigitMatrices *out);
 
 // The persistent grid (blocks of 4 waves) for the options on `device`, for
 // the kernel of all variants or (variant >= 0) the one specialised to it.

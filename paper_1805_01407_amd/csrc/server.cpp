@@ -159,7 +159,7 @@ struct slrng_server {
   unsigned blocks = 0;
   slrng_streams *streams = nullptr;
   uint8_t *arena_dev = nullptr;
-  DigitRows digits;  // the engine's digit matrices (positioning from 128-bit positions)
+  DigitMatrices digits;  // the engine's digit matrices (positioning from 128-bit positions)
   Arena arena;
   std::vector<uint64_t> head, head_hi;  // next position of each stream (128-bit)
 
@@ -523,7 +523,7 @@ extern "C" int slrng_server_create(const slrng_server_opts *opts, slrng_server *
     // the engine's digit matrices: a request's start state s_j M^pos is then
     // computed on the device from the digits of pos (built once per device
     // and engine)
-    if (!rc) rc = digit_rows(sv->device, o.variant, &sv->digits);
+    if (!rc) rc = digit_matrices(sv->device, o.variant, &sv->digits);
     if (!rc) {
       e = hipDeviceSynchronize();
       if (e != hipSuccess) rc = hip_fail(e);
