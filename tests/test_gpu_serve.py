@@ -290,7 +290,9 @@ def test_served_trace_values_at_workload_shape(P):
     64 B .. 256 MiB) through the default server (16 GiB budget), submitted as
     one burst so that admission blocks on the budget: every request of at
     most 1 MiB compared in full with the oracle, larger ones on their first
-    and last 4,096 outputs, all at the positions the server assigned."""
+    and last 4,096 outputs and on eight interior blocks of 512 outputs, each
+    straddling a multiple of 8,192 (a lane-chunk boundary for every chunk
+    length the server can fit), all at the positions the server assigned."""
     import queue
     from concurrent.futures import ThreadPoolExecutor
     from paper_1805_01407_amd import workloads as W
@@ -311,9 +313,12 @@ def test_served_trace_values_at_workload_shape(P):
             t, st, n = item
             ptr, pos = P.slrng_server_wait(sv, t)
             if n <= 131072:
-                results.append((st, pos, n, d2h(ptr, n), None))
+                results.append((st, pos, n, d2h(ptr, n), None, []))
             else:
-                results.append((st, pos, n, d2h(ptr, 4096), d2h(ptr + 8 * (n - 4096), 4096)))
+                rng = np.random.default_rng(t)
+                offs = sorted({int(m) * 8192 - 256 for m in rng.integers(1, n // 8192, 8)})
+                blocks = [(o, d2h(ptr + 8 * o, 512)) for o in offs]
+                results.append((st, pos, n, d2h(ptr, 4096), d2h(ptr + 8 * (n - 4096), 4096), blocks))
             P.slrng_server_release(sv, t)
 
     th = threading.Thread(target=consumer)
@@ -332,13 +337,17 @@ def test_served_trace_values_at_workload_shape(P):
     p = O.charpoly(g)
 
     def check(res):
-        st, pos, n, head, tail = res
+        st, pos, n, head, tail, blocks = res
         x = O.jump_poly(g, chain[st], O.xpow_mod(pos, p)) if pos else chain[st]
         if tail is None:
             return np.array_equal(head, O.generate(g, x, n)[0])
         y = O.jump_poly(g, x, O.xpow_mod(n - 4096, p))
-        return (np.array_equal(head, O.generate(g, x, 4096)[0]) and
-                np.array_equal(tail, O.generate(g, y, 4096)[0]))
+        ok = (np.array_equal(head, O.generate(g, x, 4096)[0]) and
+              np.array_equal(tail, O.generate(g, y, 4096)[0]))
+        for o, blk in blocks:
+            z = O.jump_poly(g, x, O.xpow_mod(o, p))
+            ok = ok and np.array_equal(blk, O.generate(g, z, 512)[0])
+        return ok
 
     with ThreadPoolExecutor(16) as ex:
         ok = list(ex.map(check, results))
