@@ -414,8 +414,11 @@ int slrng_batch_run_static(const slrng_request *reqs, size_t n_reqs, const slrng
  * thread batches every pending request into one iteration (request-state
  * kernel + persistent generation kernel) and launches it on one of
  * `inflight` HIP streams while earlier iterations still run; one completion
- * thread per stream stamps latencies when its iteration's event completes, so
- * iterations complete in any order.  Latency runs from the request's arrival
+ * thread per stream stamps latencies when its iteration completes, so
+ * iterations complete in any order.  The generation kernel's last wave
+ * signals completion through pinned host memory, once every output of the
+ * iteration is visible device-wide; the completion thread polls that signal
+ * (up to 2 ms, then it blocks on the stream's end event).  Latency runs from the request's arrival
  * (the submit call, before any wait for arena space; for slrng_server_replay
  * the scheduled arrival time) to the completion of its iteration.  Outputs are
  * read from the arena pointer that poll/wait return, then released
@@ -430,7 +433,9 @@ int slrng_batch_run_static(const slrng_request *reqs, size_t n_reqs, const slrng
  *   (requests admitted later start that much further; earlier ones keep their
  *   positions).  EINVAL for a bad stream id.
  * slrng_server_intervals: the generation kernels' device intervals, one per
- *   iteration in completion order (ms from a reference event of the server),
+ *   iteration in completion order: from the claim of the first tile to the
+ *   end of the last wave, read from the device clock (wall_clock64) that the
+ *   kernels stamp (ms from the server's creation),
  *   written up to `cap` entries; *count = the number recorded since creation
  *   or the last reset_stats.  Iterations on different HIP streams overlap on
  *   the device when one's interval starts before another's ends.
@@ -439,7 +444,9 @@ int slrng_batch_run_static(const slrng_request *reqs, size_t n_reqs, const slrng
  * slrng_server_drain: waits until every submitted request has completed.
  * slrng_server_get_stats / _reset_stats: counters; latency percentiles of the
  *   completed requests; busy_s is the union of the iterations' device time
- *   (copies and kernels), kernel_s that of the generation kernels alone.
+ *   (from the start of the upload kernel to the end of the generation
+ *   kernel), kernel_s that of the generation kernels alone (the intervals
+ *   above); both from the device clock stamps.
  * slrng_server_replay: submits count requests at the given arrival times
  *   (seconds from the call), with SLRNG_SUBMIT_AUTORELEASE, then drains (a
  *   load generator for benchmarks).

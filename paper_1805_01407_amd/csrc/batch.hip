@@ -158,17 +158,41 @@ __device__ __forceinline__ void batch_tile(const BatchArgs &a, const TileDesc &t
 // gets false exactly once (the claim counter only grows during the launch),
 // and the last wave to get it knows that no wave will claim again: it returns
 // both counters to zero for the next launch, so no reset kernel is needed
-// between launches.
+// between launches.  With a completion signal (a.sig), each wave makes its
+// output stores visible device-wide before it counts itself finished, and
+// the last wave then signals the host (see BatchArgs).  WT: the kernel's
+// output stores are written through the L2 (sc1), so a wave's stores are
+// visible device-wide once they have completed, and waiting for the wave's
+// vector-memory counter is enough (s_waitcnt vmcnt(0), the other counters
+// left at their maximum); other stores also need the L2 written back (an
+// agent-scope release fence, which costs every wave a write-back).
+__device__ __forceinline__ void sig_store(uint64_t *p, uint64_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
+template <bool WT>
 __device__ __forceinline__ bool next_tile(const BatchArgs &a, int lane, unsigned &t) {
   unsigned v = 0;
   if (lane == 0) v = atomicAdd(a.counter, 1u);
   t = (unsigned)__builtin_amdgcn_readfirstlane((int)v);
-  if (t < a.ntiles) return true;
+  if (t < a.ntiles) {
+    if (t == 0 && a.sig && lane == 0) sig_store(a.sig + 2, (uint64_t)wall_clock64());
+    return true;
+  }
+  if (a.sig) {  // uniform
+    if constexpr (WT) __builtin_amdgcn_s_waitcnt(0x0F70);
+    else __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+  }
   if (lane == 0) {
     const unsigned waves = gridDim.x * (kBlock / kWave);
     if (atomicAdd(a.counter + 1, 1u) == waves - 1) {
       atomicExch(a.counter, 0u);
       atomicExch(a.counter + 1, 0u);
+      if (a.sig) {
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        sig_store(a.sig + 3, (uint64_t)wall_clock64());
+        __hip_atomic_store(a.sig, a.seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+      }
     }
   }
   return false;
@@ -186,7 +210,7 @@ __global__ __launch_bounds__(kBlock) void k_batch(BatchArgs a) {
   u64 *rowptr = rowptr_all + wave * kWave;
   unsigned *rowlen = rowlen_all + wave * kWave;
   unsigned t = 0;
-  while (next_tile(a, lane, t)) {
+  while (next_tile<true>(a, lane, t)) {
     const TileDesc td = a.tiles[t];
     switch (td.variant * 2 + td.kind) {
 #define SL_CASE(V)                                                  \
@@ -213,7 +237,7 @@ __global__ __launch_bounds__(kBlock) void k_batch1(BatchArgs a) {
   u64 *rowptr = rowptr_all + wave * kWave;
   unsigned *rowlen = rowlen_all + wave * kWave;
   unsigned t = 0;
-  while (next_tile(a, lane, t)) {
+  while (next_tile<ST == 0>(a, lane, t)) {
     const TileDesc td = a.tiles[t];
     if (td.kind) batch_tile<V, 1, T, ST>(a, td, lds, rowptr, rowlen, lane);
     else batch_tile<V, 0, T, ST>(a, td, lds, rowptr, rowlen, lane);

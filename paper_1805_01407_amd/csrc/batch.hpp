@@ -66,6 +66,12 @@ struct BatchArgs {
   uint32_t tab_n[kNumVariants];
   unsigned *counter;                  // [0] tiles claimed, [1] waves finished: both zero
                                       // at launch; the last wave to finish zeroes them
+  // Completion signal in host-mapped memory, or null: the wave that claims
+  // tile 0 writes the device clock to sig[2]; the last wave to finish, once
+  // the output stores of every wave are visible device-wide, writes the clock
+  // to sig[3] and then seq to sig[0].
+  uint64_t *sig = nullptr;
+  uint64_t seq = 0;
 };
 
 // Request start states: the origin of request i (SplitMix64(seeds[i]), or, when

@@ -156,8 +156,7 @@ extern "C" int slrng_batch_run_static(const slrng_request *reqs, size_t n_reqs,
       at += run.second;
     }
     if (e == hipSuccess) {
-      BatchArgs a;
-      memset(&a, 0, sizeof(a));
+      BatchArgs a{};
       a.tiles = reinterpret_cast<const TileDesc *>(d + o_tiles);
       a.ntiles = (uint32_t)P.tiles.size();
       a.lanes = reinterpret_cast<const LaneDesc *>(d + o_lanes);

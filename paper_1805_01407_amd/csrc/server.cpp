@@ -42,6 +42,7 @@
 #include "batch_plan.hpp"
 #include "kernels.hpp"
 #include "memory.hpp"
+#include "upload.hpp"
 
 using namespace slrng;
 
@@ -111,13 +112,25 @@ struct Req {
   Clock::time_point t_arrival;   // latency origin
 };
 
-// One in-flight slot: a HIP stream, events and reusable buffers.  Everything
-// an iteration reads (the tile claim counter, already zero, then the tile,
-// lane and run descriptors and the request-state inputs) is packed into one
-// pinned buffer and uploaded with a single copy.
+// One in-flight slot: a HIP stream, an end event, a completion signal and
+// reusable buffers.  Everything an iteration reads (the tile claim counter,
+// already zero, then the tile, lane and run descriptors and the request-state
+// inputs) is packed into one pinned buffer and uploaded by one kernel.
+//
+// The signal is four words of coherent pinned memory that the iteration's
+// kernels write: [1] the device clock when the upload starts, [2] when the
+// generation kernel claims its first tile, [3] when its last wave finishes,
+// then [0] the iteration's sequence number, once its outputs are visible
+// device-wide.  The completer watches [0] (the end event only as a fallback),
+// and the busy and kernel intervals come from the clock words, so no timing
+// event sits between the kernels.
 struct Slot {
   hipStream_t st = nullptr;
-  hipEvent_t ev0 = nullptr, evk = nullptr, ev1 = nullptr;  // start, generation kernel start, end
+  hipEvent_t ev1 = nullptr;  // after the iteration's last kernel
+  uint64_t *h_sig = nullptr;  // the signal words (host address)
+  uint64_t *d_sig = nullptr;  // their device mapping
+  uint64_t seq = 0;           // iterations launched on the slot
+  bool signals = false;       // the in-flight iteration runs the generation kernel
   bool busy = false;      // taken by the worker until its iteration has completed
   bool launched = false;  // an iteration is in flight (the slot's completer waits for it)
   std::vector<uint64_t> tickets;  // that iteration's requests
@@ -125,6 +138,7 @@ struct Slot {
   std::thread completer;
   size_t cap_pack = 0, cap_req = 0;
   uint8_t *d_pack = nullptr, *h_pack = nullptr;
+  const uint8_t *h_pack_dev = nullptr;  // h_pack's device mapping, read by the upload kernel
   uint64_t *d_req_state = nullptr;
 };
 
@@ -174,7 +188,8 @@ struct slrng_server {
   int launched = 0;  // slots with an iteration in flight
   bool stop = false, worker_done = false;
   int error = 0;
-  hipEvent_t ref = nullptr;                           // time origin of the busy intervals
+  uint64_t clock_origin = 0;  // device clock at creation: origin of the intervals
+  double clock_khz = 1;       // device clock rate
   std::vector<std::pair<double, double>> busy_ivals;    // device [start, end) ms per iteration
   std::vector<std::pair<double, double>> kernel_ivals;  // generation kernel [start, end) ms
   std::thread worker;
@@ -195,10 +210,16 @@ static int slot_reserve(Slot &s, size_t bytes, size_t nreq) {
     if (s.d_pack) (void)hipFree(s.d_pack);
     if (s.h_pack) (void)hipHostFree(s.h_pack);
     s.d_pack = s.h_pack = nullptr;
+    s.h_pack_dev = nullptr;
     s.cap_pack = 0;
     hipError_t e = hipMalloc((void **)&s.d_pack, n);
-    if (e == hipSuccess) e = hipHostMalloc((void **)&s.h_pack, n, hipHostMallocDefault);
+    // coherent: the upload kernel reads what the host wrote just before its
+    // launch, never a copy cached from the slot's previous iteration
+    if (e == hipSuccess) e = hipHostMalloc((void **)&s.h_pack, n, hipHostMallocCoherent);
+    void *mapped = nullptr;
+    if (e == hipSuccess) e = hipHostGetDevicePointer(&mapped, s.h_pack, 0);
     if (e != hipSuccess) return hip_fail(e);
+    s.h_pack_dev = static_cast<const uint8_t *>(mapped);
     s.cap_pack = n;
   }
   if (nreq > s.cap_req) {
@@ -217,8 +238,7 @@ static void free_slot(Slot &s) {
   if (s.d_pack) (void)hipFree(s.d_pack);
   if (s.d_req_state) (void)hipFree(s.d_req_state);
   if (s.h_pack) (void)hipHostFree(s.h_pack);
-  if (s.ev0) (void)hipEventDestroy(s.ev0);
-  if (s.evk) (void)hipEventDestroy(s.evk);
+  if (s.h_sig) (void)hipHostFree(s.h_sig);
   if (s.ev1) (void)hipEventDestroy(s.ev1);
   if (s.st) (void)hipStreamDestroy(s.st);
 }
@@ -253,8 +273,14 @@ static int launch_iteration(slrng_server *sv, int si, const std::vector<PlanReq>
   const uint32_t *d_slot = reinterpret_cast<const uint32_t *>(d + L.slot);
   unsigned *d_counter = reinterpret_cast<unsigned *>(d + L.counter);
   hipStream_t st = s.st;
-  hipError_t e = hipEventRecord(s.ev0, st);
-  if (e == hipSuccess) e = hipMemcpyAsync(d, h, L.total, hipMemcpyHostToDevice, st);
+  // the upload is a kernel on the slot's stream (reading the pinned buffer),
+  // not a copy-engine transfer: the kernels after it then start without
+  // waiting for a hand-off between engines; it stamps the iteration's start
+  s.seq++;
+  __atomic_store_n(s.h_sig + 2, 0, __ATOMIC_RELAXED);
+  __atomic_store_n(s.h_sig + 3, 0, __ATOMIC_RELAXED);
+  s.signals = false;
+  hipError_t e = launch_upload(d, s.h_pack_dev, L.total, st, s.d_sig + 1);
   if (e != hipSuccess) return hip_fail(e);
   uint32_t off = 0;
   for (auto &run : P.rs.runs) {
@@ -273,8 +299,7 @@ static int launch_iteration(slrng_server *sv, int si, const std::vector<PlanReq>
     off += run.second;
   }
   if (!P.tiles.empty()) {
-    BatchArgs a;
-    memset(&a, 0, sizeof(a));
+    BatchArgs a{};
     a.tiles = d_tiles;
     a.ntiles = (uint32_t)P.tiles.size();
     a.lanes = d_lanes;
@@ -285,14 +310,12 @@ static int launch_iteration(slrng_server *sv, int si, const std::vector<PlanReq>
       a.tab_n[v] = P.tab_n[v];
     }
     a.counter = d_counter;  // zeroed by the upload
-    e = hipEventRecord(s.evk, st);
-    if (e != hipSuccess) return hip_fail(e);
+    a.sig = s.d_sig;
+    a.seq = s.seq;
     const unsigned blocks = std::min<unsigned>(sv->blocks, ((unsigned)P.tiles.size() + 3) / 4);
     e = launch_batch(a, sv->bo.tile, blocks, st, sv->o.variant, sv->o.store);
     if (e != hipSuccess) return hip_fail(e);
-  } else {
-    e = hipEventRecord(s.evk, st);
-    if (e != hipSuccess) return hip_fail(e);
+    s.signals = true;
   }
   e = hipEventRecord(s.ev1, st);
   return e == hipSuccess ? SLRNG_OK : hip_fail(e);
@@ -382,8 +405,29 @@ static void worker_main(slrng_server *sv) {
   }
 }
 
-// Completion of the iterations of one slot: waits for the slot's end event,
-// whatever the other slots are doing.
+// Waits for the slot's in-flight iteration: for its signal when the
+// generation kernel writes one (polled, with the end event queried now and
+// then for errors), else, and after kSpinLimit of polling, for the end event.
+constexpr std::chrono::microseconds kSpinLimit(2000);
+
+static hipError_t wait_iteration(const Slot &s) {
+  if (s.signals) {
+    const Clock::time_point t0 = Clock::now();
+    for (unsigned i = 1;; i++) {
+      if (__atomic_load_n(s.h_sig, __ATOMIC_ACQUIRE) == s.seq) return hipSuccess;
+      if ((i & 255) == 0) {
+        const hipError_t q = hipEventQuery(s.ev1);
+        if (q != hipErrorNotReady) return q;  // complete (the signal is then written) or failed
+        if (Clock::now() - t0 > kSpinLimit) break;
+      }
+      __builtin_ia32_pause();
+    }
+  }
+  return hipEventSynchronize(s.ev1);
+}
+
+// Completion of the iterations of one slot, whatever the other slots are
+// doing.
 static void completer_main(slrng_server *sv, int si) {
   (void)hipSetDevice(sv->device);
   Slot &s = sv->slots[si];
@@ -392,18 +436,16 @@ static void completer_main(slrng_server *sv, int si) {
     s.cv.wait(lk, [&] { return s.launched || sv->worker_done; });
     if (!s.launched) return;  // the worker has exited and this slot is idle
     lk.unlock();
-    hipError_t e = hipEventSynchronize(s.ev1);
+    const hipError_t e = wait_iteration(s);
     const Clock::time_point now = Clock::now();
-    float a = 0, k = 0, b = 0;
-    if (e == hipSuccess) {
-      (void)hipEventElapsedTime(&a, sv->ref, s.ev0);
-      (void)hipEventElapsedTime(&k, sv->ref, s.evk);
-      (void)hipEventElapsedTime(&b, sv->ref, s.ev1);
-    }
     lk.lock();
-    if (e == hipSuccess) {
-      sv->busy_ivals.push_back({a, b});
-      sv->kernel_ivals.push_back({k, b});
+    if (e == hipSuccess && s.signals) {
+      auto ms = [&](int w) {
+        const uint64_t t = __atomic_load_n(s.h_sig + w, __ATOMIC_RELAXED);
+        return (double)(int64_t)(t - sv->clock_origin) / sv->clock_khz;
+      };
+      sv->busy_ivals.push_back({ms(1), ms(3)});
+      sv->kernel_ivals.push_back({ms(2), ms(3)});
     }
     for (uint64_t t : s.tickets) {
       auto f = sv->reqs.find(t);
@@ -476,7 +518,6 @@ static void destroy_server(slrng_server *sv) {
     if (s.st) (void)hipStreamSynchronize(s.st);
     free_slot(s);
   }
-  if (sv->ref) (void)hipEventDestroy(sv->ref);
   if (sv->arena_dev) {
     if (sv->o.arena_plain) (void)hipFree(sv->arena_dev);
     else (void)spread_free(sv->arena_dev);
@@ -545,9 +586,14 @@ extern "C" int slrng_server_create(const slrng_server_opts *opts, slrng_server *
       for (int i = 0; i < sv->nslots; i++) {
         Slot &s = sv->slots[i];
         e = hipStreamCreateWithFlags(&s.st, hipStreamNonBlocking);
-        if (e == hipSuccess) e = hipEventCreate(&s.ev0);
-        if (e == hipSuccess) e = hipEventCreate(&s.evk);
-        if (e == hipSuccess) e = hipEventCreate(&s.ev1);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&s.ev1, hipEventDisableTiming);
+        if (e == hipSuccess) e = hipHostMalloc((void **)&s.h_sig, 4 * sizeof(uint64_t), hipHostMallocCoherent);
+        void *mapped = nullptr;
+        if (e == hipSuccess) e = hipHostGetDevicePointer(&mapped, s.h_sig, 0);
+        if (e == hipSuccess) {
+          s.d_sig = static_cast<uint64_t *>(mapped);
+          for (int w = 0; w < 4; w++) s.h_sig[w] = 0;
+        }
         if (e != hipSuccess) {
           rc = hip_fail(e);
           break;
@@ -559,10 +605,18 @@ extern "C" int slrng_server_create(const slrng_server_opts *opts, slrng_server *
       }
     }
     if (!rc) {
-      e = hipEventCreate(&sv->ref);
-      if (e == hipSuccess) e = hipEventRecord(sv->ref, sv->slots[0].st);
-      if (e == hipSuccess) e = hipEventSynchronize(sv->ref);
+      // the interval origin: the device clock now, stamped by an empty upload
+      int khz = 0;
+      e = hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, sv->device);
+      Slot &s = sv->slots[0];
+      if (e == hipSuccess) e = launch_upload(nullptr, nullptr, 0, s.st, s.d_sig + 1);
+      if (e == hipSuccess) e = hipStreamSynchronize(s.st);
+      if (e == hipSuccess && khz <= 0) e = hipErrorInvalidValue;
       if (e != hipSuccess) rc = hip_fail(e);
+      else {
+        sv->clock_khz = khz;
+        sv->clock_origin = __atomic_load_n(s.h_sig + 1, __ATOMIC_ACQUIRE);
+      }
     }
     if (rc) {
       sv->worker_done = true;
