@@ -134,6 +134,20 @@ int slrng_state_words(int variant);
 int slrng_charpoly(int variant, uint64_t *out, int out_words);
 int slrng_jump_poly(int variant, const uint64_t *J_words, int nj, uint64_t *out, int out_words);
 
+/* slrng_jump_poly_device: the same polynomials for many distances at once,
+ * computed on the device.  dev_J (device memory, m x 2 words) holds the
+ * 128-bit distances J_j = dev_J[2j] + 2^64 dev_J[2j+1]; word w of
+ * x^(J_j) mod p(x) is written to dev_out[j n/64 + w] (device memory, m x n/64
+ * words).  Each result is the product in Z/2Z[x]/p of the entries
+ * x^(d 2^(10 l)) mod p selected by J_j's radix-1024 digits d (level l); those
+ * tables are themselves computed on the device from p(x) alone, by repeated
+ * squaring and multiplication, the first time an engine is used on a device
+ * (jump functions, Section "Combining linear engines and scramblers").
+ * Asynchronous on `stream`.  EINVAL for a bad variant or a null or unaligned
+ * pointer, ERANGE for m > 2^32; m = 0 does nothing. */
+int slrng_jump_poly_device(int variant, const uint64_t *dev_J, uint64_t m, uint64_t *dev_out,
+                           hipStream_t stream);
+
 /* ---------------------------------------------------------------- streams
  *
  * slrng_streams_create: S = n_streams streams on the current device.  The

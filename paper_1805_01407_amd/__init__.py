@@ -11,7 +11,7 @@ paper_1805_01407_amd.build``).
 from .binding import (  # noqa: F401
     VARIANTS, VARIANTS32, VARIANT_IDS, SlrngError, Streams, lib, library_path,
     slrng_version, slrng_strerror, slrng_last_hip_error, slrng_state_words,
-    slrng_charpoly, slrng_jump_poly,
+    slrng_charpoly, slrng_jump_poly, slrng_jump_poly_device,
     slrng_streams_create, slrng_streams_create_from_states, slrng_streams_count,
     slrng_streams_variant, slrng_streams_seed,
     slrng_streams_jump, slrng_streams_advance, slrng_streams_advance_each, slrng_generate, slrng_linear_complexity,

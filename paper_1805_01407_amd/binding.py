@@ -110,6 +110,7 @@ def lib():
         "slrng_state_words": ([i32], i32),
         "slrng_charpoly": ([i32, u64p, i32], i32),
         "slrng_jump_poly": ([i32, u64p, i32, u64p, i32], i32),
+        "slrng_jump_poly_device": ([i32, vp, u64, vp, vp], i32),
         "slrng_streams_create": ([i32, u64, u64, vp, ctypes.POINTER(vp)], i32),
         "slrng_streams_create_from_states": ([i32, u64p, u64, vp, ctypes.POINTER(vp)], i32),
         "slrng_streams_seed": ([vp, u64, vp], i32),
@@ -233,6 +234,33 @@ def slrng_jump_poly(variant, J: int) -> int:
     _check(lib().slrng_jump_poly(_variant(variant), _u64p(jw), nj, _u64p(out), out.size),
            "slrng_jump_poly")
     return _words_to_int(out)
+
+
+def slrng_jump_poly_device(variant, J, stream=None):
+    """x^J mod p(x) for each 128-bit distance in J (Python ints, or a CUDA
+    int64 tensor of shape (m, 2) holding (low, high) words), computed on the
+    device: a CUDA int64 tensor of shape (m, n/64), row j the words of
+    x^(J_j) mod p."""
+    import torch
+    if isinstance(J, torch.Tensor):
+        assert J.is_cuda and J.dtype == torch.int64 and J.dim() == 2 and J.shape[1] == 2
+        buf = J.contiguous()
+    else:
+        words = np.zeros((len(J), 2), dtype=np.uint64)
+        for i, x in enumerate(J):
+            x = int(x)
+            words[i, 0] = x & 0xFFFFFFFFFFFFFFFF
+            words[i, 1] = (x >> 64) & 0xFFFFFFFFFFFFFFFF
+        buf = torch.from_numpy(words.view(np.int64)).cuda()
+    m = buf.shape[0]
+    nw = (slrng_charpoly(variant).bit_length() - 1) // 64
+    out = torch.empty((m, nw), dtype=torch.int64, device=buf.device)
+    _check(lib().slrng_jump_poly_device(_variant(variant), buf.data_ptr(), m, out.data_ptr(),
+                                        _stream(stream)), "slrng_jump_poly_device")
+    if buf is not J:
+        # the staging tensor must outlive the queued kernel
+        torch.cuda.synchronize()
+    return out
 
 
 def slrng_streams_create(variant, seed: int, n_streams: int, stream=None) -> int:

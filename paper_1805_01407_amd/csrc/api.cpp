@@ -20,6 +20,7 @@
 #include "kernels.hpp"
 #include "kernels32.hpp"
 #include "lincomp.hpp"
+#include "xpow.hpp"
 
 using namespace slrng;
 
@@ -119,14 +120,10 @@ int levels_for(uint64_t S) {
   return l;
 }
 
-// Entry d = x^(d * 2^e) mod p for d < 1024.
-static void power_table(const Field &f, int e, std::vector<Poly> &out) {
-  out.resize(kTabRadix);
-  Poly g;
-  f.xpow2(e, g);
-  out[0].clear();
-  out[0].w[0] = 1;
-  for (int d = 1; d < kTabRadix; d++) f.mulmod(out[d - 1], g, out[d]);
+// Tables x^(d 2^(e0 + 10 l)) mod p of one engine, built on the device from
+// p alone (xpow.hip).
+static hipError_t engine_table(const Field &f, int e0, int levels, uint64_t *out, XpowLayout lay) {
+  return xpow_table_device(f.n / 64, f.p.w, e0, 10, levels, out, lay, nullptr);
 }
 
 int get_pos_tables(int device, int engine, int levels, PosTables **out) {
@@ -138,27 +135,21 @@ int get_pos_tables(int device, int engine, int levels, PosTables **out) {
   }
   const Field &f = engine_field(engine);
   const int W = f.n / 64;
-  std::vector<Poly> ent;
-  // level 0: jump distance J = 2^(n/2); level l: 1024^l J = 2^(10 l + n/2)
-  power_table(f, f.n / 2, ent);
-  std::vector<uint64_t> h0((size_t)W * kTabRadix);
-  for (int d = 0; d < kTabRadix; d++)
-    for (int w = 0; w < W; w++) h0[(size_t)w * kTabRadix + d] = ent[d].w[w];
-  std::vector<uint64_t> hu((size_t)(levels > 1 ? levels - 1 : 1) * kTabRadix * 16, 0);
-  for (int l = 1; l < levels; l++) {
-    power_table(f, 10 * l + f.n / 2, ent);
-    for (int d = 0; d < kTabRadix; d++)
-      for (int w = 0; w < 16; w++) hu[((size_t)(l - 1) * kTabRadix + d) * 16 + w] = ent[d].w[w];
-  }
+  // level 0: jump distance J = 2^(n/2), entry d at [w 1024 + d]; level l >= 1:
+  // 1024^l J = 2^(10 l + n/2), entry d at [((l-1) 1024 + d) 16 + w]
+  const size_t nu = (size_t)(levels > 1 ? levels - 1 : 1) * kTabRadix * 16;
   uint64_t *d0 = nullptr, *du = nullptr;
-  HIPCHK(hipMalloc(&d0, h0.size() * 8));
-  hipError_t e = hipMalloc(&du, hu.size() * 8);
+  HIPCHK(hipMalloc(&d0, (size_t)W * kTabRadix * 8));
+  hipError_t e = hipMalloc(&du, nu * 8);
+  if (e == hipSuccess) e = hipMemset(du, 0, nu * 8);
+  if (e == hipSuccess) e = engine_table(f, f.n / 2, 1, d0, XpowLayout{0, 1, (size_t)kTabRadix});
+  if (e == hipSuccess && levels > 1)
+    e = engine_table(f, f.n / 2 + 10, levels - 1, du, XpowLayout{(size_t)kTabRadix * 16, 16, 1});
   if (e != hipSuccess) {
     (void)hipFree(d0);
+    if (du) (void)hipFree(du);
     return hip_fail(e);
   }
-  HIPCHK(hipMemcpy(d0, h0.data(), h0.size() * 8, hipMemcpyHostToDevice));
-  HIPCHK(hipMemcpy(du, hu.data(), hu.size() * 8, hipMemcpyHostToDevice));
   // tables of fewer levels may still be in use by queued kernels: keep them
   t.tab0 = d0;
   t.up = du;
@@ -181,16 +172,9 @@ int get_digit_tables(int device, int engine, const uint64_t **out) {
   }
   const Field &f = engine_field(engine);
   const int W = f.n / 64;
-  std::vector<uint64_t> h((size_t)kDigitLevels * W * kTabRadix);
-  std::vector<Poly> ent;
-  for (int l = 0; l < kDigitLevels; l++) {
-    power_table(f, 10 * l, ent);
-    for (int d = 0; d < kTabRadix; d++)
-      for (int w = 0; w < W; w++) h[((size_t)l * W + w) * kTabRadix + d] = ent[d].w[w];
-  }
   uint64_t *dev = nullptr;
-  HIPCHK(hipMalloc(&dev, h.size() * 8));
-  hipError_t e = hipMemcpy(dev, h.data(), h.size() * 8, hipMemcpyHostToDevice);
+  HIPCHK(hipMalloc(&dev, (size_t)kDigitLevels * W * kTabRadix * 8));
+  const hipError_t e = engine_table(f, 0, kDigitLevels, dev, XpowLayout{(size_t)W * kTabRadix, 1, (size_t)kTabRadix});
   if (e != hipSuccess) {
     (void)hipFree(dev);
     return hip_fail(e);
@@ -319,6 +303,25 @@ extern "C" int slrng_jump_poly(int variant, const uint64_t *J, int nj, uint64_t 
       f.xpow(J, nj, r);
     }
     for (int i = 0; i < f.n / 64; i++) out[i] = r.w[i];
+    return SLRNG_OK;
+  });
+}
+
+extern "C" int slrng_jump_poly_device(int variant, const uint64_t *dev_J, uint64_t m, uint64_t *dev_out,
+                                      hipStream_t stream) {
+  return guarded([&]() -> int {
+    if (!valid_variant(variant)) return SLRNG_EINVAL;
+    if (m == 0) return SLRNG_OK;
+    if (!dev_J || !dev_out || ((uintptr_t)dev_J & 7) || ((uintptr_t)dev_out & 7)) return SLRNG_EINVAL;
+    if (m > (1ull << 32)) return SLRNG_ERANGE;
+    int device = 0;
+    HIPCHK(hipGetDevice(&device));
+    const int engine = variant_engine(variant);
+    const uint64_t *tab = nullptr;
+    const int rc = get_digit_tables(device, engine, &tab);
+    if (rc) return rc;
+    const Field &f = engine_field(engine);
+    HIPCHK(launch_xpow_batch(f.n / 64, f.p.w, tab, dev_J, m, dev_out, stream));
     return SLRNG_OK;
   });
 }

@@ -25,6 +25,7 @@
 #include "engines.hpp"
 #include "f2poly.hpp"
 #include "kernels.hpp"
+#include "xpow.hpp"
 
 using namespace slrng;
 
@@ -121,26 +122,15 @@ int digit_matrices(int device, int variant, DigitMatrices *out) {
   const int bits = K <= 4 ? 8 : 4;
   const int levels = 128 / bits;
   const unsigned per = 1u << bits, entries = (unsigned)levels * per;
-  // entry l 2^bits + d: x^(d 2^(bits l)) mod p, as powers of x^(2^(bits l))
-  std::vector<uint64_t> h((size_t)entries * 16, 0);
-  for (int l = 0; l < levels; l++) {
-    uint64_t J[2] = {0, 0};
-    J[(bits * l) >> 6] = 1ull << ((bits * l) & 63);
-    Poly base, cur;
-    f.xpow(J, 2, base);
-    cur.clear();
-    cur.w[0] = 1;
-    for (unsigned d = 0; d < per; d++) {
-      for (int w = 0; w < K; w++) h[((size_t)l * per + d) * 16 + w] = cur.w[w];
-      Poly nx;
-      f.mulmod(cur, base, nx);
-      cur = nx;
-    }
-  }
+  // entry l 2^bits + d: x^(d 2^(bits l)) mod p (16 words, the first K used),
+  // built on the device from p alone
+  const size_t pwords = (size_t)entries * 16;
   uint64_t *polys = nullptr, *cols = nullptr;
-  HIPCHK(hipMalloc(&polys, h.size() * 8));
+  HIPCHK(hipMalloc(&polys, pwords * 8));
   hipError_t e = hipMalloc(&cols, (size_t)entries * f.n * K * 8);
-  if (e == hipSuccess) e = hipMemcpy(polys, h.data(), h.size() * 8, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemset(polys, 0, pwords * 8);
+  if (e == hipSuccess)
+    e = xpow_table_device(K, f.p.w, 0, bits, levels, polys, XpowLayout{(size_t)per * 16, 16, 1}, nullptr);
   if (e == hipSuccess) e = launch_digit_cols(variant, polys, entries, cols, nullptr);
   if (e == hipSuccess) e = hipStreamSynchronize(nullptr);
   (void)hipFree(polys);
