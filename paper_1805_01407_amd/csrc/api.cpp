@@ -188,6 +188,11 @@ int get_digit_tables(int device, int engine, const uint64_t **out) {
 // skew class d < D and slot j < kMaxSlots (entry (d kMaxSlots + j), 16 words;
 // entries with j C < delta_d are unused).
 int get_slot_polys(int device, int engine, uint64_t C, uint64_t D, const uint64_t **out) {
+  // the products of the digit tables' entries, on the device (taken before
+  // the lock: get_digit_tables takes it too)
+  const uint64_t *digits = nullptr;
+  const int rc = get_digit_tables(device, engine, &digits);
+  if (rc) return rc;
   std::lock_guard<std::mutex> g(g_tab_mu);
   auto key = std::make_tuple(device, engine, C, D);
   auto it = g_slot.find(key);
@@ -196,20 +201,21 @@ int get_slot_polys(int device, int engine, uint64_t C, uint64_t D, const uint64_
     return SLRNG_OK;
   }
   const Field &f = engine_field(engine);
-  std::vector<uint64_t> h((size_t)D * kMaxSlots * 16, 0);
-  for (uint64_t d = 0; d < D; d++) {
-    const uint64_t delta = d * (C / D);
-    for (int j = 1; j < kMaxSlots; j++) {
-      const uint64_t pos = (uint64_t)j * C - delta;
-      Poly r;
-      uint64_t J[1] = {pos};
-      f.xpow(J, 1, r);
-      for (int w = 0; w < 16; w++) h[((size_t)d * kMaxSlots + j) * 16 + w] = r.w[w];
-    }
-  }
+  const size_t words = (size_t)D * kMaxSlots * 16;
   uint64_t *dev = nullptr;
-  HIPCHK(hipMalloc(&dev, h.size() * 8));
-  HIPCHK(hipMemcpy(dev, h.data(), h.size() * 8, hipMemcpyHostToDevice));
+  HIPCHK(hipMalloc(&dev, words * 8));
+  hipError_t e = hipMemset(dev, 0, words * 8);
+  // class d: entries j = 1 .. kMaxSlots-1 at x^(j C - delta_d), delta_d < C
+  for (uint64_t d = 0; d < D && e == hipSuccess; d++) {
+    const uint64_t delta = d * (C / D);
+    e = launch_xpow_seq(f.n / 64, f.p.w, digits, C - delta, 0, C, kMaxSlots - 1,
+                        dev + ((size_t)d * kMaxSlots + 1) * 16, 16, 1, nullptr);
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(nullptr);
+  if (e != hipSuccess) {
+    (void)hipFree(dev);
+    return hip_fail(e);
+  }
   g_slot[key] = dev;
   *out = dev;
   return SLRNG_OK;

@@ -19,6 +19,7 @@ int variant_engine(int v);
 const Poly &jump_kind_poly(int engine, int jump_kind);
 int levels_for(uint64_t S);
 int get_slot_polys(int device, int engine, uint64_t C, uint64_t D, const uint64_t **out);
+int get_digit_tables(int device, int engine, const uint64_t **out);
 slrng_tuning tuning_for(int v, int kind);
 const uint64_t *streams_state_ptr(const slrng_streams *h);
 int check_batch_opts(const slrng_batch_opts &o);

@@ -56,23 +56,20 @@ int chunk_table(int device, int engine, uint64_t C, uint32_t need, ChunkTable *o
   }
   uint32_t n = std::max<uint32_t>(need, 64);
   n = std::min<uint32_t>(std::max<uint32_t>(n, t.n * 2), kMaxTable);
+  // entries x^(j C) mod p on the device: products of the digit tables' entries
+  const uint64_t *digits = nullptr;
+  const int rc = get_digit_tables(device, engine, &digits);
+  if (rc) return rc;
   const Field &f = engine_field(engine);
   const int W = f.n / 64;
-  Poly step, cur;
-  uint64_t J[1] = {C};
-  f.xpow(J, 1, step);
-  cur.clear();
-  cur.w[0] = 1;
-  std::vector<uint64_t> h((size_t)W * n);
-  for (uint32_t j = 0; j < n; j++) {
-    for (int w = 0; w < W; w++) h[(size_t)w * n + j] = cur.w[w];
-    Poly nx;
-    f.mulmod(cur, step, nx);
-    cur = nx;
-  }
   uint64_t *d = nullptr;
-  HIPCHK(hipMalloc(&d, h.size() * 8));
-  HIPCHK(hipMemcpy(d, h.data(), h.size() * 8, hipMemcpyHostToDevice));
+  HIPCHK(hipMalloc(&d, (size_t)W * n * 8));
+  hipError_t e = launch_xpow_seq(W, f.p.w, digits, 0, 0, C, n, d, 1, n, nullptr);
+  if (e == hipSuccess) e = hipStreamSynchronize(nullptr);
+  if (e != hipSuccess) {
+    (void)hipFree(d);
+    return hip_fail(e);
+  }
   // a smaller table may still be in use by queued work: it is kept
   t.dev = d;
   t.n = n;

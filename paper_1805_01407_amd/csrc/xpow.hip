@@ -159,13 +159,24 @@ __global__ __launch_bounds__(256) void k_xpow_digits(PLow<K> p, const uint64_t *
 }
 
 // x^J mod p for m distances: the product of the radix-1024 digit entries.
+// J_j from the array J, or, when J is null, J_j = j0 + j step (mod 2^128);
+// word w of result j at out[j es + w ws].
 template <int K>
 __global__ __launch_bounds__(256) void k_xpow_batch(PLow<K> p, const uint64_t *__restrict__ digits,
-                                                    const uint64_t *__restrict__ J, uint64_t m,
-                                                    uint64_t *out) {
+                                                    const uint64_t *__restrict__ J, uint64_t j0_lo,
+                                                    uint64_t j0_hi, uint64_t step, uint64_t m,
+                                                    uint64_t *out, uint64_t es, uint64_t ws) {
   const uint64_t j = (uint64_t)blockIdx.x * 256 + threadIdx.x;
   if (j >= m) return;
-  const uint64_t lo = J[2 * j], hi = J[2 * j + 1];
+  uint64_t lo, hi;
+  if (J) {
+    lo = J[2 * j];
+    hi = J[2 * j + 1];
+  } else {
+    const uint64_t plo = j * step, phi = __umul64hi(j, step);
+    lo = j0_lo + plo;
+    hi = j0_hi + phi + (lo < plo ? 1 : 0);
+  }
   uint64_t acc[K];
 #pragma unroll
   for (int v = 0; v < K; v++) acc[v] = v == 0 ? 1 : 0;
@@ -193,7 +204,7 @@ __global__ __launch_bounds__(256) void k_xpow_batch(PLow<K> p, const uint64_t *_
     }
   }
 #pragma unroll
-  for (int v = 0; v < K; v++) out[j * K + v] = acc[v];
+  for (int v = 0; v < K; v++) out[j * es + v * ws] = acc[v];
 }
 
 template <int K>
@@ -226,14 +237,31 @@ hipError_t table_k(const uint64_t *p_low, int e0, int bits, int levels, uint64_t
 }
 
 template <int K>
-hipError_t batch_k(const uint64_t *p_low, const uint64_t *digits, const uint64_t *J, uint64_t m,
-                   uint64_t *out, hipStream_t st) {
+hipError_t batch_k(const uint64_t *p_low, const uint64_t *digits, const uint64_t *J, uint64_t j0_lo,
+                   uint64_t j0_hi, uint64_t step, uint64_t m, uint64_t *out, uint64_t es,
+                   uint64_t ws, hipStream_t st) {
   PLow<K> p;
   for (int v = 0; v < K; v++) p.w[v] = p_low[v];
   const uint64_t grid = (m + 255) / 256;
   if (grid > 0x7fffffffull) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_xpow_batch<K>, dim3((unsigned)grid), dim3(256), 0, st, p, digits, J, m, out);
+  hipLaunchKernelGGL(k_xpow_batch<K>, dim3((unsigned)grid), dim3(256), 0, st, p, digits, J, j0_lo, j0_hi,
+                     step, m, out, es, ws);
   return hipGetLastError();
+}
+
+hipError_t batch_any(int K, const uint64_t *p_low, const uint64_t *digits, const uint64_t *J,
+                     uint64_t j0_lo, uint64_t j0_hi, uint64_t step, uint64_t m, uint64_t *out,
+                     uint64_t es, uint64_t ws, hipStream_t st) {
+  if (m == 0) return hipSuccess;
+  if (!p_low || !digits || !out) return hipErrorInvalidValue;
+  switch (K) {
+    case 1: return batch_k<1>(p_low, digits, J, j0_lo, j0_hi, step, m, out, es, ws, st);
+    case 2: return batch_k<2>(p_low, digits, J, j0_lo, j0_hi, step, m, out, es, ws, st);
+    case 4: return batch_k<4>(p_low, digits, J, j0_lo, j0_hi, step, m, out, es, ws, st);
+    case 8: return batch_k<8>(p_low, digits, J, j0_lo, j0_hi, step, m, out, es, ws, st);
+    case 16: return batch_k<16>(p_low, digits, J, j0_lo, j0_hi, step, m, out, es, ws, st);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 }  // namespace
@@ -253,16 +281,14 @@ hipError_t xpow_table_device(int K, const uint64_t *p_low, int e0, int bits, int
 
 hipError_t launch_xpow_batch(int K, const uint64_t *p_low, const uint64_t *digits, const uint64_t *J,
                              uint64_t m, uint64_t *out, hipStream_t st) {
-  if (m == 0) return hipSuccess;
-  if (!p_low || !digits || !J || !out) return hipErrorInvalidValue;
-  switch (K) {
-    case 1: return batch_k<1>(p_low, digits, J, m, out, st);
-    case 2: return batch_k<2>(p_low, digits, J, m, out, st);
-    case 4: return batch_k<4>(p_low, digits, J, m, out, st);
-    case 8: return batch_k<8>(p_low, digits, J, m, out, st);
-    case 16: return batch_k<16>(p_low, digits, J, m, out, st);
-    default: return hipErrorInvalidValue;
-  }
+  if (m && !J) return hipErrorInvalidValue;
+  return batch_any(K, p_low, digits, J, 0, 0, 0, m, out, (uint64_t)K, 1, st);
+}
+
+hipError_t launch_xpow_seq(int K, const uint64_t *p_low, const uint64_t *digits, uint64_t j0_lo,
+                           uint64_t j0_hi, uint64_t step, uint64_t m, uint64_t *out, uint64_t es,
+                           uint64_t ws, hipStream_t st) {
+  return batch_any(K, p_low, digits, nullptr, j0_lo, j0_hi, step, m, out, es, ws, st);
 }
 
 }  // namespace slrng

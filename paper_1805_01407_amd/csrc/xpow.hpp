@@ -31,4 +31,10 @@ hipError_t xpow_table_device(int K, const uint64_t *p_low, int e0, int bits, int
 hipError_t launch_xpow_batch(int K, const uint64_t *p_low, const uint64_t *digits,
                              const uint64_t *J, uint64_t m, uint64_t *out, hipStream_t st);
 
+// The same for the arithmetic sequence J_j = j0 + j step (mod 2^128, j0 =
+// j0_lo + 2^64 j0_hi), word w of result j at out[j es + w ws].
+hipError_t launch_xpow_seq(int K, const uint64_t *p_low, const uint64_t *digits, uint64_t j0_lo,
+                           uint64_t j0_hi, uint64_t step, uint64_t m, uint64_t *out, uint64_t es,
+                           uint64_t ws, hipStream_t st);
+
 }  // namespace slrng
