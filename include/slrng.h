@@ -319,9 +319,13 @@ int slrng_set_tuning(int variant, int kind, const slrng_tuning *t);
  * output memory).  Every request's values are the same in any batch, alone or
  * in any mix, in every mode.
  *
- * slrng_batch_plan: plans a batch once (host descriptors, jump polynomials,
- * device descriptor upload; with SLRNG_BATCH_GRAPH also captures and
- * instantiates a hipGraph).  The request array is not kept.
+ * slrng_batch_plan: plans a batch once (host descriptors, device descriptor
+ * upload; with SLRNG_BATCH_GRAPH also captures and instantiates a hipGraph).
+ * The request array is not kept.  Start states of requests with start > 0
+ * are computed on the device from the digits of start (the engine's digit
+ * matrices M^(d 2^(b l)), built on the device the first time the engine is
+ * used in a batch or a server: 32 MiB for xoshiro256, 64 MiB for
+ * xoroshiro1024); no polynomial is computed per request.
  * slrng_batch_launch: enqueues the planned work on `stream` (asynchronous;
  * replays the graph in SLRNG_BATCH_GRAPH mode).  Launches of one batch must
  * not overlap in time (they share a claim counter).

@@ -389,7 +389,7 @@ int build_plan(const PlanReq *reqs, size_t n_reqs, const slrng_batch_opts &o, in
       rs.seeds.push_back(reqs[r].seed);
       rs.origin_idx.push_back(reqs[r].origin_idx);
       rs.slot.push_back(req_slot[r]);
-      if (reqs[r].from_state) {
+      if (reqs[r].from_state || !host_tables) {
         // positioned on the device from the digits of its 128-bit start
         rs.pos.push_back(reqs[r].start);
         rs.pos.push_back(reqs[r].start_hi);
@@ -423,10 +423,15 @@ struct slrng_batch {
   LaneDesc *d_lanes = nullptr;
   RunDesc *d_runs = nullptr;
   uint64_t *d_req_state = nullptr;
-  uint64_t *d_req_seed = nullptr, *d_req_poly = nullptr;
+  uint64_t *d_req_seed = nullptr, *d_req_pos = nullptr;
   uint32_t *d_req_slot = nullptr;
   unsigned *d_counter = nullptr;  // two counters per unit (claims, finished waves)
-  std::vector<std::pair<int, ReqArgs>> req_launches;
+  struct ReqLaunch {
+    int variant;
+    ReqArgs args;
+    DigitMatrices digits;
+  };
+  std::vector<ReqLaunch> req_launches;
   BatchArgs args;
   unsigned blocks = 0;
   hipGraph_t graph = nullptr;
@@ -437,7 +442,7 @@ static void free_batch(slrng_batch *b) {
   if (!b) return;
   if (b->exec) (void)hipGraphExecDestroy(b->exec);
   if (b->graph) (void)hipGraphDestroy(b->graph);
-  void *ptrs[] = {b->d_tiles, b->d_lanes, b->d_runs, b->d_req_state, b->d_req_seed, b->d_req_poly,
+  void *ptrs[] = {b->d_tiles, b->d_lanes, b->d_runs, b->d_req_state, b->d_req_seed, b->d_req_pos,
                   b->d_req_slot, b->d_counter};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
@@ -484,7 +489,8 @@ static int enqueue_unit(slrng_batch *b, const PlanUnit &u, unsigned *counter, hi
 
 static int enqueue_req_states(slrng_batch *b, hipStream_t st) {
   for (auto &rl : b->req_launches) {
-    hipError_t e = launch_req_state(rl.first, rl.second, st);
+    hipError_t e = launch_req_state_digits(rl.variant, rl.args, rl.digits.dev, rl.digits.bits,
+                                           rl.digits.levels, st);
     if (e != hipSuccess) return hip_fail(e);
   }
   return SLRNG_OK;
@@ -552,21 +558,27 @@ extern "C" int slrng_batch_plan(const slrng_request *reqs, size_t n_reqs,
       e = hipMalloc(&b->d_req_state, (size_t)P.rs.nslots * 16 * 8);
       if (e != hipSuccess) rc = hip_fail(e);
       if (!rc) rc = upload((void **)&b->d_req_seed, P.rs.seeds.data(), P.rs.seeds.size() * 8);
-      if (!rc) rc = upload((void **)&b->d_req_poly, P.rs.polys.data(), P.rs.polys.size() * 8);
+      if (!rc) rc = upload((void **)&b->d_req_pos, P.rs.pos.data(), P.rs.pos.size() * 8);
       if (!rc) rc = upload((void **)&b->d_req_slot, P.rs.slot.data(), P.rs.slot.size() * 4);
+      // start states s M^start from the digits of start, on the device (the
+      // engine's digit matrices, built once per device)
       uint32_t off = 0;
       for (size_t k = 0; k < P.rs.runs.size() && !rc; k++) {
-        ReqArgs ra;
+        slrng_batch::ReqLaunch rl;
+        rl.variant = P.rs.runs[k].first;
+        rc = digit_matrices(b->device, rl.variant, &rl.digits);
+        if (rc) break;
+        ReqArgs &ra = rl.args;
         ra.seeds = b->d_req_seed + off;
         ra.origin_state = nullptr;
         ra.origin_stride = 0;
         ra.origin_idx = nullptr;
-        ra.polys = b->d_req_poly + (size_t)off * 16;
-        ra.pos = nullptr;
+        ra.polys = nullptr;
+        ra.pos = b->d_req_pos + (size_t)off * 2;
         ra.slot = b->d_req_slot + off;
         ra.req_state = b->d_req_state;
         ra.m = P.rs.runs[k].second;
-        b->req_launches.push_back({P.rs.runs[k].first, ra});
+        b->req_launches.push_back(rl);
         off += ra.m;
       }
     }
