@@ -233,8 +233,10 @@ SL_HD void step(u64 (&s)[Params<V>::k]) {
     const u64 n3 = s[3] ^ s[4];
     const u64 n4 = xor3_sel<SCALAR>(s[4], s[5], s[1]);
     const u64 n5 = s[5] ^ s[1];
-    const u64 n6 = xor3_sel<SCALAR>(s[6], s[7], s[3] ^ t);
-    const u64 n7 = rot_sel<Q::b, SCALAR>(s[7] ^ s[3]);
+    // s7 ^ s3 feeds both the new s6 and the rotation (one xor, not two)
+    const u64 m7 = s[7] ^ s[3];
+    const u64 n6 = xor3_sel<SCALAR>(s[6], m7, t);
+    const u64 n7 = rot_sel<Q::b, SCALAR>(m7);
     s[0] = n0;
     s[1] = n1;
     s[2] = n2;
