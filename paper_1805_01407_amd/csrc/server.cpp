@@ -440,12 +440,19 @@ static void completer_main(slrng_server *sv, int si) {
     const Clock::time_point now = Clock::now();
     lk.lock();
     if (e == hipSuccess && s.signals) {
-      auto ms = [&](int w) {
-        const uint64_t t = __atomic_load_n(s.h_sig + w, __ATOMIC_RELAXED);
-        return (double)(int64_t)(t - sv->clock_origin) / sv->clock_khz;
-      };
-      sv->busy_ivals.push_back({ms(1), ms(3)});
-      sv->kernel_ivals.push_back({ms(2), ms(3)});
+      uint64_t t[4];
+      for (int w = 1; w < 4; w++) t[w] = __atomic_load_n(s.h_sig + w, __ATOMIC_RELAXED);
+      auto ms = [&](uint64_t c) { return (double)(int64_t)(c - sv->clock_origin) / sv->clock_khz; };
+      // the end stamp precedes the signal in the last wave; a start stamp
+      // that reads 0 or out of order (not expected) is replaced by the other
+      // one, the kernel interval then widening to the whole iteration
+      const bool ok1 = t[1] && t[1] <= t[3], ok2 = t[2] && t[2] <= t[3];
+      if (ok1 || ok2) {
+        const uint64_t k0 = ok2 ? t[2] : t[1];
+        const uint64_t b0 = ok1 ? std::min(t[1], k0) : k0;
+        sv->busy_ivals.push_back({ms(b0), ms(t[3])});
+        sv->kernel_ivals.push_back({ms(k0), ms(t[3])});
+      }
     }
     for (uint64_t t : s.tickets) {
       auto f = sv->reqs.find(t);
