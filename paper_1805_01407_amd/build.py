@@ -12,7 +12,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libslrng.so")
-HIP_SOURCES = ["kernels.hip", "kernels32.hip", "batch.hip", "lincomp.hip", "batch_static.hip", "upload.hip", "xpow.hip"]  # device code: hipcc for gfx950
+HIP_SOURCES = ["kernels.hip", "kernels32.hip", "batch.hip", "lincomp.hip", "batch_static.hip", "xpow.hip"]  # device code: hipcc for gfx950
 HOST_SOURCES = ["api.cpp", "f2poly.cpp", "batch.cpp", "server.cpp", "memory.cpp"]  # host C++ against the HIP runtime API
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

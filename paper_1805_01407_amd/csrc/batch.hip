@@ -309,14 +309,15 @@ __global__ __launch_bounds__(kBlock) void k_digit_cols(const u64 *__restrict__ p
 // the state, so the next nonzero digit's are loaded while the current one is
 // applied (two-, four-word engines).
 template <int V>
-__global__ __launch_bounds__(kBlock) void k_req_state_digits(ReqArgs a, const u64 *__restrict__ cols,
-                                                             int bits, int levels) {
+__device__ __forceinline__ void req_state_digits_wave(const ReqArgs &a, const u64 *__restrict__ cols,
+                                                      int bits, int levels, unsigned r, int lane) {
   constexpr int K = Params<V>::k;
   constexpr int N = 64 * K;
   constexpr bool kAhead = K <= 4;
-  const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
-  const unsigned r = blockIdx.x * (kBlock / kWave) + wave;
-  if (r >= a.m) return;  // uniform per wave
+  // every input of the request read up front (they may be in host memory:
+  // one round trip instead of one per use)
+  const u64 pos[2] = {a.pos[2 * (u64)r], a.pos[2 * (u64)r + 1]};
+  const u64 slot = a.slot[r];
   u64 s[K];
   if (a.origin_state) {
     const u64 j = a.origin_idx[r];
@@ -325,7 +326,6 @@ __global__ __launch_bounds__(kBlock) void k_req_state_digits(ReqArgs a, const u6
   } else {
     splitmix64_fill<K>(a.seeds[r], s);
   }
-  const u64 pos[2] = {a.pos[2 * (u64)r], a.pos[2 * (u64)r + 1]};
   const u64 dmask = ((u64)1 << bits) - 1;
   auto digit = [&](int l) -> unsigned {
     const int b0 = l * bits;  // bits divides 64: a digit never straddles the two words
@@ -384,8 +384,42 @@ __global__ __launch_bounds__(kBlock) void k_req_state_digits(ReqArgs a, const u6
   }
   if (lane == 0) {
 #pragma unroll
-    for (int w = 0; w < K; w++) a.req_state[(u64)a.slot[r] * 16 + w] = s[w];
+    for (int w = 0; w < K; w++) a.req_state[slot * 16 + w] = s[w];
   }
+}
+
+template <int V>
+__global__ __launch_bounds__(kBlock) void k_req_state_digits(ReqArgs a, const u64 *__restrict__ cols,
+                                                             int bits, int levels) {
+  const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+  const unsigned r = blockIdx.x * (kBlock / kWave) + wave;
+  if (r >= a.m) return;  // uniform per wave
+  req_state_digits_wave<V>(a, cols, bits, levels, r, lane);
+}
+
+// A served iteration's prologue in one launch: blocks [0, up_blocks) copy
+// the descriptor pack (n16 16-byte words) from pinned host memory, through
+// its device mapping, to device memory, block 0 first stamping the device
+// clock; the other blocks compute the request start states as
+// k_req_state_digits does, one wave per request, reading positions, origins
+// and slots from the same pinned memory, so the two parts do not wait for
+// each other and the generation kernel follows one launch instead of two.
+template <int V>
+__global__ __launch_bounds__(kBlock) void k_prologue(ReqArgs a, const u64 *__restrict__ cols, int bits,
+                                                     int levels, const uint4 *__restrict__ src,
+                                                     uint4 *__restrict__ dst, u64 n16,
+                                                     unsigned up_blocks, u64 *stamp) {
+  if (blockIdx.x < up_blocks) {
+    if (stamp && blockIdx.x == 0 && threadIdx.x == 0)
+      __hip_atomic_store(stamp, (u64)wall_clock64(), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    const u64 stride = (u64)up_blocks * kBlock;
+    for (u64 i = (u64)blockIdx.x * kBlock + threadIdx.x; i < n16; i += stride) dst[i] = src[i];
+    return;
+  }
+  const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+  const unsigned r = (blockIdx.x - up_blocks) * (kBlock / kWave) + wave;
+  if (r >= a.m) return;  // uniform per wave
+  req_state_digits_wave<V>(a, cols, bits, levels, r, lane);
 }
 
 template <int V, int ST>
@@ -477,6 +511,28 @@ hipError_t launch_digit_cols(int variant, const uint64_t *polys, unsigned entrie
 #define SL_DR(V) digit_cols_v<V>(polys, entries, cols, st)
   SL_DISPATCH64(variant, SL_DR)
 #undef SL_DR
+}
+
+template <int V>
+static hipError_t prologue_v(const ReqArgs &a, const u64 *cols, int bits, int levels, const uint4 *src,
+                             uint4 *dst, u64 n16, u64 *stamp, hipStream_t st) {
+  const u64 ub = (n16 + kBlock - 1) / kBlock;
+  const unsigned up_blocks = (unsigned)(ub == 0 ? 1 : ub < 1024 ? ub : 1024);
+  const unsigned req_blocks = (a.m + (kBlock / kWave) - 1) / (kBlock / kWave);
+  hipLaunchKernelGGL((k_prologue<V>), dim3(up_blocks + req_blocks), dim3(kBlock), 0, st, a, cols, bits,
+                     levels, src, dst, n16, up_blocks, stamp);
+  return hipGetLastError();
+}
+
+hipError_t launch_prologue(int variant, const ReqArgs &a, const uint64_t *cols, int bits, int levels,
+                           void *dst, const void *src, size_t bytes, uint64_t *stamp, hipStream_t st) {
+  if ((bytes & 15) || ((uintptr_t)dst & 15) || ((uintptr_t)src & 15)) return hipErrorInvalidValue;
+  const uint4 *s16 = static_cast<const uint4 *>(src);
+  uint4 *d16 = static_cast<uint4 *>(dst);
+  const u64 n16 = bytes / 16;
+#define SL_PR(V) prologue_v<V>(a, cols, bits, levels, s16, d16, n16, stamp, st)
+  SL_DISPATCH64(variant, SL_PR)
+#undef SL_PR
 }
 
 hipError_t launch_req_state_digits(int variant, const ReqArgs &a, const uint64_t *cols, int bits,

@@ -111,4 +111,12 @@ hipError_t launch_digit_cols(int variant, const uint64_t *polys, unsigned entrie
 // M^(d 2^(bits l))), one wave per request; origins from origin_state or seeds.
 hipError_t launch_req_state_digits(int variant, const ReqArgs &a, const uint64_t *cols, int bits,
                                    int levels, hipStream_t st);
+// The two in one launch for a served iteration: `bytes` (a multiple of 16)
+// copied from `src`, the device mapping of coherent pinned host memory, to
+// device memory `dst` (16-byte aligned), the device clock stamped to `stamp`
+// (host-mapped, or null) when the copy starts, and the request states of
+// `a` computed as above, its pos, origin_idx and slot read from that pinned
+// memory (a.m may be 0).
+hipError_t launch_prologue(int variant, const ReqArgs &a, const uint64_t *cols, int bits, int levels,
+                           void *dst, const void *src, size_t bytes, uint64_t *stamp, hipStream_t st);
 }  // namespace slrng

@@ -42,7 +42,6 @@
 #include "batch_plan.hpp"
 #include "kernels.hpp"
 #include "memory.hpp"
-#include "upload.hpp"
 
 using namespace slrng;
 
@@ -115,7 +114,8 @@ struct Req {
 // One in-flight slot: a HIP stream, an end event, a completion signal and
 // reusable buffers.  Everything an iteration reads (the tile claim counter,
 // already zero, then the tile, lane and run descriptors and the request-state
-// inputs) is packed into one pinned buffer and uploaded by one kernel.
+// inputs) is packed into one pinned buffer, which the iteration's first
+// kernel copies to device memory while it computes the request states.
 //
 // The signal is four words of coherent pinned memory that the iteration's
 // kernels write: [1] the device clock when the upload starts, [2] when the
@@ -138,7 +138,7 @@ struct Slot {
   std::thread completer;
   size_t cap_pack = 0, cap_req = 0;
   uint8_t *d_pack = nullptr, *h_pack = nullptr;
-  const uint8_t *h_pack_dev = nullptr;  // h_pack's device mapping, read by the upload kernel
+  const uint8_t *h_pack_dev = nullptr;  // h_pack's device mapping, read by the prologue kernel
   uint64_t *d_req_state = nullptr;
 };
 
@@ -213,7 +213,7 @@ static int slot_reserve(Slot &s, size_t bytes, size_t nreq) {
     s.h_pack_dev = nullptr;
     s.cap_pack = 0;
     hipError_t e = hipMalloc((void **)&s.d_pack, n);
-    // coherent: the upload kernel reads what the host wrote just before its
+    // coherent: the prologue kernel reads what the host wrote just before its
     // launch, never a copy cached from the slot's previous iteration
     if (e == hipSuccess) e = hipHostMalloc((void **)&s.h_pack, n, hipHostMallocCoherent);
     void *mapped = nullptr;
@@ -268,36 +268,36 @@ static int launch_iteration(slrng_server *sv, int si, const std::vector<PlanReq>
   const TileDesc *d_tiles = reinterpret_cast<const TileDesc *>(d + L.tiles);
   const LaneDesc *d_lanes = reinterpret_cast<const LaneDesc *>(d + L.lanes);
   const RunDesc *d_runs = reinterpret_cast<const RunDesc *>(d + L.runs);
-  const uint64_t *d_pos = reinterpret_cast<const uint64_t *>(d + L.pos);
-  const uint32_t *d_idx = reinterpret_cast<const uint32_t *>(d + L.idx);
-  const uint32_t *d_slot = reinterpret_cast<const uint32_t *>(d + L.slot);
   unsigned *d_counter = reinterpret_cast<unsigned *>(d + L.counter);
   hipStream_t st = s.st;
-  // the upload is a kernel on the slot's stream (reading the pinned buffer),
-  // not a copy-engine transfer: the kernels after it then start without
-  // waiting for a hand-off between engines; it stamps the iteration's start
+  // the upload is done by a kernel on the slot's stream (reading the pinned
+  // buffer), not a copy-engine transfer, so that the generation kernel does
+  // not wait for a hand-off between engines; it stamps the iteration's start
   s.seq++;
   __atomic_store_n(s.h_sig + 2, 0, __ATOMIC_RELAXED);
   __atomic_store_n(s.h_sig + 3, 0, __ATOMIC_RELAXED);
   s.signals = false;
-  hipError_t e = launch_upload(d, s.h_pack_dev, L.total, st, s.d_sig + 1);
-  if (e != hipSuccess) return hip_fail(e);
-  uint32_t off = 0;
+  // the request states are computed in the same launch as the upload (the
+  // server has one variant: at most one run), reading positions, origins
+  // and slots from the pinned buffer
+  const uint8_t *hd = s.h_pack_dev;
+  ReqArgs ra;
+  ra.seeds = nullptr;
+  ra.origin_state = streams_state_ptr(sv->streams);
+  ra.origin_stride = sv->o.n_streams;
+  ra.origin_idx = reinterpret_cast<const uint32_t *>(hd + L.idx);
+  ra.polys = nullptr;
+  ra.pos = reinterpret_cast<const uint64_t *>(hd + L.pos);
+  ra.slot = reinterpret_cast<const uint32_t *>(hd + L.slot);
+  ra.req_state = s.d_req_state;
+  ra.m = 0;
   for (auto &run : P.rs.runs) {
-    ReqArgs ra;
-    ra.seeds = nullptr;
-    ra.origin_state = streams_state_ptr(sv->streams);
-    ra.origin_stride = sv->o.n_streams;
-    ra.origin_idx = d_idx + off;
-    ra.polys = nullptr;
-    ra.pos = d_pos + (size_t)off * 2;
-    ra.slot = d_slot + off;
-    ra.req_state = s.d_req_state;
-    ra.m = run.second;
-    e = launch_req_state_digits(run.first, ra, sv->digits.dev, sv->digits.bits, sv->digits.levels, st);
-    if (e != hipSuccess) return hip_fail(e);
-    off += run.second;
+    if (run.first != sv->o.variant) return SLRNG_EINVAL;  // not reached: requests carry the server's variant
+    ra.m += run.second;
   }
+  hipError_t e = launch_prologue(sv->o.variant, ra, sv->digits.dev, sv->digits.bits, sv->digits.levels, d,
+                                 hd, L.total, s.d_sig + 1, st);
+  if (e != hipSuccess) return hip_fail(e);
   if (!P.tiles.empty()) {
     BatchArgs a{};
     a.tiles = d_tiles;
@@ -616,7 +616,10 @@ extern "C" int slrng_server_create(const slrng_server_opts *opts, slrng_server *
       int khz = 0;
       e = hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, sv->device);
       Slot &s = sv->slots[0];
-      if (e == hipSuccess) e = launch_upload(nullptr, nullptr, 0, s.st, s.d_sig + 1);
+      if (e == hipSuccess) {
+        ReqArgs none{};
+        e = launch_prologue(o.variant, none, nullptr, 0, 0, nullptr, nullptr, 0, s.d_sig + 1, s.st);
+      }
       if (e == hipSuccess) e = hipStreamSynchronize(s.st);
       if (e == hipSuccess && khz <= 0) e = hipErrorInvalidValue;
       if (e != hipSuccess) rc = hip_fail(e);
