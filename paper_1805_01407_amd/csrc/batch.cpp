@@ -352,7 +352,11 @@ int build_plan(const PlanReq *reqs, size_t n_reqs, const slrng_batch_opts &o, in
       ut.push_back({(uint64_t)td.max_len * output_cost(td.variant), td});
     }
   }
-  // units in order; tiles heaviest first within a unit
+  // units in order; tiles heaviest first within a unit (room for all tiles
+  // at once: the plain form has one unit per request)
+  size_t ntiles_all = 0;
+  for (auto &kv : unit_tiles) ntiles_all += kv.second.size();
+  P.tiles.reserve(ntiles_all);
   for (auto &kv : unit_tiles) {
     auto &tiles = kv.second;
     const auto heavier = [](const std::pair<uint64_t, TileDesc> &x, const std::pair<uint64_t, TileDesc> &y) {
@@ -365,7 +369,6 @@ int build_plan(const PlanReq *reqs, size_t n_reqs, const slrng_batch_opts &o, in
       std::stable_sort(tiles.begin(), tiles.end(), heavier);
     PlanUnit u;
     u.tile0 = (uint32_t)P.tiles.size();
-    P.tiles.reserve(P.tiles.size() + tiles.size());
     for (auto &t : tiles) P.tiles.push_back(t.second);
     u.ntiles = (uint32_t)tiles.size();
     if (plain) {
