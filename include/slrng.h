@@ -462,7 +462,7 @@ int slrng_batch_run_static(const slrng_request *reqs, size_t n_reqs, const slrng
  * slrng_server_drain: waits until every submitted request has completed.
  * slrng_server_get_stats / _reset_stats: counters; latency percentiles of the
  *   completed requests; busy_s is the union of the iterations' device time
- *   (from the start of the upload kernel to the end of the generation
+ *   (from the start of the iteration's first kernel to the end of the generation
  *   kernel), kernel_s that of the generation kernels alone (the intervals
  *   above); both from the device clock stamps.
  * slrng_server_replay: submits count requests at the given arrival times
