@@ -151,6 +151,21 @@ def test_invalid_arguments_return_einval(P):
     assert L.slrng_calib_write(None, 16, None) == -1
 
 
+def test_jump_poly_device_argument_errors_before_any_device_call(P):
+    """slrng_jump_poly_device rejects a bad variant, null or unaligned
+    pointers and m > 2^32 before touching the device; m = 0 does nothing."""
+    L = P.lib()
+    fake = 1 << 20  # aligned, never dereferenced: the checks come first
+    assert L.slrng_jump_poly_device(99, fake, 1, fake, None) == -1
+    assert L.slrng_jump_poly_device(-1, fake, 1, fake, None) == -1
+    assert L.slrng_jump_poly_device(3, None, 1, fake, None) == -1
+    assert L.slrng_jump_poly_device(3, fake, 1, None, None) == -1
+    assert L.slrng_jump_poly_device(3, fake + 4, 1, fake, None) == -1
+    assert L.slrng_jump_poly_device(3, fake, 1, fake + 4, None) == -1
+    assert L.slrng_jump_poly_device(3, fake, (1 << 32) + 1, fake, None) == -2
+    assert L.slrng_jump_poly_device(3, None, 0, None, None) == 0
+
+
 def test_batch_argument_errors_before_any_device_call(P):
     bad_variant = P.make_requests(14, 0, 1, 0, 10, 4096)
     misaligned = P.make_requests(0, 0, 1, 0, 10, 4100)
