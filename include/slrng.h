@@ -291,7 +291,9 @@ int slrng_output_free(void *dev_ptr);
  *                8 x tile x skew outputs;
  *  min_chunk     no chunk shorter than this many outputs;
  *  store         0: plain (write-back) output stores; 1: nontemporal ones
- *                (on the 16-byte aligned path).  Which is faster depends on
+ *                (on the 16-byte aligned path; for the 64-bit generators
+ *                only when n >= 2048, shorter rows measuring faster with
+ *                plain stores).  Which is faster depends on
  *                the physical placement of the output (compact memory:
  *                plain; slrng_output_alloc memory: nontemporal, as measured
  *                on MI355X).

@@ -578,6 +578,8 @@ extern "C" int slrng_gf2_rank(const uint64_t *dev_rows, uint32_t nrows, uint32_t
   });
 }
 
+constexpr uint64_t kNtMinRow = 2048;
+
 extern "C" int slrng_generate(slrng_streams *h, int kind, uint64_t n, void *dev_out, uint64_t ld,
                               hipStream_t stream) {
   return guarded([&]() -> int {
@@ -612,7 +614,11 @@ extern "C" int slrng_generate(slrng_streams *h, int kind, uint64_t n, void *dev_
     a.out = dev_out;
     a.ld = ld;
     a.slot_polys = sp;
-    GenConfig cfg{t.tile, t.store == 1};
+    // nontemporal stores only for rows of at least kNtMinRow outputs: with
+    // rows of 1,024 outputs, plain stores measured 2-10% faster for nine of
+    // ten (64-bit generator, kind) pairs on MI355X (8 GiB launches)
+    const bool nt = t.store == 1 && (is_variant32(h->variant) || n >= kNtMinRow);
+    GenConfig cfg{t.tile, nt};
     hipError_t e = is_variant32(h->variant)
                        ? launch_generate32(h->variant, kind_index(kind), a, cfg.nt, stream)
                        : launch_generate(h->variant, kind, a, cfg, stream);
