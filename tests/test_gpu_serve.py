@@ -104,6 +104,38 @@ def test_served_requests_match_oracle_and_alone(P):
         assert np.array_equal(alone, out)
 
 
+@pytest.mark.parametrize("store,inflight", [(1, 8), (2, 1), (0, 8)])
+def test_served_store_policies_and_slots(P, store, inflight):
+    """Every store policy of the served kernel (the completion signal then
+    follows a write-back fence or a counter wait) and one to eight slots:
+    bursts of requests of many sizes, compared in full with the oracle."""
+    S = 16
+    chain = O.stream_chain(O.GEN64[NAME], 9, S)
+    # room for every request of the burst at once: they are released only
+    # after all are submitted
+    opts = P.slrng_server_default_opts(n_streams=S, budget_bytes=2 << 30, seed=9, variant=NAME,
+                                       inflight=inflight, store=store)
+    sv = P.slrng_server_create(opts)
+    rng = np.random.default_rng(store * 10 + inflight)
+    sizes = [int(x) for x in rng.choice([1, 3, 64, 500, 8192, 8193, 100000, 1 << 20], 120)]
+    announce("store/slots", store, inflight, len(sizes))
+    try:
+        tickets = [(P.slrng_server_submit(sv, k % S, n, k % 2), k % S, n, k % 2) for k, n in enumerate(sizes)]
+        got = []
+        for t, stream, n, kind in tickets:
+            ptr, pos = P.slrng_server_wait(sv, t)
+            got.append((stream, pos, n, kind, d2h(ptr, n)))
+            P.slrng_server_release(sv, t)
+        st = P.slrng_server_get_stats(sv)
+    finally:
+        P.slrng_server_destroy(sv)
+    for stream, pos, n, kind, out in got:
+        assert np.array_equal(out, expected(chain, stream, pos, n, kind)), (store, inflight, stream, pos, n)
+    assert st["completed"] == len(sizes) and st["failed"] == 0
+    # each iteration's busy interval contains its kernel interval
+    assert 0 < st["kernel_s"] <= st["busy_s"]
+
+
 def test_budget_admission_and_overlap(P):
     import time
     S = 16
