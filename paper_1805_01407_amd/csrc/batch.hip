@@ -154,38 +154,55 @@ __device__ __forceinline__ void batch_tile(const BatchArgs &a, const TileDesc &t
   }
 }
 
-// Claims the wave's next tile into t; false when none is left.  Every wave
-// gets false exactly once (the claim counter only grows during the launch),
-// and the last wave to get it knows that no wave will claim again: it returns
-// both counters to zero for the next launch, so no reset kernel is needed
-// between launches.  With a completion signal (a.sig), each wave makes its
-// output stores visible device-wide before it counts itself finished, and
-// the last wave then signals the host (see BatchArgs).  WT: the kernel's
-// output stores are written through the L2 (sc1), so a wave's stores are
-// visible device-wide once they have completed, and waiting for the wave's
-// vector-memory counter is enough (s_waitcnt vmcnt(0), the other counters
-// left at their maximum); other stores also need the L2 written back (an
-// agent-scope release fence, which costs every wave a write-back).
+// Tile claims.  Wave w of the grid's W waves takes tile w first, with no
+// atomic (tiles are ordered heaviest first, so the W heaviest go one to a
+// wave); further tiles come from the claim counter, as W plus its old value,
+// and only when there are more tiles than waves.  A device-wide atomic on
+// one address from every wave of a full grid measurably delays the start of
+// every wave (on MI355X a one-tile-per-wave launch over all 256 CUs took
+// twice as long as over 64).  When a block's waves are done, one atomic per
+// block counts it finished; the last block returns both counters to zero for
+// the next launch, so no reset kernel is needed between launches.  With a
+// completion signal (a.sig), every wave makes its output stores visible
+// device-wide before the block counts itself finished, and the last block
+// then signals the host (see BatchArgs).  WT: the kernel's output stores are
+// written through the L2 (sc1), so a wave's stores are visible device-wide
+// once they have completed, and waiting for the wave's vector-memory counter
+// is enough (s_waitcnt vmcnt(0), the other counters left at their maximum);
+// other stores also need the L2 written back (an agent-scope release fence).
 __device__ __forceinline__ void sig_store(uint64_t *p, uint64_t v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
-template <bool WT>
-__device__ __forceinline__ bool next_tile(const BatchArgs &a, int lane, unsigned &t) {
-  unsigned v = 0;
-  if (lane == 0) v = atomicAdd(a.counter, 1u);
-  t = (unsigned)__builtin_amdgcn_readfirstlane((int)v);
-  if (t < a.ntiles) {
+// The wave's next tile into t (uniform); false when none is left.  `first`
+// starts true for each wave.
+__device__ __forceinline__ bool next_tile(const BatchArgs &a, int lane, unsigned &t, bool &first) {
+  const unsigned W = gridDim.x * (kBlock / kWave);
+  if (first) {
+    first = false;
+    t = blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave;
+    if (t >= a.ntiles) return false;
     if (t == 0 && a.sig && lane == 0) sig_store(a.sig + 2, (uint64_t)wall_clock64());
     return true;
   }
+  if (a.ntiles <= W) return false;
+  unsigned v = 0;
+  if (lane == 0) v = atomicAdd(a.counter, 1u);
+  t = W + (unsigned)__builtin_amdgcn_readfirstlane((int)v);
+  return t < a.ntiles;
+}
+
+// After the block's waves have claimed their last tile (every wave of the
+// block calls it).
+template <bool WT>
+__device__ __forceinline__ void finish_block(const BatchArgs &a) {
   if (a.sig) {  // uniform
     if constexpr (WT) __builtin_amdgcn_s_waitcnt(0x0F70);
     else __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
   }
-  if (lane == 0) {
-    const unsigned waves = gridDim.x * (kBlock / kWave);
-    if (atomicAdd(a.counter + 1, 1u) == waves - 1) {
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    if (atomicAdd(a.counter + 1, 1u) == gridDim.x - 1) {
       atomicExch(a.counter, 0u);
       atomicExch(a.counter + 1, 0u);
       if (a.sig) {
@@ -195,7 +212,6 @@ __device__ __forceinline__ bool next_tile(const BatchArgs &a, int lane, unsigned
       }
     }
   }
-  return false;
 }
 
 // Every variant and kind: the switch on the tile's (variant, kind) is uniform
@@ -210,7 +226,8 @@ __global__ __launch_bounds__(kBlock) void k_batch(BatchArgs a) {
   u64 *rowptr = rowptr_all + wave * kWave;
   unsigned *rowlen = rowlen_all + wave * kWave;
   unsigned t = 0;
-  while (next_tile<true>(a, lane, t)) {
+  bool first = true;
+  while (next_tile(a, lane, t, first)) {
     const TileDesc td = a.tiles[t];
     switch (td.variant * 2 + td.kind) {
 #define SL_CASE(V)                                                  \
@@ -223,6 +240,7 @@ __global__ __launch_bounds__(kBlock) void k_batch(BatchArgs a) {
     }
     wave_sync();
   }
+  finish_block<true>(a);
 }
 
 // The same loop for tiles of one variant (the server's): the registers of
@@ -237,12 +255,14 @@ __global__ __launch_bounds__(kBlock) void k_batch1(BatchArgs a) {
   u64 *rowptr = rowptr_all + wave * kWave;
   unsigned *rowlen = rowlen_all + wave * kWave;
   unsigned t = 0;
-  while (next_tile<ST == 0>(a, lane, t)) {
+  bool first = true;
+  while (next_tile(a, lane, t, first)) {
     const TileDesc td = a.tiles[t];
     if (td.kind) batch_tile<V, 1, T, ST>(a, td, lds, rowptr, rowlen, lane);
     else batch_tile<V, 0, T, ST>(a, td, lds, rowptr, rowlen, lane);
     wave_sync();
   }
+  finish_block<ST == 0>(a);
 }
 
 template <int V>

@@ -9,9 +9,9 @@
 // a request form a run tile, described by one RunDesc (each lane derives its
 // chunk); the remaining chunks of all requests are grouped by variant and
 // kind, sorted by length and packed 64 to a list tile of LaneDescs.  One wave
-// processes a tile.  A persistent kernel claims tiles through an atomic
-// counter, heaviest tiles first, and switches on the (wave-uniform) variant
-// and kind.
+// processes a tile.  A persistent kernel hands the first tiles out one to a
+// wave and the rest through an atomic counter, heaviest tiles first, and
+// switches on the (wave-uniform) variant and kind.
 #pragma once
 #include <hip/hip_runtime_api.h>
 #include <stdint.h>
@@ -64,10 +64,11 @@ struct BatchArgs {
   const uint64_t *req_state;          // [r][16] start states of requests with start > 0
   const uint64_t *tab[kNumVariants];  // chunk tables, word-major: word w of entry j at [w*tab_n + j]
   uint32_t tab_n[kNumVariants];
-  unsigned *counter;                  // [0] tiles claimed, [1] waves finished: both zero
-                                      // at launch; the last wave to finish zeroes them
-  // Completion signal in host-mapped memory, or null: the wave that claims
-  // tile 0 writes the device clock to sig[2]; the last wave to finish, once
+  unsigned *counter;                  // [0] tiles claimed beyond the first one per wave,
+                                      // [1] blocks finished: both zero at launch; the
+                                      // last block to finish zeroes them
+  // Completion signal in host-mapped memory, or null: the wave that takes
+  // tile 0 writes the device clock to sig[2]; the last block to finish, once
   // the output stores of every wave are visible device-wide, writes the clock
   // to sig[3] and then seq to sig[0].
   uint64_t *sig = nullptr;
