@@ -120,7 +120,8 @@ def profiled_traffic() -> int | None:
 
 
 # Worker threads for the CPU oracle: the host threads this process may use,
-# at most 16 (a one-GPU machine's share of the host CPU, whatever nproc shows).
+# at most 16 (the host share that goes with one GPU on a shared multi-GPU
+# host, whatever nproc shows).
 CPU_THREAD_CAP = 16
 
 

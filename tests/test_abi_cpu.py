@@ -106,7 +106,7 @@ def test_jump_poly_matches_oracle(P, name):
 
 
 def test_jump_poly_homomorphism_in_the_library(P):
-    # r_a * r_b = r_{a+b} mod p, with the oracle's multiplier as the judge
+    # r_a * r_b = r_{a+b} mod p, the products taken with the oracle's multiplier
     name = "xoshiro256**"
     p = O.charpoly(O.GEN64[name])
     a, b = 1 << 128, 1 << 192
